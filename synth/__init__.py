@@ -1,0 +1,348 @@
+"""Seeded synthetic inputs for the MRT finite-difference lattice Boltzmann step.
+
+This package only describes problems: grid, spacings, time step, relaxation
+rates, boundary rules and the macroscopic initial fields (rho, u1, u2, T),
+plus seeded raw population fields.  It holds none of the method's arithmetic
+(no moments, no equilibria, no collision, no stencil), imports neither the
+GPU library nor the oracle, and serves both.
+
+Gas-dynamics relations used to build initial states (the Rankine-Hugoniot
+jump of a normal shock) are those of the model's gas: p = rho T with
+e = rho (T + |u|^2/2), i.e. gamma = 2.
+
+Workloads mirror the paper's experiments (Sect. V) at the sizes the
+benchmark configurations name:
+
+* ``sod``            -- Sod tube, 400x4, dt = 2e-5 (Sect. V.A(a) states)
+* ``lax``            -- Lax tube (Sect. V.A(b) states and rates)
+* ``mach_reflection``-- Mach-3 shock on a 30 degree wedge, the Sect. V.B(b)
+                        geometry (2048x512, or a crop at the same spacing)
+* ``shock_bubble``   -- Mach-1.22 shock on a light bubble, Sect. V.C
+                        (4096x1024, or a scaled run at the same spacing)
+* ``couette``        -- Couette flow with a resting and a moving wall,
+                        Sect. V.D (8192x2048, or a strip)
+* ``shear_wave``     -- periodic decaying shear wave (transport check)
+* ``tube_batch``     -- many independent seeded Riemann problems
+"""
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GAMMA = 2.0  # the model's gas: two translational degrees of freedom
+SIDES = ("west", "east", "south", "north")
+
+
+@dataclass
+class Problem:
+    name: str
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    dt: float
+    s: list
+    sides: dict
+    ic: dict
+    nsteps: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def t_end(self):
+        return self.nsteps * self.dt
+
+    def x_centres(self):
+        return (np.arange(self.nx) + 0.5) * self.dx
+
+    def y_centres(self):
+        return (np.arange(self.ny) + 0.5) * self.dy
+
+
+# ---------------------------------------------------------------- helpers
+
+def side(kind, state=(1.0, 0.0, 0.0, 1.0)):
+    """One rule along the whole side."""
+    st = tuple(float(v) for v in state)
+    return dict(kind_lo=kind, kind_hi=kind, state_lo=st, state_hi=st,
+                split0=math.inf, split_rate=0.0)
+
+
+def split_side(kind_lo, state_lo, kind_hi, state_hi, split0, split_rate=0.0):
+    """kind_lo where the along-side coordinate is <= split0 + split_rate t,
+    kind_hi beyond."""
+    return dict(kind_lo=kind_lo, kind_hi=kind_hi,
+                state_lo=tuple(float(v) for v in state_lo),
+                state_hi=tuple(float(v) for v in state_hi),
+                split0=float(split0), split_rate=float(split_rate))
+
+
+def rates(dt=None, default=1e5, **over):
+    """s_1..s_16 as a list.  s_1..s_4 act on conserved moments and are
+    irrelevant (stored as 0).  Keys s5..s16 override the default.  With dt
+    given, every rate is capped at 1/dt, the largest value the paper's runs
+    use (dt s <= 1)."""
+    s = [0.0] * 4 + [float(default)] * 12
+    for k, v in over.items():
+        idx = int(k[1:]) - 1
+        assert 4 <= idx < 16, k
+        s[idx] = float(v)
+    if dt is not None:
+        cap = 1.0 / dt
+        s = [min(v, cap) for v in s]
+    return s
+
+
+def uniform_ic(nx, ny, rho, ux, uy, T):
+    return {k: np.full((ny, nx), float(v)) for k, v in
+            (("rho", rho), ("ux", ux), ("uy", uy), ("T", T))}
+
+
+def normal_shock(rho1, p1, mach, gamma=GAMMA):
+    """Post-shock (rho2, |u2|, p2) behind a normal shock of Mach number mach
+    running into gas at rest (rho1, p1), and the shock speed W; u2 points
+    along the shock's motion.  Rankine-Hugoniot relations."""
+    a1 = math.sqrt(gamma * p1 / rho1)
+    m2 = mach * mach
+    rho2 = rho1 * (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p2 = p1 * (2.0 * gamma * m2 - (gamma - 1.0)) / (gamma + 1.0)
+    W = mach * a1
+    u2 = W * (1.0 - rho1 / rho2)
+    return rho2, u2, p2, W
+
+
+# -------------------------------------------------------------- workloads
+
+def sod(nx=400, ny=4, dt=2e-5, nsteps=10000):
+    """Sod tube on [0,1], interface at 0.5, periodic in y, f = f^eq of the
+    initial states on the x ends.  States (rho,u1,u2,T) of Sect. V.A(a):
+    (1,0,0,1) | (0.125,0,0,0.8), i.e. p = 1 | 0.1.  Rates s5 = s6 = 500,
+    s7 = s8 = 1000, s11 = 2500, others 1e5 capped at 1/dt."""
+    dx = 1.0 / nx
+    left, right = (1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.8)
+    x = (np.arange(nx) + 0.5) * dx
+    ic = {k: np.empty((ny, nx)) for k in ("rho", "ux", "uy", "T")}
+    for q, key in enumerate(("rho", "ux", "uy", "T")):
+        ic[key][:] = np.where(x < 0.5, left[q], right[q])[None, :]
+    s = rates(dt, s5=500, s6=500, s7=1000, s8=1000, s11=2500)
+    sides = {"west": side("dirichlet", left), "east": side("dirichlet", right),
+             "south": side("periodic"), "north": side("periodic")}
+    return Problem("sod", nx, ny, dx, dx, dt, s, sides, ic, nsteps,
+                   meta=dict(x0=0.5, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1)))
+
+
+def lax(nx=400, ny=4, length=1.6, dt=2e-5, t_end=0.2):
+    """Lax tube, states of Sect. V.A(b): (0.445,0.698,0,7.928) |
+    (0.5,0,0,1.142); rates s7 = s8 = 3e3, s13 = 100, others 1e5 capped at
+    1/dt.  Domain [0,length], interface in the middle."""
+    dx = length / nx
+    left, right = (0.445, 0.698, 0.0, 7.928), (0.5, 0.0, 0.0, 1.142)
+    x = (np.arange(nx) + 0.5) * dx
+    x0 = 0.5 * length
+    ic = {k: np.empty((ny, nx)) for k in ("rho", "ux", "uy", "T")}
+    for q, key in enumerate(("rho", "ux", "uy", "T")):
+        ic[key][:] = np.where(x < x0, left[q], right[q])[None, :]
+    s = rates(dt, s7=3e3, s8=3e3, s13=1e2)
+    sides = {"west": side("dirichlet", left), "east": side("dirichlet", right),
+             "south": side("periodic"), "north": side("periodic")}
+    nsteps = int(round(t_end / dt))
+    return Problem("lax", nx, ny, dx, dx, dt, s, sides, ic, nsteps,
+                   meta=dict(x0=x0, left=(0.445, 0.698, 0.445 * 7.928),
+                             right=(0.5, 0.0, 0.5 * 1.142)))
+
+
+def mach_reflection(nx=2048, ny=512, dx=0.003, dt=1e-5, mach=3.0, nsteps=20000, x0_cells=None):
+    """Planar shock of Mach number `mach` into gas at rest (rho, p) = (1, 1)
+    meeting a wedge at 30 degrees: the Sect. V.B(b) geometry.  The shock line
+    is y = tan60 (x - x0) - W t / sin30; post-shock gas lies above it and
+    moves at |u2| along (cos30, -sin30).  Boundaries: post-shock on the left
+    and on the bottom for x <= x0, reflecting bottom beyond x0,
+    extrapolation on the right, and on the top post-shock for x <= g(t) =
+    x0 + tan30 (H + W t / sin30), extrapolation beyond.  Rates of Sect.
+    V.B(a): s5 = 1e4, s6 = 2e3, s7 = s8 = 1e4, others 1e5."""
+    if x0_cells is None:
+        x0_cells = nx // 4
+    rho2, u2, p2, W = normal_shock(1.0, 1.0, mach)
+    c30, s30, t30, t60 = math.cos(math.pi / 6), 0.5, math.tan(math.pi / 6), math.tan(math.pi / 3)
+    post = (rho2, u2 * c30, -u2 * s30, p2 / rho2)
+    pre = (1.0, 0.0, 0.0, 1.0)
+    x0 = x0_cells * dx
+    H = ny * dx
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dx
+    X, Y = np.meshgrid(x, y)
+    behind = Y >= t60 * (X - x0)
+    ic = {}
+    for q, key in enumerate(("rho", "ux", "uy", "T")):
+        ic[key] = np.where(behind, post[q], pre[q]).astype(np.float64)
+    s = rates(dt, s5=1e4, s6=2e3, s7=1e4, s8=1e4)
+    sides = {
+        "west": side("dirichlet", post),
+        "east": side("extrapolate"),
+        "south": split_side("dirichlet", post, "reflect", pre, x0),
+        "north": split_side("dirichlet", post, "extrapolate", pre,
+                            x0 + t30 * H, t30 * W / s30),
+    }
+    return Problem("mach_reflection", nx, ny, dx, dx, dt, s, sides, ic, nsteps,
+                   meta=dict(mach=mach, post=post, pre=pre, W=W, x0=x0))
+
+
+def shock_bubble(nx=4096, ny=1024, dx=0.003, dt=1e-5, nsteps=10000, seed=2024,
+                 bubble_density=0.138, mach=1.22, noise=0.01):
+    """Mach-1.22 planar shock moving in -x onto a light circular bubble of
+    radius 0.1*ny cells in ambient gas (rho, p) = (1, 1), pressure-matched
+    (Sect. V.C, first case).  The centre is jittered by up to 0.05*ny cells
+    and the density carries 1 % clipped Gaussian noise at fixed pressure,
+    both from the seed.  Boundaries: post-shock inflow on the right,
+    extrapolation on the left, reflecting top and bottom.  Rates s5..s8 =
+    1e4, others 1e5."""
+    rng = np.random.default_rng(seed)
+    R = 0.1 * ny
+    cx = nx / 2 + rng.uniform(-0.05 * ny, 0.05 * ny)
+    cy = ny / 2 + rng.uniform(-0.05 * ny, 0.05 * ny)
+    xs = cx + R + 16.0
+    rho2, u2, p2, W = normal_shock(1.0, 1.0, mach)
+    post = (rho2, -u2, 0.0, p2 / rho2)
+    ii = np.arange(nx) + 0.5
+    jj = np.arange(ny) + 0.5
+    I, J = np.meshgrid(ii, jj)
+    rho = np.ones((ny, nx))
+    p = np.ones((ny, nx))
+    ux = np.zeros((ny, nx))
+    inside = (I - cx) ** 2 + (J - cy) ** 2 <= R * R
+    rho[inside] = bubble_density
+    shocked = I > xs
+    rho[shocked] = rho2
+    p[shocked] = p2
+    ux[shocked] = -u2
+    xi = np.clip(rng.standard_normal((ny, nx)), -3.0, 3.0)
+    rho = rho * (1.0 + noise * xi)
+    ic = {"rho": rho, "ux": ux, "uy": np.zeros((ny, nx)), "T": p / rho}
+    s = rates(dt, s5=1e4, s6=1e4, s7=1e4, s8=1e4)
+    sides = {"west": side("extrapolate"), "east": side("dirichlet", post),
+             "south": side("reflect"), "north": side("reflect")}
+    return Problem("shock_bubble", nx, ny, dx, dx, dt, s, sides, ic, nsteps,
+                   meta=dict(centre=(cx, cy), radius=R, shock_x=xs, post=post))
+
+
+def couette(nx=8192, ny=2048, dt=1e-5, U=0.1, nsteps=50000, seed=7, noise=1e-3,
+            s_shear=500.0, x_window=None):
+    """Couette flow (Sect. V.D) with the bottom wall at rest and the top wall
+    moving at U, both at T = 1; periodic in x; gas initially at rest with
+    rho = 1, T = 1 plus seeded 1e-3 Gaussian velocity noise.  dx = dy = 1/ny.
+    Rates s5 = s6 = s_shear, others 1e5.  The noise field is drawn for the
+    full nx*ny grid, so a window of columns (x_window = (i0, i1)) carries the
+    same per-cell values as the full run."""
+    dx = 1.0 / ny
+    rng = np.random.default_rng(seed)
+    nux = rng.standard_normal((ny, nx))
+    nuy = rng.standard_normal((ny, nx))
+    if x_window is not None:
+        i0, i1 = x_window
+        nux, nuy = nux[:, i0:i1], nuy[:, i0:i1]
+        nx = i1 - i0
+    ic = {"rho": np.ones((ny, nx)), "ux": noise * nux, "uy": noise * nuy,
+          "T": np.ones((ny, nx))}
+    s = rates(dt, s5=s_shear, s6=s_shear)
+    sides = {"west": side("periodic"), "east": side("periodic"),
+             "south": side("wall", (1.0, 0.0, 0.0, 1.0)),
+             "north": side("wall", (1.0, U, 0.0, 1.0))}
+    return Problem("couette", nx, ny, dx, dx, dt, s, sides, ic, nsteps,
+                   meta=dict(U=U, D=(ny + 1) * dx))
+
+
+def shear_wave(nx=4, ny=64, dx=1.0 / 64, dt=1e-5, amp=1e-3, s_shear=2000.0, nsteps=2000):
+    """u1 = amp sin(2 pi y / L) on a doubly periodic grid at rho = T = 1."""
+    L = ny * dx
+    y = (np.arange(ny) + 0.5) * dx
+    ic = uniform_ic(nx, ny, 1.0, 0.0, 0.0, 1.0)
+    ic["ux"] = np.tile((amp * np.sin(2 * math.pi * y / L))[:, None], (1, nx))
+    s = rates(dt, s5=s_shear, s6=s_shear)
+    sides = {k: side("periodic") for k in SIDES}
+    return Problem("shear_wave", nx, ny, dx, dx, dt, s, sides, ic, nsteps,
+                   meta=dict(L=L, amp=amp))
+
+
+def random_populations(nx, ny, seed, base=None, spread=0.5):
+    """Seeded positive raw populations [16][ny][nx]: base_i (1 + spread U),
+    U uniform in [-1, 1).  Any positive f has rho > 0 and non-negative
+    pressure, so it is a valid state for the update."""
+    rng = np.random.default_rng(seed)
+    if base is None:
+        base = np.array([0.2] * 4 + [0.002] * 4 + [0.05] * 4 + [0.02] * 4)
+    u = rng.uniform(-1.0, 1.0, size=(16, ny, nx))
+    return np.asarray(base)[:, None, None] * (1.0 + spread * u)
+
+
+def smooth_macro(nx, ny, seed, rho0=1.0, T0=1.0, du=0.2, dr=0.1, modes=3):
+    """Seeded smooth periodic macroscopic fields (sums of low Fourier modes)."""
+    rng = np.random.default_rng(seed)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+
+    def field_(amp):
+        out = np.zeros((ny, nx))
+        for _ in range(modes):
+            kx, ky = rng.integers(0, 3, size=2)
+            ph = rng.uniform(0, 2 * math.pi)
+            out += amp / modes * np.sin(2 * math.pi * (kx * X + ky * Y) + ph)
+        return out
+
+    return {"rho": rho0 * (1.0 + field_(dr)), "ux": field_(du), "uy": field_(du),
+            "T": T0 * (1.0 + field_(dr))}
+
+
+def generic(nx, ny, dx, dt, s, sides, ic, nsteps=0, name="generic"):
+    return Problem(name, nx, ny, dx, dx, dt, list(s), sides, ic, nsteps)
+
+
+def tube_batch(ntubes=512, nmin=200, nmax=8000, seed=12345, dx=0.002, dt=1e-5,
+               cfl_fraction=0.8, star_fn=None, min_star_density=0.05):
+    """Independent 1D Riemann problems, each n_k x 4 cells, periodic in y and
+    f = f^eq of its initial states at both ends, interface at the middle.
+    n_k ~ U{nmin..nmax}; per side rho ~ U[0.1,5], u ~ U[-2,2], p ~ U[0.1,100],
+    v = 0.  Rates s5 = s6 = 5e3, s7 = s8 = 3e4, others 1e5 (Sect. V.A(d)).
+
+    Each tube runs to t_end = cfl_fraction * (n_k/2) dx / S_max, where S_max
+    is its fastest wave speed.  star_fn(left, right) -> (S_max, min star
+    density) is supplied by the caller (an exact Riemann solver); draws with
+    vacuum (star_fn raising ValueError) or a star density below
+    min_star_density are redrawn."""
+    rng = np.random.default_rng(seed)
+    tubes = []
+    while len(tubes) < ntubes:
+        n = int(rng.integers(nmin, nmax + 1))
+        L = (rng.uniform(0.1, 5.0), rng.uniform(-2.0, 2.0), rng.uniform(0.1, 100.0))
+        R = (rng.uniform(0.1, 5.0), rng.uniform(-2.0, 2.0), rng.uniform(0.1, 100.0))
+        smax = None
+        if star_fn is not None:
+            try:
+                smax, rmin = star_fn(L, R)
+            except ValueError:
+                continue
+            if rmin < min_star_density:
+                continue
+        steps = None
+        if smax is not None:
+            t_end = cfl_fraction * 0.5 * n * dx / smax
+            steps = int(math.floor(t_end / dt))
+        tubes.append(dict(n=n, left=L, right=R, steps=steps))
+    s = rates(dt, s5=5e3, s6=5e3, s7=3e4, s8=3e4)
+    return dict(tubes=tubes, dx=dx, dt=dt, s=s, width=4)
+
+
+def tube_problem(batch, k):
+    """Tube k of a batch as a stand-alone 2D problem."""
+    t = batch["tubes"][k]
+    n, w, dx = t["n"], batch["width"], batch["dx"]
+    (rl, ul, pl), (rr, ur, pr) = t["left"], t["right"]
+    left, right = (rl, ul, 0.0, pl / rl), (rr, ur, 0.0, pr / rr)
+    half = n // 2
+    ic = {}
+    for q, key in enumerate(("rho", "ux", "uy", "T")):
+        row = np.where(np.arange(n) < half, left[q], right[q])
+        ic[key] = np.tile(row[None, :].astype(np.float64), (w, 1))
+    sides = {"west": side("dirichlet", left), "east": side("dirichlet", right),
+             "south": side("periodic"), "north": side("periodic")}
+    return Problem(f"tube{k}", n, w, dx, dx, batch["dt"], batch["s"], sides, ic,
+                   t["steps"] or 0, meta=dict(x0=half * dx, left=t["left"], right=t["right"]))
