@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Throughput of the MRT finite-difference lattice Boltzmann step on one MI355X.
+
+Default workload: the Mach-3 planar shock on a 30 degree wedge (the
+Mach-reflection set-up of the paper's Sect. V.B(b)), 2048x512 nodes, FP32,
+20000 steps.  A "step" is one pass of the whole hot path: boundary nodes,
+then the fused collision + Lax-Wendroff + Euler update of every node.
+
+Printed: one JSON line with MLUPS (node updates per second / 1e6), the
+roofline of the step kernel (algorithmic 128 B per node update -- 16 FP32
+populations read and written once -- over the kernel's own average launch
+duration, against 8 TB/s HBM), the FP64 CPU oracle timed on a bounded crop of
+the same workload, and the GPU crop run's error against that oracle.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % of HBM roofline (FP32 vs mixed vs batched) at stated L1 error"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 128  # 16 FP32 populations read + 16 written
+KERNEL_SRC = os.path.join(ROOT, "paper_0908_3749_amd", "csrc", "mrtfd_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def workloads():
+    import synth
+
+    return {
+        "mach3": dict(name="mach3_reflection_2048x512", make=lambda: synth.mach_reflection(),
+                      crop=lambda: synth.mach_reflection(nx=256, ny=64, x0_cells=64), steps=20000),
+        "bubble": dict(name="shock_bubble_4096x1024", make=lambda: synth.shock_bubble(),
+                       crop=lambda: synth.shock_bubble(nx=512, ny=128), steps=10000),
+        "couette": dict(name="couette_8192x2048", make=lambda: synth.couette(),
+                        crop=lambda: synth.couette(x_window=(0, 16)), steps=50000),
+        "sod": dict(name="sod_400x4", make=lambda: synth.sod(), crop=lambda: synth.sod(), steps=10000),
+    }
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_entry(workload, kernel, seg, per_launch_cells):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source, this workload and kernel variant."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    for e in rec.get("entries", []):
+        if (e.get("source_sha") == kernel_sha() and e.get("workload") == workload
+                and e.get("kernel") == kernel and int(e.get("rows", 0)) == int(seg)):
+            fetch = e["fetch_kib_per_dispatch"] * 1024 * e["copy_factor_fetch"]
+            write = e["write_kib_per_dispatch"] * 1024 * e["copy_factor_write"]
+            return {"bytes_per_launch": fetch + write,
+                    "bytes_per_update": (fetch + write) / per_launch_cells}
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's run length)")
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--config", default="mach3", choices=sorted(workloads()))
+    ap.add_argument("--kernel", default="auto", choices=["auto", "simple", "rows"])
+    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--graph-steps", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=12000, help="oracle steps on the crop")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only time a plain device copy of MIB MiB (the reference for the HBM "
+                         "byte counters and for achievable bandwidth) and exit")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)}); "
+              "the multi-GPU slab decomposition is a design, not an implementation.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_0908_3749_amd import MRT2D
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_mib": args.calibrate_copy, "bytes_read": 4 * n, "bytes_written": 4 * n,
+                          "ms": round(ms, 4), "gbs_read_plus_write": round(8 * n / ms / 1e6, 1)}), flush=True)
+        return 0
+    W = workloads()[args.config]
+    prob = W["make"]()
+    steps = args.steps if args.steps is not None else W["steps"]
+    cells = prob.nx * prob.ny
+
+    g = MRT2D.from_problem(prob, kernel=args.kernel, rows=args.rows, graph_steps=args.graph_steps)
+    g.init_problem(prob)
+    g.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(g.stream)
+    g.step(steps)
+    e1.record(g.stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / steps
+    mlups = cells * steps / (ms_total * 1e-3) / 1e6
+    sums = g.sums()
+    kernel, seg = g.kernel_info()
+    k_ms = g.kernel_time(50)
+    g.close()
+    achieved = BYTES_PER_UPDATE * cells / (k_ms * 1e-3) / 1e9
+    traffic = traffic_entry(W["name"], kernel, seg, cells)
+    print(f"bench: {W['name']} {steps} steps, {ms_step * 1e3:.2f} us/step, step kernel {kernel}"
+          f"/{seg} {k_ms * 1e3:.2f} us/launch, {mlups:.0f} MLUPS", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": W["name"], "nx": prob.nx, "ny": prob.ny, "dt": prob.dt,
+                   "kernel": kernel, "rows": seg, "graph_steps": args.graph_steps,
+                   "gamma": 2.0},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic["bytes_per_launch"]),
+                     "kernel_us": round(k_ms * 1e3, 3),
+                     "algorithmic_bytes_per_launch": BYTES_PER_UPDATE * cells},
+        "hbm_roofline_pct_whole_step": round(100.0 * BYTES_PER_UPDATE * cells / (ms_step * 1e-3) / 1e9
+                                             / HBM_PEAK_GBS, 2),
+        "fp64_sums": [float(v) for v in sums],
+    }
+
+    if not args.no_cpu:
+        from oracle import core, metrics
+
+        crop = W["crop"]()
+        n_cpu = args.cpu_steps
+        gc = MRT2D.from_problem(crop, kernel=args.kernel, rows=args.rows)
+        gc.init_problem(crop)
+        gc.step(n_cpu)
+        got = gc.macro_numpy()
+        gc.close()
+        threads = max(1, min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1, 16))
+        o = core.Grid(crop, nthreads=threads)
+        o.init_problem()
+        t0 = time.perf_counter()
+        o.run(n_cpu)
+        cpu_s = time.perf_counter() - t0
+        want = o.macro()
+        out["cpu_baseline"] = {
+            "value": round(crop.nx * crop.ny * n_cpu / cpu_s / 1e6, 3), "unit": "MLUPS",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{crop.nx}x{crop.ny} crop of {W['name']} (same dx, dt, rates, boundary rules), "
+                      f"{n_cpu} steps, FP64, {cpu_s:.1f} s",
+        }
+        out["accuracy"] = {
+            "against": "FP64 oracle, same crop and steps",
+            "rel_l1": {k: float(f"{metrics.rel_l1(got[k], want[k]):.3e}") for k in ("rho", "ux", "uy", "p")},
+            "linf": {k: float(f"{metrics.linf(got[k], want[k]):.3e}") for k in ("rho", "ux", "uy", "p")},
+        }
+        if not np.all(np.isfinite(got["rho"])):
+            out["accuracy"]["note"] = "non-finite values in the GPU crop run"
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,193 @@
+/*
+ * mrtfd -- the time step of the energy-conserving multiple-relaxation-time
+ * finite-difference lattice Boltzmann model of Chen, Xu, Zhang and Li
+ * ("Multiple-relaxation-time lattice Boltzmann model for compressible
+ * fluids", arXiv:0908.3749) on AMD MI355X (gfx950).
+ *
+ * One step, for every interior node of a 2D grid with the paper's 16
+ * discrete velocities (Sect. III, Eq. 4):
+ *   f-hat = M f (Eq. 5), equilibria f-hat^eq of the nonconserved moments
+ *   (Eq. 14), relaxation by the diagonal S-hat and the map back with M^-1
+ *   (Eq. 3), then forward Euler in time with the per-axis Lax-Wendroff
+ *   difference in space (appendix, Eq. A.1a-b), collision and advection both
+ *   evaluated at the old time level (Sect. IV, the update behind G).
+ * Boundary nodes carry f = f^eq of a macroscopic state chosen by a rule
+ * (Sect. V: prescribed, periodic, reflecting, linearly extrapolated, moving
+ * isothermal wall).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int32 status: MRTFD_OK (0) or a negative
+ *    MRTFD_ERR_* code; mrtfd_status_string() names it and
+ *    mrtfd_last_error() gives the context's last message.  No C++ exception
+ *    crosses this interface.  A failing call leaves the context usable.
+ *  - Pointers named d_* are device pointers (HBM of the GPU the context was
+ *    created on); all other pointers are host pointers.
+ *  - The caller owns all device memory: the library works inside one
+ *    caller-provided workspace and never allocates or frees device memory.
+ *    The context object itself is host memory owned by the library and
+ *    released by mrtfd_destroy().
+ *  - Every GPU operation is enqueued on the stream given at creation, in
+ *    call order.  Only calls returning host data (mrtfd_sums) synchronise
+ *    that stream.
+ *  - Macroscopic fields are FP32, row-major [ny][nx] over the interior
+ *    nodes, node (i, j) at x = (i + 1/2) dx, y = (j + 1/2) dy.
+ *  - Populations are numbered as in Eq. (4): 0-3 = cyc(+-1,0) in the order
+ *    (+,0),(0,+),(-,0),(0,-); 4-7 the same times 6; 8-11 = sqrt2(+-1,+-1) in
+ *    the order (+,+),(-,+),(-,-),(+,-); 12-15 the same times 3/sqrt2.
+ */
+#ifndef MRTFD_H
+#define MRTFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define MRTFD_OK 0
+#define MRTFD_ERR_ARG (-1)         /* a bad argument or parameter           */
+#define MRTFD_ERR_HIP (-2)         /* a HIP runtime call failed             */
+#define MRTFD_ERR_UNSTABLE (-3)    /* dt*s > 1 or Courant number > 1        */
+#define MRTFD_ERR_NONFINITE (-4)   /* NaN/Inf met in the state              */
+#define MRTFD_ERR_STATE (-5)       /* call out of order (e.g. step before init) */
+#define MRTFD_ERR_UNSUPPORTED (-6) /* a mode this build does not provide    */
+
+/* ---- boundary rules (Sect. V) ------------------------------------------ */
+#define MRTFD_BC_PERIODIC 0    /* copy of the opposite interior edge (V.A)      */
+#define MRTFD_BC_DIRICHLET 1   /* f^eq of the prescribed state (V.A, V.B)       */
+#define MRTFD_BC_REFLECT 2     /* adjacent interior state, normal velocity
+                                  reversed (V.B(a))                             */
+#define MRTFD_BC_EXTRAPOLATE 3 /* 2 q1 - q2 on (rho,u1,u2,T) from the first two
+                                  interior nodes, q1 if that gives rho <= 0 or
+                                  T <= 0 (V.B(a), "linear extrapolation")       */
+#define MRTFD_BC_WALL 4        /* (rho of the adjacent node, u1, u2, T of the
+                                  state): constant speed and temperature
+                                  walls (V.D)                                   */
+
+/* ---- arithmetic of the moment transforms ------------------------------- */
+#define MRTFD_FP32 0  /* FP32 everywhere (FP64 only in mrtfd_sums)            */
+#define MRTFD_BF16X3 1 /* transforms on MFMA, operands split hi/lo BF16, three
+                          products, FP32 accumulation                          */
+
+/* ---- kernel choice for the step ---------------------------------------- */
+#define MRTFD_KERNEL_AUTO 0   /* autotuned among the variants below            */
+#define MRTFD_KERNEL_SIMPLE 1 /* one thread per node, 64x4 tiles, neighbours
+                                 read from memory                              */
+#define MRTFD_KERNEL_ROWS 2   /* each wave: `rows` rows of 64 columns loaded
+                                 once, west/east neighbours by lane shifts     */
+
+/* One side of the grid.  The rule is kind_lo at ghost nodes whose
+ * along-side coordinate (x for the south/north sides, y for west/east) is
+ * <= split0 + split_rate * t, and kind_hi beyond; set kind_lo == kind_hi for
+ * a single rule.  state_* = (rho, u1, u2, T) for DIRICHLET, (ignored, u1,
+ * u2, T) for WALL, unused otherwise.  A PERIODIC side needs the opposite
+ * side PERIODIC too, on both parts. */
+typedef struct mrtfd_side {
+    int32_t kind_lo, kind_hi;
+    double state_lo[4];
+    double state_hi[4];
+    double split0, split_rate;
+} mrtfd_side;
+
+/* Problem parameters.  s[k] is s_{k+1} of S-hat (Eq. 3); s[0..3] act on
+ * conserved moments and are ignored.  side[] = west (i = -1), east (i = nx),
+ * south (j = -1), north (j = ny).  Validation: nx, ny >= 3; dx, dy, dt > 0;
+ * 0 <= dt*s_k <= 1 for k >= 5 (the paper never goes beyond); 6 dt / min(dx,
+ * dy) <= 1 (Courant number of the fastest velocity). */
+typedef struct mrtfd_params {
+    int32_t nx, ny;
+    double dx, dy, dt;
+    double s[16];
+    mrtfd_side side[4];
+    int32_t precision;  /* MRTFD_FP32 or MRTFD_BF16X3                        */
+    int32_t kernel;     /* MRTFD_KERNEL_*                                    */
+    int32_t rows;       /* rows per wave for MRTFD_KERNEL_ROWS (1 or 2),
+                           0 = auto                                          */
+    int32_t graph_steps;/* steps per captured HIP graph, 0 = no graph        */
+} mrtfd_params;
+
+typedef struct mrtfd_ctx mrtfd_ctx;
+
+/* Size in bytes of the device workspace a context with these parameters
+ * needs (two FP32 copies of f with a ghost ring plus reduction scratch).
+ * Returns 0 if the parameters are invalid. */
+size_t mrtfd_workspace_bytes(const mrtfd_params *p);
+
+/* Validate parameters without touching the GPU.  Writes a message into msg
+ * (host buffer of msg_len bytes, may be NULL).  Returns MRTFD_OK,
+ * MRTFD_ERR_ARG or MRTFD_ERR_UNSTABLE. */
+int32_t mrtfd_check_params(const mrtfd_params *p, char *msg, size_t msg_len);
+
+/* Create a context.  Builds M from Eq. (5) on the host, inverts it in FP64
+ * and uploads the FP32 constants.  d_workspace: device buffer of at least
+ * mrtfd_workspace_bytes(p) bytes, 256-byte aligned, owned by the caller and
+ * kept alive until mrtfd_destroy.  stream: a hipStream_t (NULL = default
+ * stream).  On success *out receives the context. */
+int32_t mrtfd_create(const mrtfd_params *p, void *d_workspace, size_t workspace_bytes,
+                     void *stream, mrtfd_ctx **out);
+
+/* Release the context (host memory, graphs).  The workspace is untouched. */
+int32_t mrtfd_destroy(mrtfd_ctx *ctx);
+
+/* Initialise f = M^-1 f-hat^eq(rho, rho u, rho (T + |u|^2/2)) at every
+ * interior node (the equilibrium of the macroscopic initial condition, as
+ * the paper's boundary and initial states are set) and reset the clock to
+ * step 0.  Inputs: four device [ny][nx] FP32 arrays.  rho > 0 and T > 0 are
+ * required; a violation (or a non-finite input) is reported by the next
+ * mrtfd_sums as MRTFD_ERR_ARG. */
+int32_t mrtfd_init_macro(mrtfd_ctx *ctx, const float *d_rho, const float *d_ux,
+                         const float *d_uy, const float *d_T);
+
+/* Advance nsteps >= 0 time steps (each: boundary nodes at time t_n = n dt
+ * from f^n, then the fused collision + Lax-Wendroff + Euler update of every
+ * interior node). */
+int32_t mrtfd_step(mrtfd_ctx *ctx, int64_t nsteps);
+
+/* Macroscopic fields of the current state: rho = f-hat_1, u = j / rho,
+ * T = (e - rho |u|^2 / 2) / rho, p = rho T (R = 1).  Outputs are device
+ * [ny][nx] FP32 arrays; any of them may be NULL. */
+int32_t mrtfd_read_macro(mrtfd_ctx *ctx, float *d_rho, float *d_ux, float *d_uy,
+                         float *d_T, float *d_p);
+
+/* FP64 sums over the interior of rho, j_x, j_y, e (host array out[4]).
+ * Deterministic (fixed reduction order).  Synchronises the stream.  Returns
+ * MRTFD_ERR_NONFINITE if any sum is not finite. */
+int32_t mrtfd_sums(mrtfd_ctx *ctx, double out[4]);
+
+/* Copy the interior populations out of / into the context as a packed
+ * device FP32 array [16][ny][nx] (checkpoint / restart, seeded states). */
+int32_t mrtfd_get_f(mrtfd_ctx *ctx, float *d_f);
+int32_t mrtfd_set_f(mrtfd_ctx *ctx, const float *d_f);
+
+/* Current step index and time t = step * dt (host outputs, may be NULL). */
+int32_t mrtfd_time(mrtfd_ctx *ctx, int64_t *step, double *t);
+
+/* Set the clock to step index `step` >= 0 (t = step * dt), e.g. after
+ * mrtfd_set_f on a restart, so that time-dependent boundary rules carry on
+ * where they stopped. */
+int32_t mrtfd_set_step(mrtfd_ctx *ctx, int64_t step);
+
+/* The step kernel actually used (MRTFD_KERNEL_SIMPLE or _ROWS) and its rows
+ * per wave, after autotuning (host outputs, may be NULL). */
+int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows);
+
+/* Average duration in milliseconds of one launch of the step kernel alone
+ * (without the boundary-node kernel), timed with HIP events over nlaunch >= 1
+ * back-to-back launches on the context's stream.  The trial launches read
+ * the current state and write the spare copy, which the next step
+ * overwrites, so the state is unchanged.  Synchronises the stream. */
+int32_t mrtfd_kernel_time(mrtfd_ctx *ctx, int32_t nlaunch, double *ms_per_launch);
+
+/* sizeof(mrtfd_params) and sizeof(mrtfd_side) as compiled into the library,
+ * so that language bindings can check their struct layouts. */
+int32_t mrtfd_struct_sizes(size_t *params_size, size_t *side_size);
+
+const char *mrtfd_status_string(int32_t status);
+const char *mrtfd_last_error(const mrtfd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRTFD_H */

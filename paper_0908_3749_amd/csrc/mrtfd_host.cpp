@@ -1,0 +1,818 @@
+// Host side of the MRT finite-difference lattice Boltzmann library: the model
+// constants (velocity set, M, its FP64 inverse, the factored FP32 transform),
+// parameter validation, the context, the HIP-graph step loop, the step-kernel
+// autotuner and the C ABI declared in include/mrtfd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "../../include/mrtfd.h"
+#include "mrtfd_internal.h"
+
+using namespace mrtfd;
+
+namespace {
+
+// ------------------------------------------------------------------ model
+
+// Discrete velocities of Eq. (4), grouped (+-1 axes, +-6 axes, sqrt2
+// diagonals, 3/sqrt2 diagonals), in the order printed in the rows of M.
+void velocity_set(double v[NQ][2])
+{
+    const double ax[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+    const double dg[4][2] = {{1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+    const double scale[4] = {1.0, 6.0, std::sqrt(2.0), 3.0 / std::sqrt(2.0)};
+    for (int g = 0; g < 4; ++g)
+        for (int k = 0; k < 4; ++k) {
+            const double(*dir)[2] = g < 2 ? ax : dg;
+            v[4 * g + k][0] = scale[g] * dir[k][0];
+            v[4 * g + k][1] = scale[g] * dir[k][1];
+        }
+}
+
+// Row r of M evaluated at velocity (x, y): the polynomials of Eq. (5a)-(5p).
+double m_row(int r, double x, double y)
+{
+    const double q = x * x + y * y, c2 = x * x - y * y, s2 = x * y;
+    const double c3 = x * (x * x - 3 * y * y), s3 = y * (3 * x * x - y * y);
+    switch (r) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return 0.5 * q;
+    case 4: return c2;
+    case 5: return s2;
+    case 6: return 0.5 * q * x;
+    case 7: return 0.5 * q * y;
+    case 8: return c3;
+    case 9: return s3;
+    case 10: return 0.25 * q * q;
+    case 11: return c2 * c2 - 4 * s2 * s2;  // x^4 - 6 x^2 y^2 + y^4
+    case 12: return q * c2;
+    case 13: return q * s2;
+    case 14: return q * c3;
+    default: return q * s3;
+    }
+}
+
+// LU factorisation with partial pivoting, then n solves for the columns of
+// the inverse.  Returns false for a singular matrix.
+bool lu_inverse(int n, const double *A, double *Ainv)
+{
+    std::vector<double> a(A, A + n * n);
+    std::vector<int> piv(n);
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        for (int r = k + 1; r < n; ++r)
+            if (std::fabs(a[r * n + k]) > std::fabs(a[p * n + k])) p = r;
+        if (a[p * n + k] == 0.0) return false;
+        piv[k] = p;
+        if (p != k)
+            for (int c = 0; c < n; ++c) std::swap(a[k * n + c], a[p * n + c]);
+        for (int r = k + 1; r < n; ++r) {
+            a[r * n + k] /= a[k * n + k];
+            for (int c = k + 1; c < n; ++c) a[r * n + c] -= a[r * n + k] * a[k * n + c];
+        }
+    }
+    for (int col = 0; col < n; ++col) {
+        std::vector<double> b(n, 0.0);
+        b[col] = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (piv[k] != k) std::swap(b[k], b[piv[k]]);
+        for (int r = 0; r < n; ++r)
+            for (int c = 0; c < r; ++c) b[r] -= a[r * n + c] * b[c];
+        for (int r = n - 1; r >= 0; --r) {
+            for (int c = r + 1; c < n; ++c) b[r] -= a[r * n + c] * b[c];
+            b[r] /= a[r * n + r];
+        }
+        for (int r = 0; r < n; ++r) Ainv[r * n + col] = b[r];
+    }
+    return true;
+}
+
+struct Model {
+    double v[NQ][2];
+    double M[NQ][NQ], Minv[NQ][NQ];
+    // Butterfly P (u = P f, u = [A0..3, X0..3, Y0..3, Q0..3]), B = M P^-1 and
+    // D B^-1 = D P M^-1 with D the butterfly scales (inverse butterfly = adds).
+    double B[NQ][NQ], DBinv[NQ][NQ];
+    bool ok = false;
+    char why[160] = {0};
+};
+
+Model build_model()
+{
+    Model m;
+    velocity_set(m.v);
+    for (int r = 0; r < NQ; ++r)
+        for (int i = 0; i < NQ; ++i) m.M[r][i] = m_row(r, m.v[i][0], m.v[i][1]);
+    if (!lu_inverse(NQ, &m.M[0][0], &m.Minv[0][0])) {
+        std::snprintf(m.why, sizeof m.why, "M is singular");
+        return m;
+    }
+    double P[NQ][NQ] = {{0}}, Pinv[NQ][NQ];
+    const int sx_axis[4] = {1, 0, -1, 0}, sy_axis[4] = {0, 1, 0, -1};
+    const int sx_diag[4] = {1, -1, -1, 1}, sy_diag[4] = {1, 1, -1, -1};
+    const int sq[4] = {1, -1, 1, -1};
+    for (int g = 0; g < 4; ++g)
+        for (int k = 0; k < 4; ++k) {
+            const int c = 4 * g + k;
+            P[g][c] = 1.0;
+            P[4 + g][c] = g < 2 ? sx_axis[k] : sx_diag[k];
+            P[8 + g][c] = g < 2 ? sy_axis[k] : sy_diag[k];
+            P[12 + g][c] = sq[k];
+        }
+    if (!lu_inverse(NQ, &P[0][0], &Pinv[0][0])) {
+        std::snprintf(m.why, sizeof m.why, "butterfly is singular");
+        return m;
+    }
+    // D: axis groups A,Q /4 and X,Y /2; diagonal groups all /4.
+    double D[NQ];
+    for (int g = 0; g < 4; ++g) {
+        D[g] = D[12 + g] = 0.25;
+        D[4 + g] = D[8 + g] = g < 2 ? 0.5 : 0.25;
+    }
+    for (int r = 0; r < NQ; ++r)
+        for (int c = 0; c < NQ; ++c) {
+            double b = 0.0, bi = 0.0;
+            for (int k = 0; k < NQ; ++k) {
+                b += m.M[r][k] * Pinv[k][c];
+                bi += P[r][k] * m.Minv[k][c];
+            }
+            m.B[r][c] = b;
+            m.DBinv[r][c] = D[r] * bi;
+        }
+    // The block structure the kernels rely on: check that everything outside
+    // the blocks vanishes, and that the adds-only inverse butterfly applied
+    // to D B^-1 gives back M^-1.
+    auto block_of_moment = [](int k) {
+        switch (k) {
+        case 0: case 3: case 10: case 11: return 0;
+        case 1: case 6: case 8: case 14: return 1;
+        case 2: case 7: case 9: case 15: return 2;
+        case 4: case 12: return 3;
+        default: return 4;  // 5, 13
+        }
+    };
+    auto block_of_comb = [](int c) {
+        if (c < 4) return 0;
+        if (c < 8) return 1;
+        if (c < 12) return 2;
+        return c < 14 ? 3 : 4;
+    };
+    double worst = 0.0;
+    for (int r = 0; r < NQ; ++r)
+        for (int c = 0; c < NQ; ++c) {
+            if (block_of_moment(r) != block_of_comb(c))
+                worst = std::max(worst, std::fabs(m.B[r][c]) / 7776.0);
+            if (block_of_comb(r) != block_of_moment(c)) worst = std::max(worst, std::fabs(m.DBinv[r][c]));
+        }
+    double E[NQ][NQ] = {{0}};  // inverse butterfly as adds (group_inv in the kernels)
+    for (int g = 0; g < 4; ++g) {
+        const int a = g, x = 4 + g, y = 8 + g, q = 12 + g, b = 4 * g;
+        E[b + 0][a] = 1; E[b + 0][q] = 1;
+        E[b + 2][a] = 1; E[b + 2][q] = 1;
+        E[b + 1][a] = 1; E[b + 1][q] = -1;
+        E[b + 3][a] = 1; E[b + 3][q] = -1;
+        if (g < 2) {
+            E[b + 0][x] = 1; E[b + 2][x] = -1; E[b + 1][y] = 1; E[b + 3][y] = -1;
+        } else {
+            E[b + 0][x] = 1; E[b + 0][y] = 1;
+            E[b + 2][x] = -1; E[b + 2][y] = -1;
+            E[b + 1][x] = -1; E[b + 1][y] = 1;
+            E[b + 3][x] = 1; E[b + 3][y] = -1;
+        }
+    }
+    for (int r = 0; r < NQ; ++r)
+        for (int c = 0; c < NQ; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < NQ; ++k) acc += E[r][k] * m.DBinv[k][c];
+            worst = std::max(worst, std::fabs(acc - m.Minv[r][c]));
+        }
+    if (worst > 1e-12) {
+        std::snprintf(m.why, sizeof m.why, "transform structure check failed (%.3g)", worst);
+        return m;
+    }
+    m.ok = true;
+    return m;
+}
+
+const Model &model()
+{
+    static const Model m = build_model();
+    return m;
+}
+
+// f^eq = M^-1 f-hat^eq of a macroscopic state, FP64 (Dirichlet boundary states).
+void feq_host(const Model &m, double rho, double ux, double uy, double T, double out[NQ])
+{
+    const double jx = rho * ux, jy = rho * uy, e = rho * (T + 0.5 * (ux * ux + uy * uy));
+    const double P = rho * T, j2 = jx * jx + jy * jy;
+    double h[NQ] = {rho, jx, jy, e,
+                    (jx * jx - jy * jy) / rho, jx * jy / rho, (e + P) * jx / rho, (e + P) * jy / rho,
+                    (jx * jx - 3 * jy * jy) * jx / (rho * rho), (3 * jx * jx - jy * jy) * jy / (rho * rho),
+                    2 * e * e / rho - j2 * j2 / (4 * rho * rho * rho), 0.0,
+                    (6 * rho * e - 2 * j2) * (jx * jx - jy * jy) / (rho * rho * rho),
+                    (6 * rho * e - 2 * j2) * jx * jy / (rho * rho * rho), 0.0, 0.0};
+    for (int i = 0; i < NQ; ++i) {
+        double a = 0.0;
+        for (int k = 0; k < NQ; ++k) a += m.Minv[i][k] * h[k];
+        out[i] = a;
+    }
+}
+
+void fill_consts(const Model &m, const mrtfd_params &p, Consts &K)
+{
+    std::memset(&K, 0, sizeof K);
+    const int r0[4] = {0, 3, 10, 11}, rx[4] = {1, 6, 8, 14}, ry[4] = {2, 7, 9, 15};
+    const int rqa[2] = {4, 12}, rqd[2] = {5, 13};
+    for (int a = 0; a < 4; ++a)
+        for (int g = 0; g < 4; ++g) {
+            K.f0[a][g] = (float)m.B[r0[a]][g];
+            K.fx[a][g] = (float)m.B[rx[a]][4 + g];
+            K.fy[a][g] = (float)m.B[ry[a]][8 + g];
+            K.i0[g][a] = (float)m.DBinv[g][r0[a]];
+            K.ix[g][a] = (float)m.DBinv[4 + g][rx[a]];
+            K.iy[g][a] = (float)m.DBinv[8 + g][ry[a]];
+        }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            K.fqa[a][b] = (float)m.B[rqa[a]][12 + b];
+            K.fqd[a][b] = (float)m.B[rqd[a]][14 + b];
+            K.iqa[a][b] = (float)m.DBinv[12 + a][rqa[b]];
+            K.iqd[a][b] = (float)m.DBinv[14 + a][rqd[b]];
+        }
+    // collision columns: D B^-1 scaled by dt s_k (FP64 product, then rounded)
+    const double dt = p.dt;
+    auto cs = [&](int row, int k) { return (float)(m.DBinv[row][k] * dt * p.s[k]); };
+    const int k0[2] = {10, 11}, kx[3] = {6, 8, 14}, ky[3] = {7, 9, 15};
+    for (int g = 0; g < 4; ++g) {
+        for (int a = 0; a < 2; ++a) K.c0[g][a] = cs(g, k0[a]);
+        for (int a = 0; a < 3; ++a) {
+            K.cx[g][a] = cs(4 + g, kx[a]);
+            K.cy[g][a] = cs(8 + g, ky[a]);
+        }
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            K.cqa[a][b] = cs(12 + a, rqa[b]);
+            K.cqd[a][b] = cs(14 + a, rqd[b]);
+        }
+    for (int q = 0; q < NQ; ++q) {
+        const double a = m.v[q][0] * dt / p.dx, b = m.v[q][1] * dt / p.dy;
+        K.lw[q][0] = (float)(0.5 * (a * a - a));
+        K.lw[q][1] = (float)(0.5 * (a * a + a));
+        K.lw[q][2] = (float)(0.5 * (b * b - b));
+        K.lw[q][3] = (float)(0.5 * (b * b + b));
+    }
+}
+
+// --------------------------------------------------------------- validation
+
+int check(const mrtfd_params *p, char *msg, size_t len)
+{
+    auto fail = [&](int code, const char *fmt, ...) {
+        if (msg && len) {
+            va_list ap;
+            va_start(ap, fmt);
+            std::vsnprintf(msg, len, fmt, ap);
+            va_end(ap);
+        }
+        return code;
+    };
+    if (!p) return fail(MRTFD_ERR_ARG, "params is NULL");
+    if (p->nx < 3 || p->ny < 3) return fail(MRTFD_ERR_ARG, "nx and ny must be >= 3 (got %d, %d)", p->nx, p->ny);
+    if ((long long)p->nx * p->ny > (1LL << 31))
+        return fail(MRTFD_ERR_ARG, "grid of %lld nodes is too large", (long long)p->nx * p->ny);
+    if (!(p->dx > 0) || !(p->dy > 0) || !(p->dt > 0) || !std::isfinite(p->dx) ||
+        !std::isfinite(p->dy) || !std::isfinite(p->dt))
+        return fail(MRTFD_ERR_ARG, "dx, dy, dt must be positive and finite");
+    for (int k = 4; k < NQ; ++k) {
+        if (!(p->s[k] >= 0) || !std::isfinite(p->s[k]))
+            return fail(MRTFD_ERR_ARG, "s_%d must be finite and >= 0", k + 1);
+        if (p->dt * p->s[k] > 1.0 + 1e-12)
+            return fail(MRTFD_ERR_UNSTABLE, "dt * s_%d = %g exceeds 1", k + 1, p->dt * p->s[k]);
+    }
+    const double cfl = 6.0 * p->dt / std::min(p->dx, p->dy);
+    if (cfl > 1.0) return fail(MRTFD_ERR_UNSTABLE, "Courant number 6 dt / min(dx,dy) = %g exceeds 1", cfl);
+    if (p->precision != MRTFD_FP32 && p->precision != MRTFD_BF16X3)
+        return fail(MRTFD_ERR_ARG, "unknown precision mode %d", p->precision);
+    if (p->precision == MRTFD_BF16X3)
+        return fail(MRTFD_ERR_UNSUPPORTED, "precision mode MRTFD_BF16X3 is not available in this build");
+    if (p->kernel < MRTFD_KERNEL_AUTO || p->kernel > MRTFD_KERNEL_ROWS)
+        return fail(MRTFD_ERR_ARG, "unknown kernel %d", p->kernel);
+    if (p->rows != 0 && p->rows != 1 && p->rows != 2)
+        return fail(MRTFD_ERR_ARG, "rows must be 0, 1 or 2");
+    if (p->graph_steps < 0 || (p->graph_steps % 2) != 0 || p->graph_steps > 4096)
+        return fail(MRTFD_ERR_ARG, "graph_steps must be even, in [0, 4096]");
+    for (int s = 0; s < 4; ++s) {
+        const mrtfd_side &S = p->side[s];
+        for (int part = 0; part < 2; ++part) {
+            const int kind = part ? S.kind_hi : S.kind_lo;
+            const double *st = part ? S.state_hi : S.state_lo;
+            if (kind < MRTFD_BC_PERIODIC || kind > MRTFD_BC_WALL)
+                return fail(MRTFD_ERR_ARG, "side %d: unknown rule %d", s, kind);
+            if (kind == MRTFD_BC_PERIODIC) {
+                const mrtfd_side &O = p->side[s ^ 1];
+                if (O.kind_lo != MRTFD_BC_PERIODIC || O.kind_hi != MRTFD_BC_PERIODIC ||
+                    S.kind_lo != MRTFD_BC_PERIODIC || S.kind_hi != MRTFD_BC_PERIODIC)
+                    return fail(MRTFD_ERR_ARG, "side %d: periodic needs the opposite side periodic", s);
+            }
+            if (kind == MRTFD_BC_DIRICHLET && (!(st[0] > 0) || !(st[3] > 0)))
+                return fail(MRTFD_ERR_ARG, "side %d: Dirichlet state needs rho > 0 and T > 0", s);
+            if (kind == MRTFD_BC_WALL && !(st[3] > 0))
+                return fail(MRTFD_ERR_ARG, "side %d: wall temperature must be > 0", s);
+            for (int c = 0; c < 4; ++c)
+                if (!std::isfinite(st[c])) return fail(MRTFD_ERR_ARG, "side %d: state is not finite", s);
+        }
+        if (std::isnan(S.split0) || !std::isfinite(S.split_rate))
+            return fail(MRTFD_ERR_ARG, "side %d: bad split point", s);
+    }
+    if (msg && len) msg[0] = 0;
+    return MRTFD_OK;
+}
+
+Field make_field(const mrtfd_params &p)
+{
+    Field F;
+    F.nx = p.nx;
+    F.ny = p.ny;
+    F.xoff = 64;
+    F.pitch = ((F.xoff + p.nx + 1 + 63) / 64) * 64;
+    F.plane = (long long)F.pitch * (p.ny + 2);
+    return F;
+}
+
+struct Layout {
+    size_t fA, fB, partials, sums, step, flag, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout layout(const mrtfd_params &p)
+{
+    const Field F = make_field(p);
+    Layout L;
+    const size_t fbytes = align256((size_t)NQ * (size_t)F.plane * sizeof(float));
+    L.fA = 0;
+    L.fB = L.fA + fbytes;
+    L.partials = L.fB + fbytes;
+    L.sums = L.partials + align256(1024 * 4 * sizeof(double));
+    L.step = L.sums + 256;
+    L.flag = L.step + 256;
+    L.total = L.flag + 256;
+    return L;
+}
+
+// ----------------------------------------------------------- autotune cache
+
+struct TuneKey {
+    int nx, ny;
+    bool operator<(const TuneKey &o) const { return nx != o.nx ? nx < o.nx : ny < o.ny; }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+
+struct mrtfd_ctx {
+    mrtfd_params p;
+    Field F;
+    Consts K;
+    Ghosts G;
+    SumW W;
+    Layout L;
+    char *ws = nullptr;
+    float *f[2] = {nullptr, nullptr};
+    double *partials = nullptr, *sums = nullptr;
+    long long *d_step = nullptr;
+    int *d_flag = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;  // private stream used only to capture graphs
+    int device = 0;
+    int cur = 0;                 // which copy holds the state
+    long long step = 0;
+    bool initialised = false;
+    int kernel = 0, seg = 0;     // chosen step kernel and its rows per wave
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // by starting copy
+    char err[512] = {0};
+};
+
+namespace {
+
+int set_err(mrtfd_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(c->err, sizeof c->err, fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return set_err(ctx, MRTFD_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+hipError_t launch_step(mrtfd_ctx *c, const float *fin, float *fout, int k, hipStream_t s)
+{
+    if (c->kernel == MRTFD_KERNEL_SIMPLE)
+        return launch_step_simple(c->F, c->K, c->G, fin, fout, c->d_step, k, s);
+    return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg, c->d_step, k, s);
+}
+
+// Enqueue n steps starting from copy `start`, then advance the device clock.
+hipError_t enqueue_steps(mrtfd_ctx *c, int start, int n, hipStream_t s)
+{
+    int a = start;
+    for (int k = 0; k < n; ++k) {
+        hipError_t e = launch_step(c, c->f[a], c->f[a ^ 1], k, s);
+        if (e != hipSuccess) return e;
+        a ^= 1;
+    }
+    return launch_counter_add(c->d_step, n, s);
+}
+
+void drop_graphs(mrtfd_ctx *c)
+{
+    for (int k = 0; k < 2; ++k)
+        if (c->graph[k]) {
+            (void)hipGraphExecDestroy(c->graph[k]);
+            c->graph[k] = nullptr;
+        }
+}
+
+int build_graph(mrtfd_ctx *c, int start)
+{
+    if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_steps(c, start, c->p.graph_steps, c->cap);
+    hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return set_err(c, MRTFD_ERR_HIP, "graph capture failed: %s",
+                       hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return set_err(c, MRTFD_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    c->graph[start] = ex;
+    return MRTFD_OK;
+}
+
+// Pick the step kernel by timing each candidate for a few steps.  Trials read
+// the current copy and write the other one, which the next real step
+// overwrites, so the state is untouched.
+int autotune(mrtfd_ctx *c)
+{
+    if (c->kernel) return MRTFD_OK;
+    const TuneKey key{c->p.nx, c->p.ny};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            c->kernel = it->second.first;
+            c->seg = it->second.second;
+            return MRTFD_OK;
+        }
+    }
+    std::vector<std::pair<int, int>> cands;
+    if (c->p.kernel == MRTFD_KERNEL_SIMPLE) {
+        cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
+    } else {
+        for (int r = 1; r <= 2; ++r) {
+            if (c->p.rows && r != c->p.rows) continue;
+            cands.push_back({MRTFD_KERNEL_ROWS, r});
+        }
+        if (c->p.kernel == MRTFD_KERNEL_AUTO) cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
+    }
+    if (cands.size() == 1) {
+        c->kernel = cands[0].first;
+        c->seg = cands[0].second;
+        return MRTFD_OK;
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const double cells = (double)c->p.nx * c->p.ny;
+    const int reps = (int)std::max(3.0, std::min(50.0, 2e7 / cells));
+    float best = 1e30f;
+    std::pair<int, int> pick = cands[0];
+    int rc = MRTFD_OK;
+    for (auto cand : cands) {
+        c->kernel = cand.first;
+        c->seg = cand.second;
+        hipError_t e = launch_step(c, c->f[c->cur], c->f[c->cur ^ 1], 0, c->stream);  // warm-up
+        e = e == hipSuccess ? hipEventRecord(e0, c->stream) : e;
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = launch_step(c, c->f[c->cur], c->f[c->cur ^ 1], 0, c->stream);
+        e = e == hipSuccess ? hipEventRecord(e1, c->stream) : e;
+        e = e == hipSuccess ? hipEventSynchronize(e1) : e;
+        float ms = 0.f;
+        e = e == hipSuccess ? hipEventElapsedTime(&ms, e0, e1) : e;
+        if (e != hipSuccess) {
+            rc = set_err(c, MRTFD_ERR_HIP, "autotune: %s", hipGetErrorString(e));
+            break;
+        }
+        if (ms < best) {
+            best = ms;
+            pick = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->kernel = pick.first;
+    c->seg = pick.second;
+    if (rc == MRTFD_OK) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = pick;
+    }
+    return rc;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char *mrtfd_status_string(int32_t s)
+{
+    switch (s) {
+    case MRTFD_OK: return "ok";
+    case MRTFD_ERR_ARG: return "invalid argument";
+    case MRTFD_ERR_HIP: return "HIP runtime error";
+    case MRTFD_ERR_UNSTABLE: return "parameters outside the stable range";
+    case MRTFD_ERR_NONFINITE: return "non-finite values in the state";
+    case MRTFD_ERR_STATE: return "call out of order";
+    case MRTFD_ERR_UNSUPPORTED: return "unsupported mode";
+    default: return "unknown status";
+    }
+}
+
+const char *mrtfd_last_error(const mrtfd_ctx *c) { return c ? c->err : "no context"; }
+
+int32_t mrtfd_struct_sizes(size_t *params_size, size_t *side_size)
+{
+    if (params_size) *params_size = sizeof(mrtfd_params);
+    if (side_size) *side_size = sizeof(mrtfd_side);
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_check_params(const mrtfd_params *p, char *msg, size_t msg_len)
+{
+    try {
+        return check(p, msg, msg_len);
+    } catch (...) {
+        return MRTFD_ERR_ARG;
+    }
+}
+
+size_t mrtfd_workspace_bytes(const mrtfd_params *p)
+{
+    try {
+        if (check(p, nullptr, 0) != MRTFD_OK) return 0;
+        return layout(*p).total;
+    } catch (...) {
+        return 0;
+    }
+}
+
+int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *stream,
+                     mrtfd_ctx **out)
+{
+    if (!out) return MRTFD_ERR_ARG;
+    *out = nullptr;
+    char msg[256];
+    int rc = check(p, msg, sizeof msg);
+    if (rc != MRTFD_OK) return rc;
+    const Model &m = model();
+    if (!m.ok) return MRTFD_ERR_ARG;
+    const Layout L = layout(*p);
+    if (!d_ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(d_ws) & 255)) return MRTFD_ERR_ARG;
+    mrtfd_ctx *c = new (std::nothrow) mrtfd_ctx();
+    if (!c) return MRTFD_ERR_ARG;
+    c->p = *p;
+    c->F = make_field(*p);
+    c->L = L;
+    c->ws = static_cast<char *>(d_ws);
+    c->f[0] = reinterpret_cast<float *>(c->ws + L.fA);
+    c->f[1] = reinterpret_cast<float *>(c->ws + L.fB);
+    c->partials = reinterpret_cast<double *>(c->ws + L.partials);
+    c->sums = reinterpret_cast<double *>(c->ws + L.sums);
+    c->d_step = reinterpret_cast<long long *>(c->ws + L.step);
+    c->d_flag = reinterpret_cast<int *>(c->ws + L.flag);
+    c->stream = static_cast<hipStream_t>(stream);
+    fill_consts(m, *p, c->K);
+    for (int k = 0; k < 4; ++k)
+        for (int q = 0; q < NQ; ++q) c->W.w[k][q] = m.M[k][q];
+    c->G.dt = p->dt;
+    c->G.per_x = p->side[0].kind_lo == MRTFD_BC_PERIODIC;
+    c->G.per_y = p->side[2].kind_lo == MRTFD_BC_PERIODIC;
+    for (int s = 0; s < 4; ++s) {
+        const mrtfd_side &S = p->side[s];
+        GhostSide &g = c->G.side[s];
+        g.kind_lo = S.kind_lo;
+        g.kind_hi = S.kind_hi;
+        g.split0 = S.split0;
+        g.split_rate = S.split_rate;
+        g.h = s < 2 ? p->dy : p->dx;
+        double fe[NQ];
+        for (int k = 0; k < 4; ++k) {
+            g.st_lo[k] = (float)S.state_lo[k];
+            g.st_hi[k] = (float)S.state_hi[k];
+        }
+        const bool dlo = S.kind_lo == MRTFD_BC_DIRICHLET, dhi = S.kind_hi == MRTFD_BC_DIRICHLET;
+        std::memset(g.feq_lo, 0, sizeof g.feq_lo);
+        std::memset(g.feq_hi, 0, sizeof g.feq_hi);
+        if (dlo) {
+            feq_host(m, S.state_lo[0], S.state_lo[1], S.state_lo[2], S.state_lo[3], fe);
+            for (int q = 0; q < NQ; ++q) g.feq_lo[q] = (float)fe[q];
+        }
+        if (dhi) {
+            feq_host(m, S.state_hi[0], S.state_hi[1], S.state_hi[2], S.state_hi[3], fe);
+            for (int q = 0; q < NQ; ++q) g.feq_hi[q] = (float)fe[q];
+        }
+    }
+    if (p->kernel == MRTFD_KERNEL_ROWS && p->rows) {
+        c->kernel = MRTFD_KERNEL_ROWS;
+        c->seg = p->rows;
+    }
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return MRTFD_ERR_HIP;
+    }
+    *out = c;
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_destroy(mrtfd_ctx *c)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    drop_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    delete c;
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_init_macro(mrtfd_ctx *c, const float *rho, const float *ux, const float *uy,
+                         const float *T)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    if (!rho || !ux || !uy || !T) return set_err(c, MRTFD_ERR_ARG, "init_macro: NULL field");
+    HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+    c->cur = 0;
+    HIPCHK(c, launch_init(c->F, c->K, c->f[0], rho, ux, uy, T, c->d_flag, c->stream));
+    HIPCHK(c, launch_counter_set(c->d_step, 0, c->stream));
+    c->step = 0;
+    c->initialised = true;
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_set_f(mrtfd_ctx *c, const float *src)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    if (!src) return set_err(c, MRTFD_ERR_ARG, "set_f: NULL array");
+    HIPCHK(c, launch_unpack(c->F, src, c->f[c->cur], c->stream));
+    c->initialised = true;
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_get_f(mrtfd_ctx *c, float *dst)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    if (!dst) return set_err(c, MRTFD_ERR_ARG, "get_f: NULL array");
+    if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "get_f before init");
+    HIPCHK(c, launch_pack(c->F, c->f[c->cur], dst, c->stream));
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_step(mrtfd_ctx *c, int64_t nsteps)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    if (nsteps < 0) return set_err(c, MRTFD_ERR_ARG, "nsteps must be >= 0");
+    if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "step before init");
+    if (nsteps == 0) return MRTFD_OK;
+    if (!c->kernel) {
+        int rc = autotune(c);
+        if (rc != MRTFD_OK) return rc;
+    }
+    long long left = nsteps;
+    const int G = c->p.graph_steps;
+    if (G > 0) {
+        while (left >= G) {
+            if (!c->graph[c->cur]) {
+                int rc = build_graph(c, c->cur);
+                if (rc != MRTFD_OK) return rc;
+            }
+            HIPCHK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
+            left -= G;  // G is even: the state ends in the copy it started from
+            c->step += G;
+        }
+    }
+    while (left > 0) {
+        const int n = (int)std::min<long long>(left, 1 << 20);
+        HIPCHK(c, enqueue_steps(c, c->cur, n, c->stream));
+        if (n & 1) c->cur ^= 1;
+        left -= n;
+        c->step += n;
+    }
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_read_macro(mrtfd_ctx *c, float *rho, float *ux, float *uy, float *T, float *p)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "read_macro before init");
+    HIPCHK(c, launch_read_macro(c->F, c->K, c->f[c->cur], rho, ux, uy, T, p, c->stream));
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_sums(mrtfd_ctx *c, double out[4])
+{
+    if (!c || !out) return MRTFD_ERR_ARG;
+    if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "sums before init");
+    HIPCHK(c, launch_sums(c->F, c->W, c->f[c->cur], c->partials, c->sums, c->stream));
+    double h[4];
+    int flag = 0;
+    HIPCHK(c, hipMemcpyAsync(h, c->sums, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&flag, c->d_flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 4; ++k) out[k] = h[k];
+    if (flag) return set_err(c, MRTFD_ERR_ARG, "initial state had rho <= 0, T <= 0 or non-finite values");
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(h[k])) return set_err(c, MRTFD_ERR_NONFINITE, "sum %d is not finite", k);
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_time(mrtfd_ctx *c, int64_t *step, double *t)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    if (step) *step = c->step;
+    if (t) *t = (double)c->step * c->p.dt;
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_set_step(mrtfd_ctx *c, int64_t step)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    if (step < 0) return set_err(c, MRTFD_ERR_ARG, "step must be >= 0");
+    HIPCHK(c, launch_counter_set(c->d_step, step, c->stream));
+    c->step = step;
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_kernel_time(mrtfd_ctx *c, int32_t n, double *ms)
+{
+    if (!c || !ms || n < 1) return MRTFD_ERR_ARG;
+    if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "kernel_time before init");
+    if (!c->kernel) {
+        int rc = autotune(c);
+        if (rc != MRTFD_OK) return rc;
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    hipError_t e = launch_step(c, c->f[c->cur], c->f[c->cur ^ 1], 0, c->stream);
+    e = e == hipSuccess ? hipEventRecord(e0, c->stream) : e;
+    for (int r = 0; r < n && e == hipSuccess; ++r)
+        e = launch_step(c, c->f[c->cur], c->f[c->cur ^ 1], 0, c->stream);
+    e = e == hipSuccess ? hipEventRecord(e1, c->stream) : e;
+    e = e == hipSuccess ? hipEventSynchronize(e1) : e;
+    float t = 0.f;
+    e = e == hipSuccess ? hipEventElapsedTime(&t, e0, e1) : e;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return set_err(c, MRTFD_ERR_HIP, "kernel_time: %s", hipGetErrorString(e));
+    *ms = (double)t / n;
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_kernel_info(mrtfd_ctx *c, int32_t *kernel, int32_t *rows)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    if (kernel) *kernel = c->kernel;
+    if (rows) *rows = c->seg;
+    return MRTFD_OK;
+}
+
+}  // extern "C"

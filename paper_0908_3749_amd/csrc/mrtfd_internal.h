@@ -1,0 +1,105 @@
+// Internal declarations shared by the host side (mrtfd_host.cpp) and the
+// kernels (mrtfd_kernels.hip) of the MRT finite-difference lattice Boltzmann
+// library.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mrtfd {
+
+constexpr int NQ = 16;
+
+// FP32 constants of one step.  The moment transform f-hat = M f is done in two
+// stages.  Stage 1, a butterfly of adds per velocity group g (4 velocities
+// each): A_g = sum of the group, X_g / Y_g = the combinations odd in v_x /
+// v_y, Q_g = the quadrupole combination.  Stage 2, small dense blocks that
+// mix the groups: every row of M is a radial weight times one angular
+// harmonic (Sect. III.A builds M from SO(2) irreducible representations), so
+// M = B P with P the butterfly and B block diagonal:
+//   harmonic 0 (m1, m4, m11, m12) <- A_0..3, cos (m2, m7, m9, m15) <- X_0..3,
+//   sin (m3, m8, m10, m16) <- Y_0..3, axis quadrupole (m5, m13) <- Q_0, Q_1,
+//   diagonal quadrupole (m6, m14) <- Q_2, Q_3.
+// The inverse is P^-1 B^-1 with the butterfly's 1/4 and 1/2 scales folded
+// into the rows of B^-1, so that the inverse butterfly is adds only.
+struct Consts {
+    float f0[4][4];   // rows m1, m4, m11, m12; columns A0..A3
+    float fx[4][4];   // rows m2, m7, m9, m15;  columns X0..X3
+    float fy[4][4];   // rows m3, m8, m10, m16; columns Y0..Y3
+    float fqa[2][2];  // rows m5, m13; columns Q0, Q1
+    float fqd[2][2];  // rows m6, m14; columns Q2, Q3
+    float i0[4][4];   // rows A'0..3; columns m1, m4, m11, m12 (scaled)
+    float ix[4][4];   // rows X'0..3; columns m2, m7, m9, m15
+    float iy[4][4];   // rows Y'0..3; columns m3, m8, m10, m16
+    float iqa[2][2];  // rows Q'0, Q'1; columns m5, m13
+    float iqd[2][2];  // rows Q'2, Q'3; columns m6, m14
+    // collision back-map: inverse blocks times dt*s_k (nonconserved columns)
+    float c0[4][2];   // columns m11, m12
+    float cx[4][3];   // columns m7, m9, m15
+    float cy[4][3];   // columns m8, m10, m16
+    float cqa[2][2];  // columns m5, m13
+    float cqd[2][2];  // columns m6, m14
+    // Lax-Wendroff + Euler weights per population: f + cE (fE - f) + cW (fW - f)
+    // + cN (fN - f) + cS (fS - f), cE = (a^2 - a)/2, cW = (a^2 + a)/2 with
+    // a = v_x dt / dx (likewise N/S with b = v_y dt / dy).
+    float lw[NQ][4];  // cE, cW, cN, cS
+};
+
+// Device layout of one copy of f: 16 planes, each (ny + 2) rows of `pitch`
+// floats.  Interior node (i, j) of population q sits at
+//   q * plane + (j + 1) * pitch + xoff + i,
+// ghost columns at i = -1 and i = nx, ghost rows at j = -1 and j = ny.
+// xoff = 64 keeps every interior row start 256-byte aligned.
+struct Field {
+    int nx, ny;
+    int pitch, xoff;
+    long long plane;
+    __host__ __device__ long long at(int q, int i, int j) const {
+        return (long long)q * plane + (long long)(j + 1) * pitch + xoff + i;
+    }
+};
+
+enum Kind { K_PERIODIC = 0, K_DIRICHLET = 1, K_REFLECT = 2, K_EXTRAPOLATE = 3, K_WALL = 4 };
+
+struct GhostSide {
+    int kind_lo, kind_hi;
+    float st_lo[4], st_hi[4];        // rho, u1, u2, T
+    float feq_lo[NQ], feq_hi[NQ];    // f^eq of the states (host FP64, rounded)
+    double split0, split_rate;       // rule switch point along the side
+    double h;                        // node spacing along the side
+};
+
+struct Ghosts {
+    GhostSide side[4];  // west, east, south, north
+    double dt;
+    int per_x, per_y;   // periodic in x (west/east) / in y (south/north)
+};
+
+// Launchers (mrtfd_kernels.hip).  All enqueue on `s` and return the HIP
+// status of the launch.
+hipError_t launch_init(const Field &F, const Consts &K, float *f, const float *rho,
+                       const float *ux, const float *uy, const float *T, int *flag,
+                       hipStream_t s);
+// One time step from fin to fout at step index *d_step + k (the boundary
+// rules read the clock from there).
+hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
+                              float *fout, const long long *d_step, int k, hipStream_t s);
+hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
+                            float *fout, int rows, const long long *d_step, int k, hipStream_t s);
+hipError_t launch_counter_add(long long *d_step, long long n, hipStream_t s);
+hipError_t launch_counter_set(long long *d_step, long long n, hipStream_t s);
+hipError_t launch_read_macro(const Field &F, const Consts &K, const float *f, float *rho,
+                             float *ux, float *uy, float *T, float *p, hipStream_t s);
+// FP64 weights of the conserved rows m1..m4 at the 16 velocities.
+struct SumW {
+    double w[4][NQ];
+};
+int sums_blocks(const Field &F);
+hipError_t launch_sums(const Field &F, const SumW &W, const float *f, double *partials,
+                       double *out, hipStream_t s);
+hipError_t launch_pack(const Field &F, const float *f, float *dst, hipStream_t s);
+hipError_t launch_unpack(const Field &F, const float *src, float *f, hipStream_t s);
+
+}  // namespace mrtfd

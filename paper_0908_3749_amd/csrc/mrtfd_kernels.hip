@@ -1,0 +1,719 @@
+// HIP kernels (gfx950) of the MRT finite-difference lattice Boltzmann step.
+//
+// Per interior node and time step (Sect. II-III, appendix):
+//   f-hat = M f; equilibria of the nonconserved moments (Eq. 14);
+//   dt*C = M^-1 (dt S-hat)(f-hat - f-hat^eq) (Eq. 3);
+//   f_new = f - dt [Lax-Wendroff difference of v.grad f] - dt*C (Eq. A.1a-b),
+// collision and stencil both on the old state.  FP32 throughout; FP64 only in
+// the conservation sums and in the time comparison that picks a boundary
+// rule.  All code is compiled with FMA contraction off: every fused
+// multiply-add below is written out, so every kernel variant rounds a node's
+// update identically and their results agree bit for bit.
+#include <type_traits>
+
+#include "mrtfd_internal.h"
+
+namespace mrtfd {
+namespace {
+
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// ---------------------------------------------------------------- transforms
+
+// Stage 1 of f-hat = M f for one velocity group (see Consts).
+template <bool AXIS>
+__device__ __forceinline__ void group_fwd(float q0, float q1, float q2, float q3, float &A,
+                                          float &X, float &Y, float &Q)
+{
+    const float s02 = q0 + q2, d02 = q0 - q2, s13 = q1 + q3, d13 = q1 - q3;
+    A = s02 + s13;
+    Q = s02 - s13;
+    if (AXIS) {  // (+,0),(0,+),(-,0),(0,-)
+        X = d02;
+        Y = d13;
+    } else {     // (+,+),(-,+),(-,-),(+,-)
+        X = d02 - d13;
+        Y = d02 + d13;
+    }
+}
+
+// Inverse butterfly of one group (scales already folded into A, X, Y, Q).
+template <bool AXIS>
+__device__ __forceinline__ void group_inv(float A, float X, float Y, float Q, float &q0, float &q1,
+                                          float &q2, float &q3)
+{
+    const float p = A + Q, m = A - Q;
+    if (AXIS) {
+        q0 = p + X;
+        q2 = p - X;
+        q1 = m + Y;
+        q3 = m - Y;
+    } else {
+        const float xy = X + Y, yx = Y - X;
+        q0 = p + xy;
+        q2 = p - xy;
+        q1 = m + yx;
+        q3 = m - yx;
+    }
+}
+
+__device__ __forceinline__ float dot4(const float (&w)[4], const float (&v)[4])
+{
+    return fma_(w[3], v[3], fma_(w[2], v[2], fma_(w[1], v[1], w[0] * v[0])));
+}
+
+__device__ __forceinline__ void butterflies(const float (&f)[NQ], float (&A)[4], float (&X)[4],
+                                            float (&Y)[4], float (&Q)[4])
+{
+    group_fwd<true>(f[0], f[1], f[2], f[3], A[0], X[0], Y[0], Q[0]);
+    group_fwd<true>(f[4], f[5], f[6], f[7], A[1], X[1], Y[1], Q[1]);
+    group_fwd<false>(f[8], f[9], f[10], f[11], A[2], X[2], Y[2], Q[2]);
+    group_fwd<false>(f[12], f[13], f[14], f[15], A[3], X[3], Y[3], Q[3]);
+}
+
+// All 16 moments, m[k] = f-hat_{k+1}.
+__device__ __forceinline__ void moments(const Consts &K, const float (&f)[NQ], float (&m)[NQ])
+{
+    float A[4], X[4], Y[4], Q[4];
+    butterflies(f, A, X, Y, Q);
+    m[0] = dot4(K.f0[0], A);
+    m[3] = dot4(K.f0[1], A);
+    m[10] = dot4(K.f0[2], A);
+    m[11] = dot4(K.f0[3], A);
+    m[1] = dot4(K.fx[0], X);
+    m[6] = dot4(K.fx[1], X);
+    m[8] = dot4(K.fx[2], X);
+    m[14] = dot4(K.fx[3], X);
+    m[2] = dot4(K.fy[0], Y);
+    m[7] = dot4(K.fy[1], Y);
+    m[9] = dot4(K.fy[2], Y);
+    m[15] = dot4(K.fy[3], Y);
+    m[4] = fma_(K.fqa[0][1], Q[1], K.fqa[0][0] * Q[0]);
+    m[12] = fma_(K.fqa[1][1], Q[1], K.fqa[1][0] * Q[0]);
+    m[5] = fma_(K.fqd[0][1], Q[3], K.fqd[0][0] * Q[2]);
+    m[13] = fma_(K.fqd[1][1], Q[3], K.fqd[1][0] * Q[2]);
+}
+
+// Conserved moments only: rho, j_x, j_y, e.
+__device__ __forceinline__ void conserved(const Consts &K, const float (&f)[NQ], float &rho,
+                                          float &jx, float &jy, float &e)
+{
+    float A[4], X[4], Y[4], Q[4];
+    butterflies(f, A, X, Y, Q);
+    rho = dot4(K.f0[0], A);
+    e = dot4(K.f0[1], A);
+    jx = dot4(K.fx[0], X);
+    jy = dot4(K.fy[0], Y);
+}
+
+// Equilibria of the nonconserved moments, Eq. (14a)-(14i), written with
+// u = j / rho; moments 12, 15, 16 have zero equilibrium.  P = e - |j|^2/(2 rho).
+struct Eq {
+    float e5, e6, e7, e8, e9, e10, e11, e13, e14;
+};
+
+__device__ __forceinline__ Eq equilibria(float rho, float jx, float jy, float e)
+{
+    Eq q;
+    const float r = 1.0f / rho;  // IEEE division
+    const float ux = jx * r, uy = jy * r;
+    const float jux = jx * ux, juy = jy * uy;
+    const float P = fma_(-0.5f, jux + juy, e);
+    const float h = e + P;
+    const float uxx = ux * ux, uyy = uy * uy;
+    const float u2 = uxx + uyy;
+    q.e5 = jux - juy;                                 // (jx^2 - jy^2) / rho
+    q.e6 = jx * uy;                                   // jx jy / rho
+    q.e7 = h * ux;                                    // (e + P) jx / rho
+    q.e8 = h * uy;                                    // (e + P) jy / rho
+    q.e9 = fma_(-3.0f, uyy, uxx) * jx;                // (jx^2 - 3 jy^2) jx / rho^2
+    q.e10 = fma_(3.0f, uxx, -uyy) * jy;               // (3 jx^2 - jy^2) jy / rho^2
+    const float er = e * r;
+    q.e11 = fma_(2.0f * e, er, (-0.25f * rho) * (u2 * u2));  // 2 e^2/rho - |j|^4/(4 rho^3)
+    const float kap = fma_(6.0f, er, -2.0f * u2);    // (6 rho e - 2 |j|^2) / rho^2
+    q.e13 = kap * q.e5;
+    q.e14 = kap * q.e6;
+    return q;
+}
+
+// dC = dt * C of Eq. (3) for one node.
+__device__ __forceinline__ void collide(const Consts &K, const float (&f)[NQ], float (&dC)[NQ])
+{
+    float m[NQ];
+    moments(K, f, m);
+    const Eq q = equilibria(m[0], m[1], m[2], m[3]);
+    const float d5 = m[4] - q.e5, d6 = m[5] - q.e6, d7 = m[6] - q.e7, d8 = m[7] - q.e8;
+    const float d9 = m[8] - q.e9, d10 = m[9] - q.e10, d11 = m[10] - q.e11, d12 = m[11];
+    const float d13 = m[12] - q.e13, d14 = m[13] - q.e14, d15 = m[14], d16 = m[15];
+    float A[4], X[4], Y[4], Q[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        A[g] = fma_(K.c0[g][1], d12, K.c0[g][0] * d11);
+        X[g] = fma_(K.cx[g][2], d15, fma_(K.cx[g][1], d9, K.cx[g][0] * d7));
+        Y[g] = fma_(K.cy[g][2], d16, fma_(K.cy[g][1], d10, K.cy[g][0] * d8));
+    }
+    Q[0] = fma_(K.cqa[0][1], d13, K.cqa[0][0] * d5);
+    Q[1] = fma_(K.cqa[1][1], d13, K.cqa[1][0] * d5);
+    Q[2] = fma_(K.cqd[0][1], d14, K.cqd[0][0] * d6);
+    Q[3] = fma_(K.cqd[1][1], d14, K.cqd[1][0] * d6);
+    group_inv<true>(A[0], X[0], Y[0], Q[0], dC[0], dC[1], dC[2], dC[3]);
+    group_inv<true>(A[1], X[1], Y[1], Q[1], dC[4], dC[5], dC[6], dC[7]);
+    group_inv<false>(A[2], X[2], Y[2], Q[2], dC[8], dC[9], dC[10], dC[11]);
+    group_inv<false>(A[3], X[3], Y[3], Q[3], dC[12], dC[13], dC[14], dC[15]);
+}
+
+// f^eq = M^-1 f-hat^eq of a macroscopic state (initial and boundary nodes).
+__device__ __forceinline__ void feq_velocity(const Consts &K, float rho, float ux, float uy,
+                                             float T, float (&f)[NQ])
+{
+    const float jx = rho * ux, jy = rho * uy;
+    const float e = rho * fma_(0.5f, fma_(ux, ux, uy * uy), T);
+    const Eq q = equilibria(rho, jx, jy, e);
+    const float h0[4] = {rho, e, q.e11, 0.0f};
+    const float hx[4] = {jx, q.e7, q.e9, 0.0f};
+    const float hy[4] = {jy, q.e8, q.e10, 0.0f};
+    float A[4], X[4], Y[4], Q[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        A[g] = dot4(K.i0[g], h0);
+        X[g] = dot4(K.ix[g], hx);
+        Y[g] = dot4(K.iy[g], hy);
+    }
+    Q[0] = fma_(K.iqa[0][1], q.e13, K.iqa[0][0] * q.e5);
+    Q[1] = fma_(K.iqa[1][1], q.e13, K.iqa[1][0] * q.e5);
+    Q[2] = fma_(K.iqd[0][1], q.e14, K.iqd[0][0] * q.e6);
+    Q[3] = fma_(K.iqd[1][1], q.e14, K.iqd[1][0] * q.e6);
+    group_inv<true>(A[0], X[0], Y[0], Q[0], f[0], f[1], f[2], f[3]);
+    group_inv<true>(A[1], X[1], Y[1], Q[1], f[4], f[5], f[6], f[7]);
+    group_inv<false>(A[2], X[2], Y[2], Q[2], f[8], f[9], f[10], f[11]);
+    group_inv<false>(A[3], X[3], Y[3], Q[3], f[12], f[13], f[14], f[15]);
+}
+
+// (rho, u1, u2, T) of one node.
+__device__ __forceinline__ void macro_of(const Consts &K, const float (&f)[NQ], float (&q)[4])
+{
+    float rho, jx, jy, e;
+    conserved(K, f, rho, jx, jy, e);
+    const float r = 1.0f / rho;
+    const float ux = jx * r, uy = jy * r;
+    const float P = fma_(-0.5f, jx * ux + jy * uy, e);
+    q[0] = rho;
+    q[1] = ux;
+    q[2] = uy;
+    q[3] = P * r;
+}
+
+// Which populations move along x / along y.
+__host__ __device__ constexpr bool has_x(int q) { return q >= 8 || (q % 2) == 0; }
+__host__ __device__ constexpr bool has_y(int q) { return q >= 8 || (q % 2) == 1; }
+
+// Lax-Wendroff + Euler update of population q (same operation order in every
+// kernel variant).
+template <int Q>
+__device__ __forceinline__ float lw_update(const Consts &K, float fc, float dC, float fE, float fW,
+                                           float fN, float fS)
+{
+    float r = fc - dC;
+    if (has_x(Q)) {
+        r = fma_(K.lw[Q][0], fE - fc, r);
+        r = fma_(K.lw[Q][1], fW - fc, r);
+    }
+    if (has_y(Q)) {
+        r = fma_(K.lw[Q][2], fN - fc, r);
+        r = fma_(K.lw[Q][3], fS - fc, r);
+    }
+    return r;
+}
+
+template <int Q>
+struct Unroll {
+    template <class F>
+    __device__ __forceinline__ static void run(F &&fn)
+    {
+        Unroll<Q - 1>::run(fn);
+        fn(std::integral_constant<int, Q - 1>());
+    }
+};
+template <>
+struct Unroll<0> {
+    template <class F>
+    __device__ __forceinline__ static void run(F &&)
+    {
+    }
+};
+
+// ------------------------------------------------------------ boundary nodes
+
+// Boundary nodes are never stored: a node next to a non-periodic side builds
+// the value of its missing neighbour when it needs it ("virtual ghost"), and a
+// periodic side is an index wrap.  The ghost node of side SD (0 west, 1 east,
+// 2 south, 3 north) at along-side index a carries f^eq of a macroscopic state
+// found by the side's rule (Sect. V) from n1, the boundary node itself, and n2,
+// the next node inward, at time t.  The rule switches from kind_lo to kind_hi
+// where the ghost's along-side coordinate passes split0 + split_rate t; that
+// comparison is done in FP64.
+template <int SD>
+__device__ __forceinline__ void ghost_of(const Consts &K, const Ghosts &G, double t, int a,
+                                         const float (&n1)[NQ], const float (&n2)[NQ],
+                                         float (&out)[NQ])
+{
+    const GhostSide &S = G.side[SD];
+    const double split = S.split0 + S.split_rate * t;
+    const bool lo = ((double)a + 0.5) * S.h <= split;
+    const int kind = lo ? S.kind_lo : S.kind_hi;
+    if (kind == K_DIRICHLET) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) out[q] = lo ? S.feq_lo[q] : S.feq_hi[q];
+        return;
+    }
+    float q1[4], st[4];
+    macro_of(K, n1, q1);
+    if (kind == K_REFLECT) {
+        st[0] = q1[0];
+        st[1] = SD < 2 ? -q1[1] : q1[1];
+        st[2] = SD < 2 ? q1[2] : -q1[2];
+        st[3] = q1[3];
+    } else if (kind == K_EXTRAPOLATE) {
+        float q2[4];
+        macro_of(K, n2, q2);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) st[c] = fma_(2.0f, q1[c], -q2[c]);
+        if (!(st[0] > 0.f) || !(st[3] > 0.f)) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) st[c] = q1[c];
+        }
+    } else {  // wall: density of the fluid, speed and temperature of the wall
+        st[0] = q1[0];
+        st[1] = lo ? S.st_lo[1] : S.st_hi[1];
+        st[2] = lo ? S.st_lo[2] : S.st_hi[2];
+        st[3] = lo ? S.st_lo[3] : S.st_hi[3];
+    }
+    feq_velocity(K, st[0], st[1], st[2], st[3], out);
+}
+
+// ------------------------------------------------------------ step kernels
+
+// Update of node (i, j) with its neighbours read from global memory, every
+// boundary rule handled.  The Lax-Wendroff terms are added in the order east,
+// west, north, south for every population, the order lw_update uses, so all
+// kernel variants agree bit for bit.
+__device__ __forceinline__ void node_update(const Field &F, const Consts &K, const Ghosts &G,
+                                            const float *__restrict__ fin,
+                                            float *__restrict__ fout, int i, int j, double t)
+{
+    const int nx = F.nx, ny = F.ny;
+    float fc[NQ], out[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) fc[q] = fin[F.at(q, i, j)];
+    {
+        float dC[NQ];
+        collide(K, fc, dC);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) out[q] = fc[q] - dC[q];
+    }
+    if (i == nx - 1 && !G.per_x) {
+        float n2[NQ], g[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) n2[q] = fin[F.at(q, i - 1, j)];
+        ghost_of<1>(K, G, t, j, fc, n2, g);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (has_x(q)) out[q] = fma_(K.lw[q][0], g[q] - fc[q], out[q]);
+    } else {
+        const int ie = i == nx - 1 ? 0 : i + 1;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (has_x(q)) out[q] = fma_(K.lw[q][0], fin[F.at(q, ie, j)] - fc[q], out[q]);
+    }
+    if (i == 0 && !G.per_x) {
+        float n2[NQ], g[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) n2[q] = fin[F.at(q, i + 1, j)];
+        ghost_of<0>(K, G, t, j, fc, n2, g);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (has_x(q)) out[q] = fma_(K.lw[q][1], g[q] - fc[q], out[q]);
+    } else {
+        const int iw = i == 0 ? nx - 1 : i - 1;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (has_x(q)) out[q] = fma_(K.lw[q][1], fin[F.at(q, iw, j)] - fc[q], out[q]);
+    }
+    if (j == ny - 1 && !G.per_y) {
+        float n2[NQ], g[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) n2[q] = fin[F.at(q, i, j - 1)];
+        ghost_of<3>(K, G, t, i, fc, n2, g);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (has_y(q)) out[q] = fma_(K.lw[q][2], g[q] - fc[q], out[q]);
+    } else {
+        const int jn = j == ny - 1 ? 0 : j + 1;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (has_y(q)) out[q] = fma_(K.lw[q][2], fin[F.at(q, i, jn)] - fc[q], out[q]);
+    }
+    if (j == 0 && !G.per_y) {
+        float n2[NQ], g[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) n2[q] = fin[F.at(q, i, j + 1)];
+        ghost_of<2>(K, G, t, i, fc, n2, g);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (has_y(q)) out[q] = fma_(K.lw[q][3], g[q] - fc[q], out[q]);
+    } else {
+        const int js = j == 0 ? ny - 1 : j - 1;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (has_y(q)) out[q] = fma_(K.lw[q][3], fin[F.at(q, i, js)] - fc[q], out[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) fout[F.at(q, i, j)] = out[q];
+}
+
+__device__ __forceinline__ double step_time(const Ghosts &G, const long long *d_step, int k)
+{
+    return (double)(*d_step + k) * G.dt;
+}
+
+// One thread per node, 64x4 nodes per block; neighbours read straight from
+// global memory (the caches absorb the re-reads).
+__global__ __launch_bounds__(256) void k_step_simple(Field F, Consts K, Ghosts G,
+                                                     const float *__restrict__ fin,
+                                                     float *__restrict__ fout,
+                                                     const long long *__restrict__ d_step, int k)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= F.nx || j >= F.ny) return;
+    node_update(F, K, G, fin, fout, i, j, step_time(G, d_step, k));
+}
+
+// Wavefront shifts across all 64 lanes (DPP wave_shr:1 / wave_shl:1, CDNA).
+// shr1: lane l takes v from lane l-1, lane 0 keeps `edge`.
+// shl1: lane l takes v from lane l+1, lane 63 keeps `edge`.
+__device__ __forceinline__ float shr1(float v, float edge)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float shl1(float v, float edge)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+
+// Buffer resource over one copy of f (raw buffer, byte offsets, 32-bit range
+// checked by the hardware: out-of-range loads return 0, stores are dropped).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const float *p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+
+// Row kernel.  Each wavefront updates R consecutive rows of 64 consecutive
+// columns; the four waves of a block take vertically adjacent row groups of
+// the same columns.  Rows y0-1 .. y0+R of the wave's columns are loaded once
+// (the rows above and below only for populations moving in y), all loads
+// issued before any arithmetic.  West/east neighbours come from the adjacent
+// lanes by DPP; the two columns just outside the wave come from one extra
+// load per population and row (lanes 0-31 read column x0-1, lanes 32-63
+// column x0+64, so lane 0 and lane 63 hold what they need).  Waves with a node
+// on a side of the grid take node_update, which knows the boundary rules; the
+// others have only interior neighbours.  Addressing is by buffer
+// instructions: one per-lane byte offset shared by all loads of a column, plus
+// a wave-uniform offset for (plane, row).
+template <int R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
+                 float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
+                 const long long *__restrict__ d_step, int k)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // Consecutive blocks land on different XCDs (round robin over 8); give
+    // each XCD a contiguous range of blocks so that neighbouring tiles, which
+    // share halo rows and columns, share an L2.
+    int b = blockIdx.x;
+    if ((nblocks & 7) == 0) b = (b & 7) * (nblocks >> 3) + (b >> 3);
+    const int col = b % ncol;
+    const int rg = (b / ncol) * 4 + wv;
+    if (rg >= nrg) return;
+    const int x0 = col * 64, y0 = rg * R, x = x0 + lane;
+    if (col == 0 || x0 + 64 >= F.nx || y0 == 0 || y0 + R >= F.ny) {
+        const double t = step_time(G, d_step, k);
+        if (x < F.nx) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (y0 + r < F.ny) node_update(F, K, G, fin, fout, x, y0 + r, t);
+        }
+        return;
+    }
+    const unsigned vo = 4u * (unsigned)(F.xoff + x);
+    const unsigned vh = 4u * (unsigned)(F.xoff + (lane < 32 ? x0 - 1 : x0 + 64));
+    const unsigned planeB = 4u * (unsigned)F.plane, pitchB = 4u * (unsigned)F.pitch;
+    const auto rin = buffer_of(fin, bytes);
+    const auto rout = buffer_of(fout, bytes);
+    // byte offset of row j (j = -1 .. ny) of plane q
+    auto row = [&](int q, int j) { return (unsigned)q * planeB + (unsigned)(j + 1) * pitchB; };
+
+    float v[R + 2][NQ], h[R][NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        v[0][q] = has_y(q) ? bload(rin, vo, row(q, y0 - 1)) : 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            v[r + 1][q] = bload(rin, vo, row(q, y0 + r));
+            h[r][q] = has_x(q) ? bload(rin, vh, row(q, y0 + r)) : 0.f;
+        }
+        v[R + 1][q] = has_y(q) ? bload(rin, vo, row(q, y0 + R)) : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float dC[NQ];
+        collide(K, v[r + 1], dC);
+        Unroll<NQ>::run([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            float fE = 0.f, fW = 0.f;
+            if (has_x(q)) {
+                fE = shl1(v[r + 1][q], h[r][q]);
+                fW = shr1(v[r + 1][q], h[r][q]);
+            }
+            const float o = lw_update<q>(K, v[r + 1][q], dC[q], fE, fW, v[r + 2][q], v[r][q]);
+            bstore(rout, o, vo, row(q, y0 + r));
+        });
+    }
+}
+
+// ------------------------------------------------------------ other kernels
+
+__global__ __launch_bounds__(256) void k_init(Field F, Consts K, float *__restrict__ f,
+                                              const float *__restrict__ rho,
+                                              const float *__restrict__ ux,
+                                              const float *__restrict__ uy,
+                                              const float *__restrict__ T, int *flag)
+{
+    const long long n = (long long)F.nx * F.ny;
+    const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (c >= n) return;
+    const int i = (int)(c % F.nx), j = (int)(c / F.nx);
+    const float r = rho[c], t = T[c];
+    if (!(r > 0.f) || !(t > 0.f) || !isfinite(ux[c]) || !isfinite(uy[c]) || !isfinite(r) ||
+        !isfinite(t))
+        atomicOr(flag, 1);
+    float fe[NQ];
+    feq_velocity(K, r, ux[c], uy[c], t, fe);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) f[F.at(q, i, j)] = fe[q];
+}
+
+__global__ void k_counter(long long *d_step, long long n, int set)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (set)
+            d_step[0] = n;
+        else
+            d_step[0] += n;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_read_macro(Field F, Consts K, const float *__restrict__ f,
+                                                    float *rho, float *ux, float *uy, float *T,
+                                                    float *p)
+{
+    const long long n = (long long)F.nx * F.ny;
+    const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (c >= n) return;
+    const int i = (int)(c % F.nx), j = (int)(c / F.nx);
+    float fc[NQ], q[4];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) fc[k] = f[F.at(k, i, j)];
+    macro_of(K, fc, q);
+    if (rho) rho[c] = q[0];
+    if (ux) ux[c] = q[1];
+    if (uy) uy[c] = q[2];
+    if (T) T[c] = q[3];
+    if (p) p[c] = q[0] * q[3];
+}
+
+constexpr int SUM_BLOCKS_MAX = 1024;
+
+// FP64 sums of rho, j_x, j_y, e.  Each thread walks a fixed set of nodes,
+// then a fixed-order tree reduction per block; a second kernel adds the block
+// partials in order.  The result is independent of timing.
+__global__ __launch_bounds__(256) void k_sums_partial(Field F, SumW W, const float *__restrict__ f,
+                                                      double *partials)
+{
+    __shared__ double sh[4][256];
+    const long long n = (long long)F.nx * F.ny;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < n;
+         c += (long long)gridDim.x * 256) {
+        const int i = (int)(c % F.nx), j = (int)(c / F.nx);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double v = (double)f[F.at(q, i, j)];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] += W.w[k][q] * v;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partials[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_sums_final(const double *__restrict__ partials, int nblk,
+                                                    double *out)
+{
+    __shared__ double sh[4][256];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += partials[b * 4 + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_pack(Field F, const float *__restrict__ f,
+                                              float *__restrict__ dst)
+{
+    const long long n = (long long)F.nx * F.ny;
+    const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int q = blockIdx.y;
+    if (c >= n) return;
+    const int i = (int)(c % F.nx), j = (int)(c / F.nx);
+    dst[(long long)q * n + c] = f[F.at(q, i, j)];
+}
+
+__global__ __launch_bounds__(256) void k_unpack(Field F, const float *__restrict__ src,
+                                                float *__restrict__ f)
+{
+    const long long n = (long long)F.nx * F.ny;
+    const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int q = blockIdx.y;
+    if (c >= n) return;
+    const int i = (int)(c % F.nx), j = (int)(c / F.nx);
+    f[F.at(q, i, j)] = src[(long long)q * n + c];
+}
+
+inline unsigned blocks_for(long long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_init(const Field &F, const Consts &K, float *f, const float *rho, const float *ux,
+                       const float *uy, const float *T, int *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init, dim3(blocks_for((long long)F.nx * F.ny, 256)), dim3(256), 0, s, F,
+                       K, f, rho, ux, uy, T, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
+                              float *fout, const long long *d_step, int k, hipStream_t s)
+{
+    dim3 grid(blocks_for(F.nx, 64), blocks_for(F.ny, 4));
+    hipLaunchKernelGGL(k_step_simple, grid, dim3(256), 0, s, F, K, G, fin, fout, d_step, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
+                            float *fout, int rows, const long long *d_step, int k, hipStream_t s)
+{
+    const int ncol = (F.nx + 63) / 64;
+    const int nrg = (F.ny + rows - 1) / rows;
+    const int nb = ncol * ((nrg + 3) / 4);
+    const long long total = 4LL * NQ * F.plane;
+    if (total >= (1LL << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
+    const unsigned bytes = (unsigned)total;
+    switch (rows) {
+#define MRTFD_ROWS(Rr)                                                                             \
+    case Rr:                                                                                       \
+        hipLaunchKernelGGL(k_step_rows<Rr>, dim3(nb), dim3(256), 0, s, F, K, G, fin, fout, bytes,  \
+                           ncol, nrg, nb, d_step, k);                                              \
+        break;
+        MRTFD_ROWS(1)
+        MRTFD_ROWS(2)
+#undef MRTFD_ROWS
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_counter_add(long long *d_step, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, s, d_step, n, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_counter_set(long long *d_step, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, s, d_step, n, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_read_macro(const Field &F, const Consts &K, const float *f, float *rho,
+                             float *ux, float *uy, float *T, float *p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_read_macro, dim3(blocks_for((long long)F.nx * F.ny, 256)), dim3(256), 0,
+                       s, F, K, f, rho, ux, uy, T, p);
+    return hipGetLastError();
+}
+
+int sums_blocks(const Field &F)
+{
+    const long long n = (long long)F.nx * F.ny;
+    long long b = (n + 255) / 256;
+    return (int)(b < SUM_BLOCKS_MAX ? b : SUM_BLOCKS_MAX);
+}
+
+hipError_t launch_sums(const Field &F, const SumW &W, const float *f, double *partials,
+                       double *out, hipStream_t s)
+{
+    const int nb = sums_blocks(F);
+    hipLaunchKernelGGL(k_sums_partial, dim3(nb), dim3(256), 0, s, F, W, f, partials);
+    hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const Field &F, const float *f, float *dst, hipStream_t s)
+{
+    dim3 grid(blocks_for((long long)F.nx * F.ny, 256), NQ);
+    hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, s, F, f, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Field &F, const float *src, float *f, hipStream_t s)
+{
+    dim3 grid(blocks_for((long long)F.nx * F.ny, 256), NQ);
+    hipLaunchKernelGGL(k_unpack, grid, dim3(256), 0, s, F, src, f);
+    return hipGetLastError();
+}
+
+}  // namespace mrtfd

@@ -1,0 +1,170 @@
+"""Thin Python front end of libmrtfd: torch provides device memory and the
+stream; every step of the computation runs in the library's HIP kernels."""
+import ctypes as C
+import math
+
+import numpy as np
+
+from . import _abi
+from ._abi import check, lib
+
+SIDES = ("west", "east", "south", "north")
+KERNELS = {"auto": _abi.MRTFD_KERNEL_AUTO, "simple": _abi.MRTFD_KERNEL_SIMPLE,
+           "rows": _abi.MRTFD_KERNEL_ROWS}
+PRECISIONS = {"fp32": _abi.MRTFD_FP32, "bf16x3": _abi.MRTFD_BF16X3}
+
+
+def make_params(nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto", rows=0,
+                graph_steps=0):
+    """Fill the C parameter struct.  sides: dict west/east/south/north of
+    dicts with kind_lo, kind_hi (rule names), state_lo, state_hi
+    (rho, u1, u2, T), split0, split_rate."""
+    p = _abi.mrtfd_params()
+    p.nx, p.ny = int(nx), int(ny)
+    p.dx, p.dy, p.dt = float(dx), float(dy), float(dt)
+    if len(s) != 16:
+        raise ValueError("s must hold the 16 rates s_1..s_16")
+    for k in range(16):
+        p.s[k] = float(s[k])
+    for k, name in enumerate(SIDES):
+        sd = sides[name]
+        p.side[k].kind_lo = _abi.BC_KINDS[sd["kind_lo"]]
+        p.side[k].kind_hi = _abi.BC_KINDS[sd["kind_hi"]]
+        for q in range(4):
+            p.side[k].state_lo[q] = float(sd["state_lo"][q])
+            p.side[k].state_hi[q] = float(sd["state_hi"][q])
+        p.side[k].split0 = float(sd.get("split0", math.inf))
+        p.side[k].split_rate = float(sd.get("split_rate", 0.0))
+    p.precision = PRECISIONS[precision]
+    p.kernel = KERNELS[kernel]
+    p.rows = int(rows)
+    p.graph_steps = int(graph_steps)
+    return p
+
+
+def check_params(p):
+    """(status, message) of the library's validation; needs no GPU."""
+    buf = C.create_string_buffer(256)
+    st = lib().mrtfd_check_params(C.byref(p), buf, len(buf))
+    return st, buf.value.decode()
+
+
+class MRT2D:
+    """One 2D grid on one GPU."""
+
+    def __init__(self, nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto",
+                 rows=0, graph_steps=0, device=None, stream=None):
+        import torch
+
+        self.torch = torch
+        self.p = make_params(nx, ny, dx, dy, dt, s, sides, precision, kernel, rows, graph_steps)
+        st, msg = check_params(self.p)
+        if st != _abi.MRTFD_OK:
+            raise _abi.MrtfdError(st, msg)
+        self.nx, self.ny = int(nx), int(ny)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = lib().mrtfd_workspace_bytes(C.byref(self.p))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().mrtfd_create(C.byref(self.p), C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(self._ctx)))
+        self._keep = []
+
+    @classmethod
+    def from_problem(cls, problem, **kw):
+        """Build from any object with nx, ny, dx, dy, dt, s and sides
+        attributes (the seeded problem descriptions used by tests/bench)."""
+        return cls(problem.nx, problem.ny, problem.dx, problem.dy, problem.dt, problem.s,
+                   problem.sides, **kw)
+
+    # ------------------------------------------------------------ helpers
+    def _dev(self, a):
+        t = self.torch
+        if isinstance(a, np.ndarray):
+            a = t.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
+        a = a.to(device=self.device, dtype=t.float32).contiguous()
+        return a
+
+    def _ptr(self, a):
+        return C.c_void_p(a.data_ptr()) if a is not None else None
+
+    # ------------------------------------------------------------- C ABI
+    def init_macro(self, rho, ux, uy, T):
+        arrs = [self._dev(a).reshape(self.ny, self.nx) for a in (rho, ux, uy, T)]
+        self._keep = arrs
+        check(lib().mrtfd_init_macro(self._ctx, *[self._ptr(a) for a in arrs]), self._ctx)
+
+    def init_problem(self, problem):
+        ic = problem.ic
+        self.init_macro(ic["rho"], ic["ux"], ic["uy"], ic["T"])
+
+    def step(self, nsteps=1):
+        check(lib().mrtfd_step(self._ctx, int(nsteps)), self._ctx)
+
+    def read_macro(self):
+        t = self.torch
+        out = {k: t.empty((self.ny, self.nx), dtype=t.float32, device=self.device)
+               for k in ("rho", "ux", "uy", "T", "p")}
+        check(lib().mrtfd_read_macro(self._ctx, *[self._ptr(out[k]) for k in ("rho", "ux", "uy", "T", "p")]),
+              self._ctx)
+        return out
+
+    def macro_numpy(self):
+        out = self.read_macro()
+        self.stream.synchronize()
+        return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+
+    def sums(self):
+        out = (C.c_double * 4)()
+        check(lib().mrtfd_sums(self._ctx, out), self._ctx)
+        return np.array(out[:])
+
+    def get_f(self):
+        t = self.torch
+        f = t.empty((16, self.ny, self.nx), dtype=t.float32, device=self.device)
+        check(lib().mrtfd_get_f(self._ctx, self._ptr(f)), self._ctx)
+        return f
+
+    def get_f_numpy(self):
+        f = self.get_f()
+        self.stream.synchronize()
+        return f.cpu().numpy()
+
+    def set_f(self, f):
+        a = self._dev(f).reshape(16, self.ny, self.nx)
+        self._keep = [a]
+        check(lib().mrtfd_set_f(self._ctx, self._ptr(a)), self._ctx)
+
+    def time(self):
+        step = C.c_int64()
+        t = C.c_double()
+        check(lib().mrtfd_time(self._ctx, C.byref(step), C.byref(t)), self._ctx)
+        return step.value, t.value
+
+    def set_step(self, step):
+        check(lib().mrtfd_set_step(self._ctx, int(step)), self._ctx)
+
+    def kernel_info(self):
+        k = C.c_int32()
+        s = C.c_int32()
+        check(lib().mrtfd_kernel_info(self._ctx, C.byref(k), C.byref(s)), self._ctx)
+        return {1: "simple", 2: "rows"}.get(k.value, "none"), s.value
+
+    def kernel_time(self, nlaunch=20):
+        """Average milliseconds per launch of the step kernel alone."""
+        ms = C.c_double()
+        check(lib().mrtfd_kernel_time(self._ctx, int(nlaunch), C.byref(ms)), self._ctx)
+        return ms.value
+
+    def close(self):
+        if self._ctx:
+            lib().mrtfd_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

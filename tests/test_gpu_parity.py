@@ -1,0 +1,323 @@
+"""GPU parity: the HIP step (through the C ABI) against the FP64 oracle on the
+same seeded inputs, plus properties that hold at any size.
+
+Tolerances (FP32 arithmetic against an FP64 reference):
+* one step from arbitrary positive populations: |f_gpu - f_oracle| <=
+  2e-6 max|f|.  A node's update is a chain of about 30 FP32 roundings
+  (butterflies, 4x4 blocks, equilibria, back-map, stencil), each <= 2^-24 of
+  a partial result no larger than a few max|f|: 30 * 6e-8 * ~1 ~ 2e-6.
+* many steps of smooth flow: relative L1 <= 1e-5 on rho, u, p (the stated
+  accuracy target for smooth flow).
+* shocks: the density midpoint crossing within one cell of the oracle's.
+* different kernel variants, graph replay, restart: bit for bit equal.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import core, metrics
+
+pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+RATES = synth.rates(1e-5, s5=500, s6=700, s7=1000, s8=1100, s11=2500)
+VARIANTS = [("simple", 0), ("rows", 1), ("rows", 2)]
+
+SIDE_SETS = {
+    "periodic": {k: synth.side("periodic") for k in synth.SIDES},
+    "dirichlet": {"west": synth.side("dirichlet", (1.0, 0.1, 0.0, 1.0)),
+                  "east": synth.side("dirichlet", (0.5, 0.0, 0.1, 0.8)),
+                  "south": synth.side("periodic"), "north": synth.side("periodic")},
+    "reflect_extrapolate": {"west": synth.side("extrapolate"), "east": synth.side("extrapolate"),
+                            "south": synth.side("reflect"), "north": synth.side("reflect")},
+    "wall_split": {"west": synth.side("periodic"), "east": synth.side("periodic"),
+                   "south": synth.side("wall", (1.0, 0.0, 0.0, 1.0)),
+                   "north": synth.split_side("dirichlet", (2.0, 0.3, -0.2, 1.5), "extrapolate",
+                                             (1.0, 0.0, 0.0, 1.0), 0.2, 5.0)},
+}
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0908_3749_amd import MRT2D
+    torch.cuda.set_device(0)
+    return MRT2D
+
+
+def run_gpu(MRT2D, prob, f0=None, nsteps=1, **kw):
+    g = MRT2D.from_problem(prob, **kw)
+    if f0 is None:
+        g.init_problem(prob)
+    else:
+        g.set_f(f0)
+    g.step(nsteps)
+    f = g.get_f_numpy()
+    mac = g.macro_numpy()
+    info = g.kernel_info()
+    g.close()
+    return f, mac, info
+
+
+def run_oracle(prob, f0=None, nsteps=1):
+    o = core.Grid(prob, nthreads=THREADS)
+    if f0 is None:
+        o.init_problem()
+    else:
+        o.set_f(f0)
+    o.run(nsteps)
+    return o.get_f(), o.macro()
+
+
+@pytest.mark.parametrize("sides", sorted(SIDE_SETS))
+def test_one_step_matches_oracle_every_variant(gpu, sides):
+    """Arbitrary positive populations on a ragged 150x37 grid (several
+    64-column strips plus a tail), one step, each boundary rule set, every
+    kernel variant; and all variants agree bit for bit."""
+    nx, ny = 150, 37
+    f0 = synth.random_populations(nx, ny, seed=1)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS[sides], None)
+    want, _ = run_oracle(prob, f0, 1)
+    outs = []
+    for kern, seg in VARIANTS:
+        got, _, info = run_gpu(gpu, prob, f0, 1, kernel=kern, rows=seg)
+        assert info == (kern, seg)
+        err = np.max(np.abs(got - want))
+        assert err <= 2e-6 * np.max(np.abs(want)), (kern, seg, err)
+        outs.append(got)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("sides", ["periodic", "reflect_extrapolate", "wall_split"])
+def test_smooth_flow_many_steps(gpu, sides):
+    nx, ny = 130, 70
+    ic = synth.smooth_macro(nx, ny, seed=3, du=0.2, dr=0.1)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS[sides], ic)
+    _, want = run_oracle(prob, None, 300)
+    _, got, _ = run_gpu(gpu, prob, None, 300)
+    for k in ("rho", "ux", "uy", "p"):
+        assert metrics.rel_l1(got[k], want[k]) <= 1e-5, k
+
+
+def test_sod_tube(gpu):
+    """The Sod configuration (400x4, 10k steps to t = 0.2) in FP32 against the
+    FP64 oracle: relative L1 <= 1e-5 on rho, u, p and the shock within one
+    cell."""
+    prob = synth.sod()
+    _, want = run_oracle(prob, None, prob.nsteps)
+    _, got, _ = run_gpu(gpu, prob, None, prob.nsteps)
+    for k in ("rho", "ux", "p"):
+        assert metrics.rel_l1(got[k], want[k]) <= 1e-5, (k, metrics.rel_l1(got[k], want[k]))
+    x = prob.x_centres()
+    lvl = 0.5 * (0.125 + 0.2043)
+    a = metrics.crossing(x, want["rho"][1], lvl, lo=0.8)
+    b = metrics.crossing(x, got["rho"][1], lvl, lo=0.8)
+    assert abs(a - b) <= prob.dx
+
+
+def test_uniform_flow_stays_bitwise_uniform(gpu):
+    nx, ny = 100, 30
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"],
+                         synth.uniform_ic(nx, ny, 1.3, 0.4, -0.2, 0.9))
+    f, mac, _ = run_gpu(gpu, prob, None, 50)
+    assert np.all(f == f[:, :1, :1])
+    np.testing.assert_allclose(mac["rho"], 1.3, rtol=1e-6)
+    np.testing.assert_allclose(mac["ux"], 0.4, rtol=1e-5)
+
+
+def test_periodic_conservation_fp64_sums(gpu):
+    nx, ny = 200, 120
+    ic = synth.smooth_macro(nx, ny, seed=9, du=0.3, dr=0.2)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"], ic)
+    g = gpu.from_problem(prob)
+    g.init_problem(prob)
+    a = g.sums()
+    g.step(1000)
+    b = g.sums()
+    g.close()
+    o = core.Grid(prob, nthreads=THREADS)
+    o.init_problem()
+    ref = o.sums()
+    # FP64 sums of the FP32 state: the initial totals agree with the oracle
+    # to FP32 rounding of the initial state, and drift by FP32 round-off only
+    np.testing.assert_allclose(a, ref, rtol=1e-6, atol=1e-6 * abs(ref[0]))
+    drift = np.abs(b - a) / np.array([a[0], a[0], a[0], a[3]])
+    assert np.all(drift <= 2e-5), drift
+
+
+def test_graph_replay_equals_direct_launches(gpu):
+    nx, ny = 150, 37
+    f0 = synth.random_populations(nx, ny, seed=4)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["wall_split"], None)
+    direct, _, _ = run_gpu(gpu, prob, f0, 37, kernel="rows", rows=2)
+    graph, _, _ = run_gpu(gpu, prob, f0, 37, kernel="rows", rows=2, graph_steps=8)
+    assert np.array_equal(direct, graph)
+    # replays after eager work in between
+    g = gpu.from_problem(prob, kernel="rows", rows=2, graph_steps=4)
+    g.set_f(f0)
+    for n in (4, 9, 8, 16):
+        g.step(n)
+        g.sums()
+    got = g.get_f_numpy()
+    g.close()
+    ref, _, _ = run_gpu(gpu, prob, f0, 37, kernel="simple")
+    assert np.array_equal(got, ref)
+
+
+def test_restart_is_bitwise(gpu):
+    """Checkpoint/restart: 2N steps equal N steps, get_f, a fresh context
+    with set_f and the clock restored, N more steps -- bit for bit, with a
+    time-dependent boundary rule in play."""
+    nx, ny = 90, 40
+    ic = synth.smooth_macro(nx, ny, seed=5)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["wall_split"], ic)
+    full, _, _ = run_gpu(gpu, prob, None, 40)
+    g = gpu.from_problem(prob)
+    g.init_problem(prob)
+    g.step(20)
+    mid = g.get_f()
+    step, t = g.time()
+    g.close()
+    assert step == 20 and abs(t - 20 * prob.dt) < 1e-15
+    h = gpu.from_problem(prob)
+    h.set_f(mid)
+    h.set_step(step)
+    h.step(20)
+    again = h.get_f_numpy()
+    h.close()
+    assert np.array_equal(full, again)
+
+
+def test_error_paths(gpu):
+    from paper_0908_3749_amd import MrtfdError
+    from paper_0908_3749_amd import _abi
+    nx, ny = 40, 20
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"],
+                         synth.uniform_ic(nx, ny, 1.0, 0.0, 0.0, 1.0))
+    g = gpu.from_problem(prob)
+    with pytest.raises(MrtfdError) as e:
+        g.step(1)
+    assert e.value.status == _abi.MRTFD_ERR_STATE
+    bad = dict(prob.ic)
+    bad["rho"] = prob.ic["rho"].copy()
+    bad["rho"][3, 4] = -1.0
+    g.init_macro(bad["rho"], bad["ux"], bad["uy"], bad["T"])
+    with pytest.raises(MrtfdError) as e:
+        g.sums()
+    assert e.value.status == _abi.MRTFD_ERR_ARG
+    g.init_problem(prob)
+    g.sums()
+    f = g.get_f_numpy()
+    f[2, 5, 5] = np.nan
+    g.set_f(f)
+    g.step(3)
+    with pytest.raises(MrtfdError) as e:
+        g.sums()
+    assert e.value.status == _abi.MRTFD_ERR_NONFINITE
+    g.close()
+
+
+U32 = 2.0 ** -24  # FP32 unit roundoff
+
+
+@pytest.mark.parametrize("state", [(1.0, 0.0, 0.0, 1.0), (0.125, 0.3, -0.2, 0.8),
+                                   (2.4545, 2.177, -1.257, 4.753), (0.138, 0.0, 0.0, 7.246),
+                                   (1.28, -0.377, 0.0, 1.29)])
+def test_init_matches_oracle(gpu, state):
+    """f = M^-1 f-hat^eq(rho, u, T) evaluated in FP32: each population within
+    64 u of the magnitude sum_k |M^-1_ik| |f-hat^eq_k| that its evaluation
+    cancels (FP32 unit roundoff u = 2^-24; 64 covers the ~20 roundings of the
+    equilibria and the back-map)."""
+    nx, ny = 70, 5
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"],
+                         synth.uniform_ic(nx, ny, *state))
+    g = gpu.from_problem(prob)
+    g.init_problem(prob)
+    got = g.get_f_numpy()[:, 0, 0]
+    g.close()
+    m = core.model()
+    rho, ux, uy, T = state
+    fh = core.feq_moments(rho, rho * ux, rho * uy, rho * (T + 0.5 * (ux * ux + uy * uy)))
+    want = m.Minv @ fh
+    scale = np.abs(m.Minv) @ np.abs(fh)
+    ratio = np.abs(got - want) / (U32 * scale)
+    print(f"init {state}: max err / (u scale) = {ratio.max():.2f}")
+    assert np.all(ratio <= 64), ratio
+
+
+@pytest.mark.parametrize("config", ["mach3", "bubble"])
+def test_full_size_steps_match_oracle(gpu, config):
+    """At the benchmark's full sizes (2048x512 Mach reflection, 4096x1024
+    shock-bubble) and in its launch configuration (autotuned kernel, graph
+    of 64 steps): a few steps from the oracle's initial state (rounded to
+    FP32) agree with the whole-grid FP64 oracle node by node, within
+    8 u max|f| per step (the emulated FP32 node update errs by about 2 u
+    max|f|, the stored result by another 0.5 u)."""
+    prob = synth.mach_reflection() if config == "mach3" else synth.shock_bubble()
+    n = 4 if config == "mach3" else 2
+    o = core.Grid(prob, nthreads=THREADS)
+    o.init_problem()
+    f0 = o.get_f().astype(np.float32)
+    o.set_f(f0.astype(np.float64))
+    o.run(n)
+    want = o.get_f()
+    got, _, info = run_gpu(gpu, prob, f0, n, graph_steps=64)
+    err = np.max(np.abs(got - want))
+    bound = 8 * n * U32 * np.max(np.abs(want))
+    print(f"full size {config} {info}: max err {err:.3e}, bound {bound:.3e}")
+    assert err <= bound
+
+
+def _shock_x(prob, rho, row, lo, hi):
+    x = prob.x_centres()
+    r = rho[row]
+    level = 0.5 * (np.max(r[(x >= lo) & (x <= hi)]) + np.min(r[(x >= lo) & (x <= hi)]))
+    return metrics.crossing(x, r, level, lo=lo, hi=hi)
+
+
+def test_mach_reflection_crop(gpu):
+    """The 256x64 crop of the Mach-3 reflection (same dx, dt, rates and
+    rules), 1000 steps.  Shock flow at T up to 4.75, where populations reach
+    20 and FP32 rounding of f alone is 1e-6 per step: relative L1 <= 1e-4,
+    and the incident shock crossing every row within one cell of the oracle."""
+    prob = synth.mach_reflection(nx=256, ny=64, x0_cells=64)
+    _, want = run_oracle(prob, None, 1000)
+    _, got, _ = run_gpu(gpu, prob, None, 1000)
+    errs = {k: metrics.rel_l1(got[k], want[k]) for k in ("rho", "ux", "uy", "p")}
+    print("mach3 crop 1000 steps rel L1", errs)
+    for k, v in errs.items():
+        assert v <= 1e-4, (k, v)
+    for row in range(0, 64, 8):
+        a = _shock_x(prob, want["rho"], row, 0.2, 0.77)
+        b = _shock_x(prob, got["rho"], row, 0.2, 0.77)
+        assert a is not None and abs(a - b) <= prob.dx, (row, a, b)
+
+
+def test_shock_bubble_scaled(gpu):
+    prob = synth.shock_bubble(nx=512, ny=128)
+    _, want = run_oracle(prob, None, 300)
+    _, got, _ = run_gpu(gpu, prob, None, 300)
+    errs = {k: metrics.rel_l1(got[k], want[k]) for k in ("rho", "ux", "uy", "p")}
+    print("bubble 512x128 300 steps rel L1", errs)
+    for k in ("rho", "p"):
+        assert errs[k] <= 1e-5, (k, errs[k])
+
+
+def test_couette_strip(gpu):
+    """Couette strip (walls at rest and at U = 0.1, seeded 1e-3 noise),
+    1000 steps: rho and p within 1e-5 relative L1 (smooth flow); u, whose
+    noise part is 1e-3, within 1e-5 U node by node."""
+    prob = synth.couette(nx=16, ny=256, noise=1e-3)
+    _, want = run_oracle(prob, None, 1000)
+    _, got, _ = run_gpu(gpu, prob, None, 1000)
+    errs = {k: metrics.rel_l1(got[k], want[k]) for k in ("rho", "ux", "uy", "p")}
+    print("couette 16x256 1000 steps rel L1", errs, "u Linf", metrics.linf(got["ux"], want["ux"]))
+    for k in ("rho", "p"):
+        assert errs[k] <= 1e-5, (k, errs[k])
+    assert metrics.linf(got["ux"], want["ux"]) <= 1e-6
+    assert metrics.linf(got["uy"], want["uy"]) <= 1e-6
