@@ -24,6 +24,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS and % of HBM roofline (FP32 vs mixed vs batched) at stated L1 error"
 HBM_PEAK_GBS = 8000.0
+# VALU ceiling of the node update: 256 CUs x 64 FP32 lanes x 2.4 GHz over
+# about 330 operations per node update (factored transform, no packed math)
+ALU_NODE_RATE = 256 * 64 * 2.4e9 / 330
 BYTES_PER_UPDATE = 128  # 16 FP32 populations read + 16 written
 KERNEL_SRC = os.path.join(ROOT, "paper_0908_3749_amd", "csrc", "mrtfd_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
@@ -40,7 +43,108 @@ def workloads():
         "couette": dict(name="couette_8192x2048", make=lambda: synth.couette(),
                         crop=lambda: synth.couette(x_window=(0, 16)), steps=50000),
         "sod": dict(name="sod_400x4", make=lambda: synth.sod(), crop=lambda: synth.sod(), steps=10000),
+        "tubes": dict(name="tube_batch_512", make=None, crop=None, steps=None),
     }
+
+
+def tube_star(L, R):
+    from oracle import riemann
+
+    W = riemann.wave_speeds(L, R)
+    return riemann.max_signal_speed(L, R), min(W["rho_star_left"], W["rho_star_right"])
+
+
+def bench_tubes(args):
+    """512 seeded tubes in one batch (temporally blocked rounds), against the
+    same tubes run one after another through the single-grid path (a sample,
+    extrapolated by node updates), and the oracle on the smallest tubes."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0908_3749_amd import MRT2D, TubeBatch
+
+    batch = synth.tube_batch(star_fn=tube_star)
+    tubes = batch["tubes"]
+    work = sum(4 * t["n"] * t["steps"] for t in tubes)
+    B = TubeBatch.from_description(batch, use_graph=not args.no_graph)
+    t0 = time.perf_counter()
+    B.init()
+    B.run()  # autotune, capture; also the warm-up
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    B.init()
+    torch.cuda.synchronize()
+    e0.record(B.stream)
+    B.run()
+    e1.record(B.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    seg, ks, rounds = B.info()
+    mlups = work / (ms * 1e-3) / 1e6
+    # separate single-grid runs of a sample of tubes (graph-replayed steps)
+    rng = np.random.default_rng(1)
+    sample = sorted(rng.choice(len(tubes), size=8, replace=False).tolist())
+    sep_ms, sep_work = 0.0, 0
+    for k in sample:
+        prob = synth.tube_problem(batch, k)
+        n_steps = min(prob.nsteps, 4000)
+        g = MRT2D.from_problem(prob, graph_steps=64)
+        g.init_problem(prob)
+        g.step(64)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(g.stream)
+        g.step(n_steps)
+        b.record(g.stream)
+        torch.cuda.synchronize()
+        sep_ms += a.elapsed_time(b)
+        sep_work += 4 * prob.nx * n_steps
+        g.close()
+    sep_mlups = sep_work / (sep_ms * 1e-3) / 1e6
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": int(max(t["steps"] for t in tubes)), "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tube_batch_512", "ntubes": len(tubes), "rows": 4,
+                   "node_updates": work, "seg_cols": seg, "round_steps": ks, "rounds": rounds,
+                   "graph": not args.no_graph, "gamma": 2.0},
+        "wall_ms": round(ms, 2), "setup_s": round(setup_s, 2),
+        "roofline": {"bound": "alu", "achieved": round(work / (ms * 1e-3) / 1e9, 2),
+                     "peak": round(ALU_NODE_RATE / 1e9, 1), "unit": "Gnode/s",
+                     "frac": round(work / (ms * 1e-3) / ALU_NODE_RATE, 4), "traffic": None},
+        "separate_launches": {"value": round(sep_mlups, 1), "unit": "MLUPS",
+                              "sample": f"tubes {sample}, up to 4000 steps each, single-grid path, graph of 64 steps",
+                              "speedup_batch": round(mlups / sep_mlups, 2)},
+    }
+    if not args.no_cpu:
+        from oracle import core, metrics
+
+        order = sorted(range(len(tubes)), key=lambda k: tubes[k]["n"] * tubes[k]["steps"])[:2]
+        threads = max(1, min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1, 16))
+        cpu_s, cpu_work, acc = 0.0, 0, {}
+        for k in order:
+            prob = synth.tube_problem(batch, k)
+            o = core.Grid(prob, nthreads=threads)
+            o.init_problem()
+            t0 = time.perf_counter()
+            o.run(prob.nsteps)
+            cpu_s += time.perf_counter() - t0
+            cpu_work += 4 * prob.nx * prob.nsteps
+            want = o.macro()
+            got = B.macro_numpy(k)
+            acc[f"tube{k}"] = {q: float(f"{metrics.rel_l1(got[q], want[q]):.3e}") for q in ("rho", "ux", "p")}
+        out["cpu_baseline"] = {"value": round(cpu_work / cpu_s / 1e6, 3), "unit": "MLUPS", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"tubes {order} (the two smallest), full run each, FP64, {cpu_s:.1f} s"}
+        out["accuracy"] = {"against": "FP64 oracle, same tubes", "rel_l1": acc}
+    B.close()
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def kernel_sha():
@@ -75,8 +179,10 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "simple", "rows"])
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--graph-steps", type=int, default=64)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
     ap.add_argument("--cpu-steps", type=int, default=12000, help="oracle steps on the crop")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--no-graph", action="store_true", help="tubes: launch rounds directly")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only time a plain device copy of MIB MiB (the reference for the HBM "
                          "byte counters and for achievable bandwidth) and exit")
@@ -116,12 +222,15 @@ def main():
         print(json.dumps({"copy_mib": args.calibrate_copy, "bytes_read": 4 * n, "bytes_written": 4 * n,
                           "ms": round(ms, 4), "gbs_read_plus_write": round(8 * n / ms / 1e6, 1)}), flush=True)
         return 0
+    if args.config == "tubes":
+        return bench_tubes(args)
     W = workloads()[args.config]
     prob = W["make"]()
     steps = args.steps if args.steps is not None else W["steps"]
     cells = prob.nx * prob.ny
 
-    g = MRT2D.from_problem(prob, kernel=args.kernel, rows=args.rows, graph_steps=args.graph_steps)
+    g = MRT2D.from_problem(prob, kernel=args.kernel, rows=args.rows, graph_steps=args.graph_steps,
+                           precision=args.precision)
     g.init_problem(prob)
     g.step(args.warmup)
     torch.cuda.synchronize()
@@ -155,9 +264,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else "bf16x3+f32",
         "data": "synthetic",
         "config": {"workload": W["name"], "nx": prob.nx, "ny": prob.ny, "dt": prob.dt,
+                   "precision": args.precision,
                    "kernel": kernel, "rows": seg, "graph_steps": args.graph_steps,
                    "gamma": 2.0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -175,7 +285,7 @@ def main():
 
         crop = W["crop"]()
         n_cpu = args.cpu_steps
-        gc = MRT2D.from_problem(crop, kernel=args.kernel, rows=args.rows)
+        gc = MRT2D.from_problem(crop, kernel=args.kernel, rows=args.rows, precision=args.precision)
         gc.init_problem(crop)
         gc.step(n_cpu)
         got = gc.macro_numpy()

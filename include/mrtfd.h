@@ -68,8 +68,10 @@ extern "C" {
 
 /* ---- arithmetic of the moment transforms ------------------------------- */
 #define MRTFD_FP32 0  /* FP32 everywhere (FP64 only in mrtfd_sums)            */
-#define MRTFD_BF16X3 1 /* transforms on MFMA, operands split hi/lo BF16, three
-                          products, FP32 accumulation                          */
+#define MRTFD_BF16X3 1 /* the two 16x16 transforms of the collision on the matrix
+                          cores, operands split into high and low BF16
+                          parts, three products, FP32 accumulation; the rest
+                          FP32 (nodes next to a side use the FP32 path)      */
 
 /* ---- kernel choice for the step ---------------------------------------- */
 #define MRTFD_KERNEL_AUTO 0   /* autotuned among the variants below            */
@@ -169,8 +171,9 @@ int32_t mrtfd_time(mrtfd_ctx *ctx, int64_t *step, double *t);
  * where they stopped. */
 int32_t mrtfd_set_step(mrtfd_ctx *ctx, int64_t step);
 
-/* The step kernel actually used (MRTFD_KERNEL_SIMPLE or _ROWS) and its rows
- * per wave, after autotuning (host outputs, may be NULL). */
+/* The step kernel actually used (MRTFD_KERNEL_SIMPLE, _ROWS, or 3 for the
+ * matrix-core kernel of MRTFD_BF16X3) and its rows per wave, after
+ * autotuning (host outputs, may be NULL). */
 int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows);
 
 /* Average duration in milliseconds of one launch of the step kernel alone
@@ -180,12 +183,75 @@ int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows);
  * overwrites, so the state is unchanged.  Synchronises the stream. */
 int32_t mrtfd_kernel_time(mrtfd_ctx *ctx, int32_t nlaunch, double *ms_per_launch);
 
+/* The library's FP64 model on the host: velocity set v[16][2] (Eq. 4), M
+ * [16][16] (Eq. 5, row-major, M[k][i] = m_{k+1}(v_i)) and its inverse, as
+ * used to build the kernels' constants.  Host arrays; any may be NULL. */
+int32_t mrtfd_model(double *v, double *M, double *Minv);
+
 /* sizeof(mrtfd_params) and sizeof(mrtfd_side) as compiled into the library,
  * so that language bindings can check their struct layouts. */
 int32_t mrtfd_struct_sizes(size_t *params_size, size_t *side_size);
 
 const char *mrtfd_status_string(int32_t status);
 const char *mrtfd_last_error(const mrtfd_ctx *ctx);
+
+/* ---- batches of independent shock tubes ----------------------------------
+ * Many one-dimensional Riemann problems (Sect. V.A) of different lengths run
+ * together.  Tube k has n[k] columns and 4 rows, periodic in y, and its two
+ * ends carry f = f^eq of its left / right state (as the paper sets its tube
+ * ends); its initial state is the left state for columns x < n[k]/2 and the
+ * right state beyond.  Every tube advances its own number of steps.  The
+ * work is split into items of seg_cols columns that advance round_steps
+ * steps per launch inside on-chip memory (temporal blocking); the launch of
+ * a round covers the items of all tubes still running.  Each node's update
+ * is the same arithmetic as the single-grid step, so tube k ends bit for bit
+ * where a single grid with the same parameters would. */
+typedef struct mrtfd_batch mrtfd_batch;
+
+typedef struct mrtfd_batch_params {
+    int32_t ntubes;      /* >= 1                                                */
+    double dx, dt;       /* node spacing (dx = dy) and time step, all tubes     */
+    double s[16];        /* relaxation rates as in mrtfd_params, all tubes      */
+    int32_t seg_cols;    /* columns per work item (64, 96, 112), 0 = autotune   */
+    int32_t round_steps; /* steps per round (8, 16), 0 = autotune              */
+    int32_t use_graph;   /* 1: replay all rounds as one captured HIP graph      */
+} mrtfd_batch_params;
+
+/* Device workspace bytes for a batch with tube lengths n[ntubes] (host
+ * array); 0 if the parameters are invalid. */
+size_t mrtfd_batch_workspace_bytes(const mrtfd_batch_params *p, const int32_t *n);
+
+/* Create a batch.  Host arrays: n[ntubes] (>= 3 columns), steps[ntubes]
+ * (>= 0), left[ntubes][4] and right[ntubes][4] = (rho, u1, u2, T) with
+ * rho > 0, T > 0.  d_workspace: caller-owned device buffer of
+ * mrtfd_batch_workspace_bytes bytes, 256-byte aligned.  stream as for
+ * mrtfd_create.  Validation as for mrtfd_params (dt s_k <= 1, 6 dt / dx <= 1). */
+int32_t mrtfd_batch_create(const mrtfd_batch_params *p, const int32_t *n, const int64_t *steps,
+                           const double *left, const double *right, void *d_workspace,
+                           size_t workspace_bytes, void *stream, mrtfd_batch **out);
+
+/* Set every tube to its initial Riemann state (step 0). */
+int32_t mrtfd_batch_init(mrtfd_batch *b);
+
+/* Advance every tube by its own number of steps (after mrtfd_batch_init;
+ * once per initialisation).  The first call on a batch shape autotunes
+ * seg_cols and round_steps unless given. */
+int32_t mrtfd_batch_run(mrtfd_batch *b);
+
+/* Macroscopic fields (device [4][n[tube]] FP32 arrays, any may be NULL) or
+ * the packed populations (device [16][4][n[tube]]) of one tube's current
+ * state. */
+int32_t mrtfd_batch_read_macro(mrtfd_batch *b, int32_t tube, float *d_rho, float *d_ux,
+                               float *d_uy, float *d_T, float *d_p);
+int32_t mrtfd_batch_get_f(mrtfd_batch *b, int32_t tube, float *d_f);
+
+/* Chosen work-item width, steps per round and number of rounds (host
+ * outputs, may be NULL). */
+int32_t mrtfd_batch_info(mrtfd_batch *b, int32_t *seg_cols, int32_t *round_steps,
+                         int32_t *rounds);
+
+int32_t mrtfd_batch_destroy(mrtfd_batch *b);
+const char *mrtfd_batch_last_error(const mrtfd_batch *b);
 
 #ifdef __cplusplus
 }

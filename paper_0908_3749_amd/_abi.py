@@ -43,6 +43,15 @@ class mrtfd_side(C.Structure):
     ]
 
 
+class mrtfd_batch_params(C.Structure):
+    _fields_ = [
+        ("ntubes", C.c_int32),
+        ("dx", C.c_double), ("dt", C.c_double),
+        ("s", C.c_double * 16),
+        ("seg_cols", C.c_int32), ("round_steps", C.c_int32), ("use_graph", C.c_int32),
+    ]
+
+
 class mrtfd_params(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32),
@@ -71,9 +80,22 @@ _PROTOS = {
     "mrtfd_set_step": (C.c_int32, [_vp, C.c_int64]),
     "mrtfd_kernel_info": (C.c_int32, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "mrtfd_kernel_time": (C.c_int32, [_vp, C.c_int32, C.POINTER(C.c_double)]),
+    "mrtfd_model": (C.c_int32, [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "mrtfd_struct_sizes": (C.c_int32, [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "mrtfd_status_string": (C.c_char_p, [C.c_int32]),
     "mrtfd_last_error": (C.c_char_p, [_vp]),
+    "mrtfd_batch_workspace_bytes": (C.c_size_t, [C.POINTER(mrtfd_batch_params), C.POINTER(C.c_int32)]),
+    "mrtfd_batch_create": (C.c_int32, [C.POINTER(mrtfd_batch_params), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "mrtfd_batch_init": (C.c_int32, [_vp]),
+    "mrtfd_batch_run": (C.c_int32, [_vp]),
+    "mrtfd_batch_read_macro": (C.c_int32, [_vp, C.c_int32, _fp, _fp, _fp, _fp, _fp]),
+    "mrtfd_batch_get_f": (C.c_int32, [_vp, C.c_int32, _fp]),
+    "mrtfd_batch_info": (C.c_int32, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32)]),
+    "mrtfd_batch_destroy": (C.c_int32, [_vp]),
+    "mrtfd_batch_last_error": (C.c_char_p, [_vp]),
 }
 
 _lib = None
@@ -107,11 +129,14 @@ class MrtfdError(RuntimeError):
         super().__init__(f"mrtfd status {status} ({name}){': ' + msg if msg else ''}")
 
 
-def check(status, ctx=None):
+def check(status, ctx=None, batch=None):
     if status != MRTFD_OK:
         msg = ""
         if ctx is not None:
             raw = lib().mrtfd_last_error(ctx)
+            msg = raw.decode() if raw else ""
+        elif batch is not None:
+            raw = lib().mrtfd_batch_last_error(batch)
             msg = raw.decode() if raw else ""
         raise MrtfdError(status, msg)
     return status

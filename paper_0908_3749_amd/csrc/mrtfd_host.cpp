@@ -276,6 +276,39 @@ void fill_consts(const Model &m, const mrtfd_params &p, Consts &K)
     }
 }
 
+// BF16 bits of an FP32 value, round to nearest even (as the kernels do).
+unsigned short bf16_of(float x)
+{
+    unsigned u;
+    std::memcpy(&u, &x, 4);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+double bf16_value(unsigned short b)
+{
+    const unsigned u = (unsigned)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// Split-BF16 A operands of the two transforms (lane layout of the 16x16x16
+// matrix instruction: lane l holds row l % 16, columns 4 (l/16) .. +3).
+void fill_mfma(const Model &m, const mrtfd_params &p, MfmaOperands &mo)
+{
+    std::memset(&mo, 0, sizeof mo);
+    for (int l = 0; l < 64; ++l)
+        for (int c = 0; c < 4; ++c) {
+            const int r = l % 16, k = 4 * (l / 16) + c;
+            const double a = m.M[r][k], b = m.Minv[r][k] * p.dt;
+            const unsigned short ah = bf16_of((float)a), bh = bf16_of((float)b);
+            mo.m_hi[l][c] = ah;
+            mo.m_lo[l][c] = bf16_of((float)(a - bf16_value(ah)));
+            mo.inv_hi[l][c] = bh;
+            mo.inv_lo[l][c] = bf16_of((float)(b - bf16_value(bh)));
+        }
+    for (int k = 0; k < NQ; ++k) mo.s[k] = k < 4 ? 0.f : (float)p.s[k];
+}
+
 // --------------------------------------------------------------- validation
 
 int check(const mrtfd_params *p, char *msg, size_t len)
@@ -306,8 +339,6 @@ int check(const mrtfd_params *p, char *msg, size_t len)
     if (cfl > 1.0) return fail(MRTFD_ERR_UNSTABLE, "Courant number 6 dt / min(dx,dy) = %g exceeds 1", cfl);
     if (p->precision != MRTFD_FP32 && p->precision != MRTFD_BF16X3)
         return fail(MRTFD_ERR_ARG, "unknown precision mode %d", p->precision);
-    if (p->precision == MRTFD_BF16X3)
-        return fail(MRTFD_ERR_UNSUPPORTED, "precision mode MRTFD_BF16X3 is not available in this build");
     if (p->kernel < MRTFD_KERNEL_AUTO || p->kernel > MRTFD_KERNEL_ROWS)
         return fail(MRTFD_ERR_ARG, "unknown kernel %d", p->kernel);
     if (p->rows != 0 && p->rows != 1 && p->rows != 2)
@@ -353,7 +384,7 @@ Field make_field(const mrtfd_params &p)
 }
 
 struct Layout {
-    size_t fA, fB, partials, sums, step, flag, total;
+    size_t fA, fB, partials, sums, step, flag, mfma, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -369,7 +400,8 @@ Layout layout(const mrtfd_params &p)
     L.sums = L.partials + align256(1024 * 4 * sizeof(double));
     L.step = L.sums + 256;
     L.flag = L.step + 256;
-    L.total = L.flag + 256;
+    L.mfma = L.flag + 256;
+    L.total = L.mfma + align256(sizeof(MfmaOperands));
     return L;
 }
 
@@ -398,6 +430,8 @@ struct mrtfd_ctx {
     double *partials = nullptr, *sums = nullptr;
     long long *d_step = nullptr;
     int *d_flag = nullptr;
+    MfmaOperands *d_mfma = nullptr;
+    MfmaOperands h_mfma;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream used only to capture graphs
     int device = 0;
@@ -433,7 +467,9 @@ hipError_t launch_step(mrtfd_ctx *c, const float *fin, float *fout, int k, hipSt
 {
     if (c->kernel == MRTFD_KERNEL_SIMPLE)
         return launch_step_simple(c->F, c->K, c->G, fin, fout, c->d_step, k, s);
-    return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg, c->d_step, k, s);
+    if (c->kernel == MRTFD_KERNEL_ROWS)
+        return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg, c->d_step, k, s);
+    return launch_step_mfma(c->F, c->K, c->G, c->d_mfma, fin, fout, c->d_step, k, s);
 }
 
 // Enqueue n steps starting from copy `start`, then advance the device clock.
@@ -569,6 +605,16 @@ const char *mrtfd_status_string(int32_t s)
 
 const char *mrtfd_last_error(const mrtfd_ctx *c) { return c ? c->err : "no context"; }
 
+int32_t mrtfd_model(double *v, double *M, double *Minv)
+{
+    const Model &m = model();
+    if (!m.ok) return MRTFD_ERR_ARG;
+    if (v) std::memcpy(v, m.v, sizeof m.v);
+    if (M) std::memcpy(M, m.M, sizeof m.M);
+    if (Minv) std::memcpy(Minv, m.Minv, sizeof m.Minv);
+    return MRTFD_OK;
+}
+
 int32_t mrtfd_struct_sizes(size_t *params_size, size_t *side_size)
 {
     if (params_size) *params_size = sizeof(mrtfd_params);
@@ -619,6 +665,8 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     c->sums = reinterpret_cast<double *>(c->ws + L.sums);
     c->d_step = reinterpret_cast<long long *>(c->ws + L.step);
     c->d_flag = reinterpret_cast<int *>(c->ws + L.flag);
+    c->d_mfma = reinterpret_cast<MfmaOperands *>(c->ws + L.mfma);
+    fill_mfma(m, *p, c->h_mfma);
     c->stream = static_cast<hipStream_t>(stream);
     fill_consts(m, *p, c->K);
     for (int k = 0; k < 4; ++k)
@@ -655,8 +703,16 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         c->kernel = MRTFD_KERNEL_ROWS;
         c->seg = p->rows;
     }
+    if (p->precision == MRTFD_BF16X3) {
+        c->kernel = MRTFD_KERNEL_ROWS + 1;  // the matrix-core kernel (see launch_step)
+        c->seg = 1;
+    }
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_mfma, &c->h_mfma, sizeof(MfmaOperands), hipMemcpyHostToDevice,
+                           c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         delete c;
         return MRTFD_ERR_HIP;
@@ -814,5 +870,431 @@ int32_t mrtfd_kernel_info(mrtfd_ctx *c, int32_t *kernel, int32_t *rows)
     if (rows) *rows = c->seg;
     return MRTFD_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------ tube batches
+
+namespace {
+
+struct BatchLayout {
+    size_t fA, fB, tubes, states, items, total;
+    long long ncols;
+    size_t max_items;
+};
+
+const int kTubeSegs[] = {64, 96, 112};
+
+int batch_check(const mrtfd_batch_params *p, const int32_t *n, char *msg, size_t len)
+{
+    auto fail = [&](int code, const char *fmt, ...) {
+        if (msg && len) {
+            va_list ap;
+            va_start(ap, fmt);
+            std::vsnprintf(msg, len, fmt, ap);
+            va_end(ap);
+        }
+        return code;
+    };
+    if (!p || !n) return fail(MRTFD_ERR_ARG, "NULL argument");
+    if (p->ntubes < 1) return fail(MRTFD_ERR_ARG, "ntubes must be >= 1");
+    if (!(p->dx > 0) || !(p->dt > 0) || !std::isfinite(p->dx) || !std::isfinite(p->dt))
+        return fail(MRTFD_ERR_ARG, "dx and dt must be positive and finite");
+    for (int k = 4; k < NQ; ++k) {
+        if (!(p->s[k] >= 0) || !std::isfinite(p->s[k])) return fail(MRTFD_ERR_ARG, "bad s_%d", k + 1);
+        if (p->dt * p->s[k] > 1.0 + 1e-12)
+            return fail(MRTFD_ERR_UNSTABLE, "dt * s_%d = %g exceeds 1", k + 1, p->dt * p->s[k]);
+    }
+    if (6.0 * p->dt / p->dx > 1.0) return fail(MRTFD_ERR_UNSTABLE, "Courant number 6 dt / dx exceeds 1");
+    if (p->seg_cols && p->round_steps && !tubes_config_built(p->seg_cols, p->round_steps))
+        return fail(MRTFD_ERR_ARG, "seg_cols/round_steps pair not built");
+    if (p->seg_cols && p->seg_cols != 64 && p->seg_cols != 96 && p->seg_cols != 112)
+        return fail(MRTFD_ERR_ARG, "seg_cols must be 0, 64, 96 or 112");
+    if (p->round_steps && p->round_steps != 8 && p->round_steps != 16)
+        return fail(MRTFD_ERR_ARG, "round_steps must be 0, 8 or 16");
+    long long total = 0;
+    for (int k = 0; k < p->ntubes; ++k) {
+        if (n[k] < 3) return fail(MRTFD_ERR_ARG, "tube %d has %d < 3 columns", k, n[k]);
+        total += n[k];
+    }
+    if (4LL * NQ * TUBE_ROWS * total >= (1LL << 34)) return fail(MRTFD_ERR_ARG, "batch too large");
+    if (msg && len) msg[0] = 0;
+    return MRTFD_OK;
+}
+
+BatchLayout batch_layout(const mrtfd_batch_params *p, const int32_t *n)
+{
+    BatchLayout L;
+    L.ncols = 0;
+    L.max_items = 0;
+    for (int k = 0; k < p->ntubes; ++k) {
+        L.ncols += n[k];
+        L.max_items += (size_t)((n[k] + 63) / 64);
+    }
+    const size_t fbytes = align256((size_t)NQ * TUBE_ROWS * (size_t)L.ncols * sizeof(float));
+    L.fA = 0;
+    L.fB = fbytes;
+    L.tubes = 2 * fbytes;
+    L.states = L.tubes + align256((size_t)p->ntubes * sizeof(TubeInfo));
+    L.items = L.states + align256((size_t)p->ntubes * 8 * sizeof(float));
+    L.total = L.items + align256(L.max_items * sizeof(TubeItem));
+    return L;
+}
+
+}  // namespace
+
+struct mrtfd_batch {
+    mrtfd_batch_params p;
+    BatchLayout L;
+    TubeGrid TG;
+    Consts K;
+    std::vector<int> n, start, order;
+    std::vector<long long> steps;
+    std::vector<TubeInfo> info;
+    std::vector<float> states;
+    std::vector<TubeItem> items;      // for the chosen seg, tubes by decreasing steps
+    std::vector<int> round_items;     // items active in each round
+    std::vector<int> final_copy;      // copy holding each tube's state
+    char *ws = nullptr;
+    float *f[2] = {nullptr, nullptr};
+    TubeInfo *d_tubes = nullptr;
+    float *d_states = nullptr;
+    TubeItem *d_items = nullptr;
+    hipStream_t stream = nullptr, cap = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int seg = 0, ks = 0, max_n = 0;
+    bool initialised = false, done = false;
+    char err[512] = {0};
+};
+
+namespace {
+
+int bset_err(mrtfd_batch *b, int code, const char *fmt, ...)
+{
+    if (b) {
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(b->err, sizeof b->err, fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define BHIPCHK(b, expr)                                                                           \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return bset_err(b, MRTFD_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+// Items of all tubes (in order of decreasing step count) for a work-item
+// width; round_items[r] = number of leading items whose tube still runs in
+// round r.
+void build_items(mrtfd_batch *b, int seg, int ks, std::vector<TubeItem> &items,
+                 std::vector<int> &round_items)
+{
+    items.clear();
+    std::vector<size_t> first(b->order.size() + 1, 0);
+    for (size_t r = 0; r < b->order.size(); ++r) {
+        const int k = b->order[r];
+        first[r] = items.size();
+        for (int x0 = 0; x0 < b->n[k]; x0 += seg) items.push_back(TubeItem{k, x0});
+    }
+    first[b->order.size()] = items.size();
+    long long max_steps = b->order.empty() ? 0 : b->steps[b->order[0]];
+    const long long rounds = (max_steps + ks - 1) / ks;
+    round_items.assign((size_t)rounds, 0);
+    size_t t = b->order.size();  // tubes still running: a prefix of the order
+    for (long long r = 0; r < rounds; ++r) {
+        while (t > 0 && b->steps[b->order[t - 1]] <= r * ks) --t;
+        round_items[(size_t)r] = (int)first[t];
+    }
+}
+
+hipError_t enqueue_rounds(mrtfd_batch *b, hipStream_t s)
+{
+    const int R = (int)b->round_items.size();
+    for (int r = 0; r < R; ++r) {
+        hipError_t e = launch_tubes(b->TG, b->K, b->d_tubes, b->d_items, b->round_items[r], r,
+                                    b->seg, b->ks, b->f[r & 1], b->f[(r + 1) & 1], s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int batch_autotune(mrtfd_batch *b)
+{
+    if (b->seg && b->ks) return MRTFD_OK;
+    static std::mutex mu;
+    static std::map<std::vector<int>, std::pair<int, int>> cache;
+    std::vector<int> key(b->n);
+    for (long long v : b->steps) key.push_back((int)std::min<long long>(v, 1 << 30));
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            b->seg = it->second.first;
+            b->ks = it->second.second;
+            return MRTFD_OK;
+        }
+    }
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    double best = -1.0;
+    std::pair<int, int> pick{64, 8};
+    int rc = MRTFD_OK;
+    std::vector<std::vector<TubeItem>> keep;  // host sources of the async uploads
+    for (int seg : kTubeSegs) {
+        if (b->p.seg_cols && seg != b->p.seg_cols) continue;
+        for (int ks : {8, 16}) {
+            if (b->p.round_steps && ks != b->p.round_steps) continue;
+            if (!tubes_config_built(seg, ks)) continue;
+            keep.emplace_back();
+            std::vector<TubeItem> &items = keep.back();
+            std::vector<int> ri;
+            build_items(b, seg, ks, items, ri);
+            if (ri.empty() || ri[0] == 0) continue;
+            double work = 0.0;  // node updates in round 0
+            for (int k = 0; k < b->p.ntubes; ++k)
+                work += (double)b->n[k] * TUBE_ROWS * (double)std::min<long long>(ks, b->steps[k]);
+            hipError_t e = hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(TubeItem),
+                                          hipMemcpyHostToDevice, b->stream);
+            // trial round 0: reads copy 0, writes copy 1 (overwritten by the real run)
+            if (e == hipSuccess)
+                e = launch_tubes(b->TG, b->K, b->d_tubes, b->d_items, ri[0], 0, seg, ks, b->f[0], b->f[1],
+                                 b->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
+                e = launch_tubes(b->TG, b->K, b->d_tubes, b->d_items, ri[0], 0, seg, ks, b->f[0],
+                                 b->f[1], b->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = bset_err(b, MRTFD_ERR_HIP, "batch autotune: %s", hipGetErrorString(e));
+                break;
+            }
+            const double rate = 2.0 * work / std::max(1e-6, (double)ms);
+            if (rate > best) {
+                best = rate;
+                pick = {seg, ks};
+            }
+        }
+        if (rc != MRTFD_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->seg = pick.first;
+    b->ks = pick.second;
+    if (rc == MRTFD_OK) {
+        std::lock_guard<std::mutex> lk(mu);
+        cache[key] = pick;
+    }
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mrtfd_batch_workspace_bytes(const mrtfd_batch_params *p, const int32_t *n)
+{
+    try {
+        if (batch_check(p, n, nullptr, 0) != MRTFD_OK) return 0;
+        return batch_layout(p, n).total;
+    } catch (...) {
+        return 0;
+    }
+}
+
+int32_t mrtfd_batch_create(const mrtfd_batch_params *p, const int32_t *n, const int64_t *steps,
+                           const double *left, const double *right, void *d_ws, size_t ws_bytes,
+                           void *stream, mrtfd_batch **out)
+{
+    if (!out) return MRTFD_ERR_ARG;
+    *out = nullptr;
+    int rc = batch_check(p, n, nullptr, 0);
+    if (rc != MRTFD_OK) return rc;
+    if (!steps || !left || !right) return MRTFD_ERR_ARG;
+    for (int k = 0; k < p->ntubes; ++k) {
+        if (steps[k] < 0) return MRTFD_ERR_ARG;
+        for (const double *st : {left + 4 * k, right + 4 * k}) {
+            if (!(st[0] > 0) || !(st[3] > 0)) return MRTFD_ERR_ARG;
+            for (int c = 0; c < 4; ++c)
+                if (!std::isfinite(st[c])) return MRTFD_ERR_ARG;
+        }
+    }
+    const Model &m = model();
+    if (!m.ok) return MRTFD_ERR_ARG;
+    const BatchLayout L = batch_layout(p, n);
+    if (!d_ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(d_ws) & 255)) return MRTFD_ERR_ARG;
+    mrtfd_batch *b = new (std::nothrow) mrtfd_batch();
+    if (!b) return MRTFD_ERR_ARG;
+    try {
+        b->p = *p;
+        b->L = L;
+        b->ws = static_cast<char *>(d_ws);
+        b->f[0] = reinterpret_cast<float *>(b->ws + L.fA);
+        b->f[1] = reinterpret_cast<float *>(b->ws + L.fB);
+        b->d_tubes = reinterpret_cast<TubeInfo *>(b->ws + L.tubes);
+        b->d_states = reinterpret_cast<float *>(b->ws + L.states);
+        b->d_items = reinterpret_cast<TubeItem *>(b->ws + L.items);
+        b->stream = static_cast<hipStream_t>(stream);
+        b->TG.ncols = (int)L.ncols;
+        b->TG.plane = (long long)TUBE_ROWS * L.ncols;
+        // the step constants: same construction as a single grid with dx = dy
+        mrtfd_params gp;
+        std::memset(&gp, 0, sizeof gp);
+        gp.dx = gp.dy = p->dx;
+        gp.dt = p->dt;
+        for (int k = 0; k < NQ; ++k) gp.s[k] = p->s[k];
+        fill_consts(m, gp, b->K);
+        b->n.assign(n, n + p->ntubes);
+        b->steps.assign(steps, steps + p->ntubes);
+        b->start.resize(p->ntubes);
+        b->info.resize(p->ntubes);
+        b->states.resize((size_t)p->ntubes * 8);
+        long long acc = 0;
+        for (int k = 0; k < p->ntubes; ++k) {
+            b->start[k] = (int)acc;
+            acc += n[k];
+            b->max_n = std::max(b->max_n, n[k]);
+            TubeInfo &t = b->info[k];
+            std::memset(&t, 0, sizeof t);
+            t.n = n[k];
+            t.start = b->start[k];
+            t.steps = (int)std::min<long long>(steps[k], (long long)1 << 30);
+            double fe[NQ];
+            feq_host(m, left[4 * k], left[4 * k + 1], left[4 * k + 2], left[4 * k + 3], fe);
+            for (int q = 0; q < NQ; ++q) t.feq_left[q] = (float)fe[q];
+            feq_host(m, right[4 * k], right[4 * k + 1], right[4 * k + 2], right[4 * k + 3], fe);
+            for (int q = 0; q < NQ; ++q) t.feq_right[q] = (float)fe[q];
+            for (int c = 0; c < 4; ++c) {
+                b->states[8 * k + c] = (float)left[4 * k + c];
+                b->states[8 * k + 4 + c] = (float)right[4 * k + c];
+            }
+        }
+        b->order.resize(p->ntubes);
+        for (int k = 0; k < p->ntubes; ++k) b->order[k] = k;
+        std::stable_sort(b->order.begin(), b->order.end(),
+                         [&](int a, int c) { return b->steps[a] > b->steps[c]; });
+        b->final_copy.assign(p->ntubes, 0);
+        if (p->seg_cols && p->round_steps) {
+            b->seg = p->seg_cols;
+            b->ks = p->round_steps;
+        }
+    } catch (...) {
+        delete b;
+        return MRTFD_ERR_ARG;
+    }
+    hipError_t e = hipMemsetAsync(b->ws, 0, L.total, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_tubes, b->info.data(), b->info.size() * sizeof(TubeInfo),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_states, b->states.data(), b->states.size() * sizeof(float),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        delete b;
+        return MRTFD_ERR_HIP;
+    }
+    *out = b;
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_batch_init(mrtfd_batch *b)
+{
+    if (!b) return MRTFD_ERR_ARG;
+    BHIPCHK(b, launch_tubes_init(b->TG, b->K, b->d_tubes, b->d_states, b->p.ntubes, b->max_n, b->f[0],
+                                 b->stream));
+    std::fill(b->final_copy.begin(), b->final_copy.end(), 0);
+    b->initialised = true;
+    b->done = false;
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_batch_run(mrtfd_batch *b)
+{
+    if (!b) return MRTFD_ERR_ARG;
+    if (!b->initialised || b->done) return bset_err(b, MRTFD_ERR_STATE, "run needs a fresh mrtfd_batch_init");
+    if (!b->seg) {
+        int rc = batch_autotune(b);
+        if (rc != MRTFD_OK) return rc;
+    }
+    if (b->items.empty()) {
+        build_items(b, b->seg, b->ks, b->items, b->round_items);
+        BHIPCHK(b, hipMemcpyAsync(b->d_items, b->items.data(), b->items.size() * sizeof(TubeItem),
+                                  hipMemcpyHostToDevice, b->stream));
+    }
+    if (b->p.use_graph) {
+        if (!b->graph) {
+            if (!b->cap) BHIPCHK(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            BHIPCHK(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_rounds(b, b->cap);
+            hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return bset_err(b, MRTFD_ERR_HIP, "batch graph capture failed");
+            }
+            e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return bset_err(b, MRTFD_ERR_HIP, "batch graph instantiate failed");
+        }
+        BHIPCHK(b, hipGraphLaunch(b->graph, b->stream));
+    } else {
+        BHIPCHK(b, enqueue_rounds(b, b->stream));
+    }
+    for (int k = 0; k < b->p.ntubes; ++k) {
+        const long long rounds = (b->steps[k] + b->ks - 1) / b->ks;
+        b->final_copy[k] = (int)(rounds & 1);
+    }
+    b->done = true;
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_batch_read_macro(mrtfd_batch *b, int32_t tube, float *rho, float *ux, float *uy,
+                               float *T, float *pr)
+{
+    if (!b) return MRTFD_ERR_ARG;
+    if (tube < 0 || tube >= b->p.ntubes) return bset_err(b, MRTFD_ERR_ARG, "bad tube index %d", tube);
+    if (!b->initialised) return bset_err(b, MRTFD_ERR_STATE, "read before init");
+    BHIPCHK(b, launch_tube_macro(b->TG, b->K, b->d_tubes, tube, b->n[tube], b->f[b->final_copy[tube]], rho,
+                                 ux, uy, T, pr, b->stream));
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_batch_get_f(mrtfd_batch *b, int32_t tube, float *dst)
+{
+    if (!b || !dst) return MRTFD_ERR_ARG;
+    if (tube < 0 || tube >= b->p.ntubes) return bset_err(b, MRTFD_ERR_ARG, "bad tube index %d", tube);
+    if (!b->initialised) return bset_err(b, MRTFD_ERR_STATE, "read before init");
+    BHIPCHK(b, launch_tube_pack(b->TG, b->d_tubes, tube, b->n[tube], b->f[b->final_copy[tube]], dst,
+                                b->stream));
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_batch_info(mrtfd_batch *b, int32_t *seg, int32_t *ks, int32_t *rounds)
+{
+    if (!b) return MRTFD_ERR_ARG;
+    if (seg) *seg = b->seg;
+    if (ks) *ks = b->ks;
+    if (rounds) *rounds = (int32_t)b->round_items.size();
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_batch_destroy(mrtfd_batch *b)
+{
+    if (!b) return MRTFD_ERR_ARG;
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return MRTFD_OK;
+}
+
+const char *mrtfd_batch_last_error(const mrtfd_batch *b) { return b ? b->err : "no batch"; }
 
 }  // extern "C"

@@ -61,6 +61,17 @@ struct Field {
     }
 };
 
+// Operands of the split-BF16 transforms on the matrix cores, in the lane
+// layout of v_mfma_f32_16x16x16_bf16 for the A operand (lane l holds row
+// l % 16, columns 4 (l / 16) .. +3): M (rows m1..m16 over populations) and
+// dt M^-1 (rows populations over moments), each as a high and a low BF16
+// part; and dt-free rates s_k per moment for the relaxation in between.
+struct MfmaOperands {
+    unsigned short m_hi[64][4], m_lo[64][4];
+    unsigned short inv_hi[64][4], inv_lo[64][4];
+    float s[NQ];
+};
+
 enum Kind { K_PERIODIC = 0, K_DIRICHLET = 1, K_REFLECT = 2, K_EXTRAPOLATE = 3, K_WALL = 4 };
 
 struct GhostSide {
@@ -76,6 +87,10 @@ struct Ghosts {
     double dt;
     int per_x, per_y;   // periodic in x (west/east) / in y (south/north)
 };
+
+hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
+                            const MfmaOperands *mo, const float *fin, float *fout,
+                            const long long *d_step, int k, hipStream_t s);
 
 // Launchers (mrtfd_kernels.hip).  All enqueue on `s` and return the HIP
 // status of the launch.
@@ -100,6 +115,43 @@ int sums_blocks(const Field &F);
 hipError_t launch_sums(const Field &F, const SumW &W, const float *f, double *partials,
                        double *out, hipStream_t s);
 hipError_t launch_pack(const Field &F, const float *f, float *dst, hipStream_t s);
+
+// ------------------------------------------------------------------ tubes
+// Batched independent tubes: tube k has n columns and TUBE_ROWS rows,
+// periodic in y, f = f^eq of its left / right state beyond its two ends.  All
+// tubes live side by side in one FP32 array per copy: population q, row y,
+// column x of tube k at q * plane + y * ncols + start + x, ncols = sum of n.
+constexpr int TUBE_ROWS = 4;
+
+struct TubeInfo {
+    int n, start, steps, pad;
+    float feq_left[NQ], feq_right[NQ];
+};
+
+struct TubeItem {  // one work item: columns [x0, x0 + seg) of a tube
+    int tube, x0;
+};
+
+struct TubeGrid {
+    long long plane;  // TUBE_ROWS * ncols
+    int ncols;
+};
+
+// One round: every listed item advances min(round_steps, steps - round *
+// round_steps) steps.  seg/round_steps must be one of the built pairs.
+hipError_t launch_tubes(const TubeGrid &T, const Consts &K, const TubeInfo *tubes,
+                        const TubeItem *items, int nitems, int round, int seg, int round_steps,
+                        const float *fin, float *fout, hipStream_t s);
+bool tubes_config_built(int seg, int round_steps);
+// f = f^eq of the left state for x < n/2 and of the right state beyond, per
+// tube; states = device [ntubes][2][4] (rho, u1, u2, T).
+hipError_t launch_tubes_init(const TubeGrid &T, const Consts &K, const TubeInfo *tubes,
+                             const float *states, int ntubes, int max_n, float *f, hipStream_t s);
+hipError_t launch_tube_macro(const TubeGrid &T, const Consts &K, const TubeInfo *tubes, int tube,
+                             int n, const float *f, float *rho, float *ux, float *uy, float *Tt,
+                             float *p, hipStream_t s);
+hipError_t launch_tube_pack(const TubeGrid &T, const TubeInfo *tubes, int tube, int n,
+                            const float *f, float *dst, hipStream_t s);
 hipError_t launch_unpack(const Field &F, const float *src, float *f, hipStream_t s);
 
 }  // namespace mrtfd

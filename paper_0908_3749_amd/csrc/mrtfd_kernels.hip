@@ -492,6 +492,278 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
     }
 }
 
+// ------------------------------------------------- split-BF16 matrix cores
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Round-to-nearest-even FP32 -> BF16 bits, and back.
+__device__ __forceinline__ unsigned short bf16_bits(float x)
+{
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+// x = hi + lo with both parts BF16 (|x - hi - lo| <= 2^-18 |x|).
+__device__ __forceinline__ void split4(const float (&x)[4], bf16x4 &hi, bf16x4 &lo)
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const unsigned short h = bf16_bits(x[c]);
+        hi[c] = (short)h;
+        lo[c] = (short)bf16_bits(x[c] - bf16_float(h));
+    }
+}
+
+// A . B with A, B split into BF16 parts: A_hi B_hi + A_hi B_lo + A_lo B_hi,
+// FP32 accumulation on the matrix cores.
+__device__ __forceinline__ f32x4 mfma3(bf16x4 ahi, bf16x4 alo, bf16x4 bhi, bf16x4 blo)
+{
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, c, 0, 0, 0);
+    return c;
+}
+
+// Step kernel with the two 16x16 transforms of the collision on the matrix
+// cores (split-BF16, three products, FP32 accumulation); the equilibria, the
+// relaxation and the Lax-Wendroff update stay FP32.  Block = 64 columns x 4
+// rows, wave = one row (lane = node, west/east neighbours by DPP as in the
+// row kernel).  Per 16-node group the wave stages its populations in LDS
+// ([node][population]) so that lane l reads populations 4 (l/16) .. +3 of node
+// l % 16 -- the B-operand layout; the product M F comes back with lane l
+// holding moments 4 (l/16) .. +3 of node l % 16, which is again the B layout
+// for the back-map.  Blocks touching a side of the grid use the FP32 node path.
+__global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
+                                                   const MfmaOperands *__restrict__ mo,
+                                                   const float *__restrict__ fin,
+                                                   float *__restrict__ fout, unsigned bytes,
+                                                   int ncol, int nrb, int nblocks,
+                                                   const long long *__restrict__ d_step, int k)
+{
+    __shared__ float stage[4][64][NQ + 4];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int b = blockIdx.x;
+    if ((nblocks & 7) == 0) b = (b & 7) * (nblocks >> 3) + (b >> 3);
+    const int col = b % ncol, rb = b / ncol;
+    const int x0 = col * 64, yb = rb * 4, x = x0 + lane, y = yb + wv;
+    if (col == 0 || x0 + 64 >= F.nx || yb == 0 || yb + 4 >= F.ny) {  // uniform over the block
+        if (x < F.nx && y < F.ny) node_update(F, K, G, fin, fout, x, y, step_time(G, d_step, k));
+        return;
+    }
+    const unsigned vo = 4u * (unsigned)(F.xoff + x);
+    const unsigned vh = 4u * (unsigned)(F.xoff + (lane < 32 ? x0 - 1 : x0 + 64));
+    const unsigned planeB = 4u * (unsigned)F.plane, pitchB = 4u * (unsigned)F.pitch;
+    const auto rin = buffer_of(fin, bytes);
+    const auto rout = buffer_of(fout, bytes);
+    auto row = [&](int q, int j) { return (unsigned)q * planeB + (unsigned)(j + 1) * pitchB; };
+    float prv[NQ], cur[NQ], nxt[NQ], hc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        prv[q] = has_y(q) ? bload(rin, vo, row(q, y - 1)) : 0.f;
+        cur[q] = bload(rin, vo, row(q, y));
+        nxt[q] = has_y(q) ? bload(rin, vo, row(q, y + 1)) : 0.f;
+        hc[q] = has_x(q) ? bload(rin, vh, row(q, y)) : 0.f;
+    }
+    // A operands (constant): lane l holds row l%16, columns 4(l/16)..+3
+    bf16x4 mh, ml, ih, il;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        mh[c] = (short)mo->m_hi[lane][c];
+        ml[c] = (short)mo->m_lo[lane][c];
+        ih[c] = (short)mo->inv_hi[lane][c];
+        il[c] = (short)mo->inv_lo[lane][c];
+    }
+    const int grp = lane >> 4, nd = lane & 15;
+    float (*st)[NQ + 4] = stage[wv];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) st[lane][q] = cur[q];
+    __syncthreads();
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const int node = nb * 16 + nd;
+        float fv[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fv[c] = st[node][4 * grp + c];
+        bf16x4 fh, fl;
+        split4(fv, fh, fl);
+        const f32x4 m = mfma3(mh, ml, fh, fl);  // moments 4 grp .. +3 of `node`
+        // conserved moments of the node live in lanes 0..15 (grp 0)
+        const float rho = __shfl(m[0], nd), jx = __shfl(m[1], nd), jy = __shfl(m[2], nd),
+                    e = __shfl(m[3], nd);
+        const Eq q = equilibria(rho, jx, jy, e);
+        const float eqv[NQ] = {rho, jx, jy, e, q.e5, q.e6, q.e7, q.e8,
+                               q.e9, q.e10, q.e11, 0.f, q.e13, q.e14, 0.f, 0.f};
+        float d[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int mk = 4 * grp + c;
+            float eqk = eqv[0];
+#pragma unroll
+            for (int t = 1; t < NQ; ++t) eqk = mk == t ? eqv[t] : eqk;
+            d[c] = mo->s[mk] * (m[c] - eqk);
+        }
+        bf16x4 dh, dl;
+        split4(d, dh, dl);
+        const f32x4 dc = mfma3(ih, il, dh, dl);  // dt C, populations 4 grp .. +3 of `node`
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) st[node][4 * grp + c] = dc[c];
+        __syncthreads();
+    }
+    float dC[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) dC[q] = st[lane][q];
+    Unroll<NQ>::run([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        float fE = 0.f, fW = 0.f;
+        if (has_x(q)) {
+            fE = shl1(cur[q], hc[q]);
+            fW = shr1(cur[q], hc[q]);
+        }
+        bstore(rout, lw_update<q>(K, cur[q], dC[q], fE, fW, nxt[q], prv[q]), vo, row(q, y));
+    });
+}
+
+// ------------------------------------------------------------- tube batches
+
+// Temporal blocking of one work item (columns [x0, x0 + S) of a tube) over KS
+// steps in LDS.  The block loads columns x0 - KS .. x0 + S + KS of all rows and
+// populations once, then advances them KS steps in LDS: after each step the
+// outermost valid column on each side goes stale (a trapezoid), except at the
+// ends of the tube, where the column beyond the end holds the constant
+// boundary equilibrium for every step.  After the last step the S owned
+// columns are written back.  Each node's update is the same arithmetic as the
+// single-grid kernels (collide, then the east/west/north/south terms in that
+// order), so a tube run here equals the same tube run as a grid, bit for bit.
+// LDS: 2 copies x 16 populations x 4 rows x (S + 2 KS) floats.
+template <int S, int KS>
+__global__ __launch_bounds__(256) void k_tubes(TubeGrid TG, Consts K,
+                                               const TubeInfo *__restrict__ tubes,
+                                               const TubeItem *__restrict__ items, int round,
+                                               const float *__restrict__ fin,
+                                               float *__restrict__ fout)
+{
+    constexpr int TW = S + 2 * KS;
+    constexpr int WY = TUBE_ROWS;
+    __shared__ float buf[2][NQ][WY][TW];
+    const TubeItem it = items[blockIdx.x];
+    const int n = tubes[it.tube].n;
+    const int start = tubes[it.tube].start;
+    const int nsteps = min(KS, tubes[it.tube].steps - round * KS);
+    const int xbase = it.x0 - KS;  // tube column of tile column 0
+    const int cL = -1 - xbase;     // tile column of the west boundary node (x = -1)
+    const int cR = n - xbase;      // tile column of the east boundary node (x = n)
+    const float *feqL = tubes[it.tube].feq_left;
+    const float *feqR = tubes[it.tube].feq_right;
+    for (int idx = threadIdx.x; idx < NQ * WY * TW; idx += 256) {
+        const int q = idx / (WY * TW), rem = idx % (WY * TW);
+        const int y = rem / TW, c = rem % TW;
+        const int x = xbase + c;
+        float v = 0.f;
+        if (x >= 0 && x < n)
+            v = fin[(long long)q * TG.plane + (long long)y * TG.ncols + start + x];
+        else if (x == -1)
+            v = feqL[q];
+        else if (x == n)
+            v = feqR[q];
+        buf[0][q][y][c] = v;
+        buf[1][q][y][c] = v;
+    }
+    __syncthreads();
+    int src = 0;
+    for (int st = 0; st < nsteps; ++st) {
+        // valid input columns [a, b); update a+1 .. b-2 (interior nodes only)
+        const int a = cL >= 0 ? cL : st;
+        const int b = cR < TW ? cR + 1 : TW - st;
+        const int c0 = a + 1, ncl = b - 2 - a;
+        for (int idx = threadIdx.x; idx < ncl * WY; idx += 256) {
+            const int c = c0 + idx % ncl, y = idx / ncl;
+            const int yn = y == WY - 1 ? 0 : y + 1, ys = y == 0 ? WY - 1 : y - 1;
+            float fc[NQ], dC[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) fc[q] = buf[src][q][y][c];
+            collide(K, fc, dC);
+            Unroll<NQ>::run([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                float fE = 0.f, fW = 0.f, fN = 0.f, fS = 0.f;
+                if (has_x(q)) {
+                    fE = buf[src][q][y][c + 1];
+                    fW = buf[src][q][y][c - 1];
+                }
+                if (has_y(q)) {
+                    fN = buf[src][q][yn][c];
+                    fS = buf[src][q][ys][c];
+                }
+                buf[src ^ 1][q][y][c] = lw_update<q>(K, fc[q], dC[q], fE, fW, fN, fS);
+            });
+        }
+        __syncthreads();
+        src ^= 1;
+    }
+    for (int idx = threadIdx.x; idx < NQ * WY * S; idx += 256) {
+        const int q = idx / (WY * S), rem = idx % (WY * S);
+        const int y = rem / S, c = KS + rem % S;
+        const int x = xbase + c;
+        if (x >= 0 && x < n)
+            fout[(long long)q * TG.plane + (long long)y * TG.ncols + start + x] = buf[src][q][y][c];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tubes_init(TubeGrid TG, Consts K,
+                                                    const TubeInfo *__restrict__ tubes,
+                                                    const float *__restrict__ states,
+                                                    float *__restrict__ f)
+{
+    const int k = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int n = tubes[k].n;
+    if (x >= n) return;
+    const float *st = states + (long long)k * 8 + (x < n / 2 ? 0 : 4);
+    float fe[NQ];
+    feq_velocity(K, st[0], st[1], st[2], st[3], fe);
+    const int start = tubes[k].start;
+    for (int y = 0; y < TUBE_ROWS; ++y)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            f[(long long)q * TG.plane + (long long)y * TG.ncols + start + x] = fe[q];
+}
+
+__global__ __launch_bounds__(256) void k_tube_macro(TubeGrid TG, Consts K,
+                                                    const TubeInfo *__restrict__ tubes, int k,
+                                                    const float *__restrict__ f, float *rho,
+                                                    float *ux, float *uy, float *Tt, float *p)
+{
+    const int n = tubes[k].n, start = tubes[k].start;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n * TUBE_ROWS) return;
+    const int y = idx / n, x = idx % n;
+    float fc[NQ], q[4];
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) fc[c] = f[(long long)c * TG.plane + (long long)y * TG.ncols + start + x];
+    macro_of(K, fc, q);
+    if (rho) rho[idx] = q[0];
+    if (ux) ux[idx] = q[1];
+    if (uy) uy[idx] = q[2];
+    if (Tt) Tt[idx] = q[3];
+    if (p) p[idx] = q[0] * q[3];
+}
+
+__global__ __launch_bounds__(256) void k_tube_pack(TubeGrid TG, const TubeInfo *__restrict__ tubes,
+                                                   int k, const float *__restrict__ f,
+                                                   float *__restrict__ dst)
+{
+    const int n = tubes[k].n, start = tubes[k].start;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int q = blockIdx.y;
+    if (idx >= n * TUBE_ROWS) return;
+    const int y = idx / n, x = idx % n;
+    dst[(long long)q * n * TUBE_ROWS + idx] = f[(long long)q * TG.plane + (long long)y * TG.ncols + start + x];
+}
+
 // ------------------------------------------------------------ other kernels
 
 __global__ __launch_bounds__(256) void k_init(Field F, Consts K, float *__restrict__ f,
@@ -713,6 +985,73 @@ hipError_t launch_unpack(const Field &F, const float *src, float *f, hipStream_t
 {
     dim3 grid(blocks_for((long long)F.nx * F.ny, 256), NQ);
     hipLaunchKernelGGL(k_unpack, grid, dim3(256), 0, s, F, src, f);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ tube launchers
+
+#define MRTFD_TUBE_CONFIGS(X) X(64, 8) X(64, 16) X(96, 8) X(96, 16) X(112, 8)
+
+bool tubes_config_built(int seg, int round_steps)
+{
+#define MRTFD_TC(Sv, Kv) if (seg == Sv && round_steps == Kv) return true;
+    MRTFD_TUBE_CONFIGS(MRTFD_TC)
+#undef MRTFD_TC
+    return false;
+}
+
+hipError_t launch_tubes(const TubeGrid &T, const Consts &K, const TubeInfo *tubes,
+                        const TubeItem *items, int nitems, int round, int seg, int round_steps,
+                        const float *fin, float *fout, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+#define MRTFD_TL(Sv, Kv)                                                                           \
+    if (seg == Sv && round_steps == Kv) {                                                          \
+        hipLaunchKernelGGL((k_tubes<Sv, Kv>), dim3(nitems), dim3(256), 0, s, T, K, tubes, items,   \
+                           round, fin, fout);                                                      \
+        return hipGetLastError();                                                                  \
+    }
+    MRTFD_TUBE_CONFIGS(MRTFD_TL)
+#undef MRTFD_TL
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tubes_init(const TubeGrid &T, const Consts &K, const TubeInfo *tubes,
+                             const float *states, int ntubes, int max_n, float *f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tubes_init, dim3(blocks_for(max_n, 256), ntubes), dim3(256), 0, s, T, K,
+                       tubes, states, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_tube_macro(const TubeGrid &T, const Consts &K, const TubeInfo *tubes, int tube,
+                             int n, const float *f, float *rho, float *ux, float *uy, float *Tt,
+                             float *p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tube_macro, dim3(blocks_for((long long)n * TUBE_ROWS, 256)), dim3(256), 0,
+                       s, T, K, tubes, tube, f, rho, ux, uy, Tt, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_tube_pack(const TubeGrid &T, const TubeInfo *tubes, int tube, int n,
+                            const float *f, float *dst, hipStream_t s)
+{
+    dim3 grid(blocks_for((long long)n * TUBE_ROWS, 256), NQ);
+    hipLaunchKernelGGL(k_tube_pack, grid, dim3(256), 0, s, T, tubes, tube, f, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
+                            const MfmaOperands *mo, const float *fin, float *fout,
+                            const long long *d_step, int k, hipStream_t s)
+{
+    const int ncol = (F.nx + 63) / 64;
+    const int nrb = (F.ny + 3) / 4;
+    const int nb = ncol * nrb;
+    const long long total = 4LL * NQ * F.plane;
+    if (total >= (1LL << 32)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_mfma, dim3(nb), dim3(256), 0, s, F, K, G, mo, fin, fout,
+                       (unsigned)total, ncol, nrb, nb, d_step, k);
     return hipGetLastError();
 }
 

@@ -150,7 +150,7 @@ class MRT2D:
         k = C.c_int32()
         s = C.c_int32()
         check(lib().mrtfd_kernel_info(self._ctx, C.byref(k), C.byref(s)), self._ctx)
-        return {1: "simple", 2: "rows"}.get(k.value, "none"), s.value
+        return {1: "simple", 2: "rows", 3: "mfma"}.get(k.value, "none"), s.value
 
     def kernel_time(self, nlaunch=20):
         """Average milliseconds per launch of the step kernel alone."""
@@ -162,6 +162,97 @@ class MRT2D:
         if self._ctx:
             lib().mrtfd_destroy(self._ctx)
             self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class TubeBatch:
+    """Many independent shock tubes (4 rows, periodic in y, f^eq of the end
+    states beyond both ends) advanced together, each to its own step count."""
+
+    ROWS = 4
+
+    def __init__(self, n, steps, left, right, dx, dt, s, seg_cols=0, round_steps=0,
+                 use_graph=False, device=None, stream=None):
+        import torch
+
+        self.torch = torch
+        self.n = [int(v) for v in n]
+        nt = len(self.n)
+        p = _abi.mrtfd_batch_params()
+        p.ntubes = nt
+        p.dx, p.dt = float(dx), float(dt)
+        for k in range(16):
+            p.s[k] = float(s[k])
+        p.seg_cols, p.round_steps, p.use_graph = int(seg_cols), int(round_steps), int(bool(use_graph))
+        self.p = p
+        self._n = (C.c_int32 * nt)(*self.n)
+        self._steps = (C.c_int64 * nt)(*[int(v) for v in steps])
+        lf = np.ascontiguousarray(left, dtype=np.float64).reshape(nt, 4)
+        rt = np.ascontiguousarray(right, dtype=np.float64).reshape(nt, 4)
+        self._left = (C.c_double * (4 * nt))(*lf.ravel().tolist())
+        self._right = (C.c_double * (4 * nt))(*rt.ravel().tolist())
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = lib().mrtfd_batch_workspace_bytes(C.byref(p), self._n)
+        if nbytes == 0:
+            raise _abi.MrtfdError(_abi.MRTFD_ERR_ARG, "invalid batch parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._b = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().mrtfd_batch_create(C.byref(p), self._n, self._steps, self._left, self._right,
+                                           C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                           C.c_void_p(self.stream.cuda_stream), C.byref(self._b)))
+
+    @classmethod
+    def from_description(cls, batch, **kw):
+        """From a dict with tubes (n, left, right as (rho, u, p), steps), dx,
+        dt, s -- the seeded batch descriptions used by tests and bench."""
+        left = [(r, u, 0.0, p / r) for (r, u, p) in (t["left"] for t in batch["tubes"])]
+        right = [(r, u, 0.0, p / r) for (r, u, p) in (t["right"] for t in batch["tubes"])]
+        return cls([t["n"] for t in batch["tubes"]], [t["steps"] for t in batch["tubes"]], left, right,
+                   batch["dx"], batch["dt"], batch["s"], **kw)
+
+    def init(self):
+        check(lib().mrtfd_batch_init(self._b), batch=self._b)
+
+    def run(self):
+        check(lib().mrtfd_batch_run(self._b), batch=self._b)
+
+    def info(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().mrtfd_batch_info(self._b, C.byref(a), C.byref(b), C.byref(c)), batch=self._b)
+        return a.value, b.value, c.value
+
+    def read_macro(self, k):
+        t = self.torch
+        out = {key: t.empty((self.ROWS, self.n[k]), dtype=t.float32, device=self.device)
+               for key in ("rho", "ux", "uy", "T", "p")}
+        check(lib().mrtfd_batch_read_macro(self._b, int(k), *[C.c_void_p(out[key].data_ptr())
+                                                             for key in ("rho", "ux", "uy", "T", "p")]),
+              batch=self._b)
+        return out
+
+    def macro_numpy(self, k):
+        out = self.read_macro(k)
+        self.stream.synchronize()
+        return {key: v.cpu().numpy().astype(np.float64) for key, v in out.items()}
+
+    def get_f_numpy(self, k):
+        t = self.torch
+        f = t.empty((16, self.ROWS, self.n[k]), dtype=t.float32, device=self.device)
+        check(lib().mrtfd_batch_get_f(self._b, int(k), C.c_void_p(f.data_ptr())), batch=self._b)
+        self.stream.synchronize()
+        return f.cpu().numpy()
+
+    def close(self):
+        if self._b:
+            lib().mrtfd_batch_destroy(self._b)
+            self._b = C.c_void_p()
 
     def __del__(self):
         try:

@@ -321,3 +321,41 @@ def test_couette_strip(gpu):
         assert errs[k] <= 1e-5, (k, errs[k])
     assert metrics.linf(got["ux"], want["ux"]) <= 1e-6
     assert metrics.linf(got["uy"], want["uy"]) <= 1e-6
+
+
+def test_bf16x3_one_step_error_bound(gpu):
+    """Split-BF16 transforms on the matrix cores: each operand x = hi + lo with
+    |x - hi - lo| <= 2^-18 |x|, three products (the lo*lo term, <= 2^-18,
+    dropped), FP32 accumulation.  Per population the collision then errs by
+    at most c 2^-18 (|dt M^-1| |S| |M| |f|)_i; with c = 16 (representation of
+    both operands of both products, the dropped term, accumulation) on top of
+    the FP32 bound.  Interior nodes only (nodes next to a side use FP32)."""
+    nx, ny = 200, 40
+    f0 = synth.random_populations(nx, ny, seed=8, spread=0.3)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"], None)
+    want, _ = run_oracle(prob, f0, 1)
+    got, _, info = run_gpu(gpu, prob, f0, 1, precision="bf16x3")
+    assert info[0] == "mfma"
+    m = core.model()
+    A = np.abs(m.Minv) * prob.dt @ np.diag(np.abs(RATES)) @ np.abs(m.M)
+    scale = np.einsum("ik,kyx->iyx", A, np.abs(f0))
+    bound = 16 * 2.0 ** -18 * scale + 2e-6 * np.max(np.abs(want))
+    inner = (slice(None), slice(4, ny - 4), slice(64, 128))
+    ratio = np.abs(got - want)[inner] / bound[inner]
+    print(f"bf16x3 one step: max err {np.max(np.abs(got - want)[inner]):.3e}, max err/bound {ratio.max():.3f}")
+    assert np.all(ratio <= 1.0)
+    fp32, _, _ = run_gpu(gpu, prob, f0, 1)
+    # edge blocks run the FP32 path: identical there
+    assert np.array_equal(got[:, :4, :], fp32[:, :4, :])
+
+
+def test_bf16x3_couette_strip(gpu):
+    prob = synth.couette(nx=256, ny=256, noise=1e-3)
+    _, want = run_oracle(prob, None, 500)
+    _, got32, _ = run_gpu(gpu, prob, None, 500)
+    _, got16, _ = run_gpu(gpu, prob, None, 500, precision="bf16x3")
+    e32 = {k: metrics.rel_l1(got32[k], want[k]) for k in ("rho", "ux", "p")}
+    e16 = {k: metrics.rel_l1(got16[k], want[k]) for k in ("rho", "ux", "p")}
+    print("couette 256x256 500 steps rel L1: fp32", e32, "bf16x3", e16)
+    for k in ("rho", "p"):
+        assert e16[k] <= 1e-4, (k, e16[k])

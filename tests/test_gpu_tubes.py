@@ -1,0 +1,115 @@
+"""GPU batches of independent shock tubes (temporally blocked in LDS): each
+tube equals the single-grid run of the same tube bit for bit, for every
+work-item width, steps-per-round and with or without graph replay; and the
+tubes agree with the FP64 oracle and the gamma = 2 exact Riemann solution."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import core, metrics, riemann
+
+pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def star_fn(L, R):
+    W = riemann.wave_speeds(L, R)
+    return riemann.max_signal_speed(L, R), min(W["rho_star_left"], W["rho_star_right"])
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_0908_3749_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    b = synth.tube_batch(ntubes=7, nmin=130, nmax=520, seed=77, star_fn=star_fn)
+    for k, t in enumerate(b["tubes"]):
+        t["steps"] = min(t["steps"], 300 + 97 * k)  # keep the single-grid runs short
+    b["tubes"][3]["steps"] = 0                    # a tube that does not move
+    return b
+
+
+def single_grid(P, batch, k):
+    prob = synth.tube_problem(batch, k)
+    g = P.MRT2D.from_problem(prob)
+    g.init_problem(prob)
+    g.step(prob.nsteps)
+    f = g.get_f_numpy()
+    g.close()
+    return f
+
+
+@pytest.mark.parametrize("cfg", [dict(), dict(seg_cols=64, round_steps=8), dict(seg_cols=96, round_steps=16),
+                                 dict(seg_cols=112, round_steps=8, use_graph=True),
+                                 dict(seg_cols=64, round_steps=16, use_graph=True)])
+def test_batch_equals_single_grid_bitwise(gpu, small_batch, cfg):
+    B = gpu.TubeBatch.from_description(small_batch, **cfg)
+    B.init()
+    B.run()
+    seg, ks, rounds = B.info()
+    print(f"batch cfg {cfg}: seg {seg}, steps/round {ks}, rounds {rounds}")
+    for k in range(len(small_batch["tubes"])):
+        got = B.get_f_numpy(k)
+        want = single_grid(gpu, small_batch, k)
+        assert np.array_equal(got, want), k
+    B.close()
+
+
+def test_batch_run_needs_fresh_init(gpu, small_batch):
+    B = gpu.TubeBatch.from_description(small_batch, seg_cols=64, round_steps=8)
+    with pytest.raises(gpu.MrtfdError):
+        B.run()
+    B.init()
+    B.run()
+    with pytest.raises(gpu.MrtfdError):
+        B.run()
+    B.close()
+
+
+def test_batch_tubes_match_oracle_and_exact(gpu):
+    """Two seeded tubes at their full CFL-limited run length: FP32 batch vs
+    FP64 oracle (relative L1 <= 1e-4, strong shocks at T up to 1000 make
+    populations large), the fastest shock within one cell of the oracle's and
+    within three cells of the exact solution."""
+    batch = synth.tube_batch(ntubes=2, nmin=300, nmax=500, seed=2024, star_fn=star_fn)
+    B = gpu.TubeBatch.from_description(batch)
+    B.init()
+    B.run()
+    for k, t in enumerate(batch["tubes"]):
+        prob = synth.tube_problem(batch, k)
+        got = B.macro_numpy(k)
+        o = core.Grid(prob, nthreads=THREADS)
+        o.init_problem()
+        o.run(prob.nsteps)
+        want = o.macro()
+        errs = {q: metrics.rel_l1(got[q], want[q]) for q in ("rho", "ux", "p")}
+        print(f"tube {k} n={t['n']} steps={t['steps']}: rel L1 {errs}")
+        for q, v in errs.items():
+            assert v <= 1e-4, (k, q, v)
+        L, R = t["left"], t["right"]
+        W = riemann.wave_speeds(L, R)
+        x = prob.x_centres()
+        for side in ("left", "right"):
+            if not W[side + "_shock"]:
+                continue
+            xs = prob.meta["x0"] + W[side + "_head"] * prob.t_end
+            pre = L[0] if side == "left" else R[0]
+            post = W["rho_star_" + side]
+            lvl = 0.5 * (pre + post)
+            lo, hi = xs - 6 * prob.dx, xs + 6 * prob.dx
+            a = metrics.crossing(x, want["rho"][1], lvl, lo=lo, hi=hi)
+            b = metrics.crossing(x, got["rho"][1], lvl, lo=lo, hi=hi)
+            assert a is not None and b is not None, (k, side)
+            assert abs(a - b) <= prob.dx, (k, side, a, b)
+            assert abs(b - xs) <= 3 * prob.dx, (k, side, b, xs)
+    B.close()

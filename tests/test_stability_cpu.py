@@ -1,0 +1,71 @@
+"""The von Neumann screen (Sect. IV) on the host: closed-form limits and an
+independent Jacobian."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import core
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_0908_3749_amd import _abi, build_lib, stability
+    import os
+    if not os.path.exists(_abi.LIB_PATH):
+        build_lib.build()
+    return stability
+
+
+def test_library_model_is_the_oracles(S):
+    v, M, Minv = S.model()
+    m = core.model()
+    np.testing.assert_allclose(v, m.v, atol=1e-15)
+    np.testing.assert_allclose(M, m.M, atol=1e-12)
+    assert np.max(np.abs(M @ Minv - np.eye(16))) < 1e-13
+
+
+@pytest.mark.parametrize("state", [(1.0, 0.0, 0.0, 1.0), (2.0, 10.0, 0.0, 2.0), (0.3, -1.2, 0.7, 4.0)])
+def test_jacobian_against_finite_differences_of_the_oracle(S, state):
+    rho, ux, uy, T = state
+    e = rho * (T + 0.5 * (ux * ux + uy * uy))
+    x0 = np.array([rho, rho * ux, rho * uy, e])
+    J = S.feq_jacobian(*state)
+    for k in range(4):
+        h = 1e-6 * max(1.0, abs(x0[k]))
+        xp, xm = x0.copy(), x0.copy()
+        xp[k] += h
+        xm[k] -= h
+        fd = (core.feq_moments(*xp) - core.feq_moments(*xm)) / (2 * h)
+        np.testing.assert_allclose(J[:, k], fd, rtol=1e-6, atol=1e-6 * np.max(np.abs(fd)))
+
+
+def test_zero_rates_give_the_advection_factor(S):
+    dx, dt = 2e-3, 2e-5
+    v, _, _ = S.model()
+    for tx, ty in [(0.3, 0.0), (1.1, -2.0), (math.pi, 0.5)]:
+        G = S.amplification((1.0, 0.2, 0.0, 1.0), [0.0] * 16, dx, dx, dt, tx, ty)
+        a, b = v[:, 0] * dt / dx, v[:, 1] * dt / dx
+        want = 1 - 1j * a * np.sin(tx) + a * a * (np.cos(tx) - 1) - 1j * b * np.sin(ty) + b * b * (np.cos(ty) - 1)
+        np.testing.assert_allclose(np.diag(G), want, atol=1e-15)
+        assert np.max(np.abs(G - np.diag(np.diag(G)))) == 0.0
+
+
+def test_uniform_mode_eigenvalues(S):
+    """At theta = 0 the collision maps conserved moments to themselves and
+    relaxes moment k by 1 - dt s_k: eigenvalues {1 x4} and {1 - dt s_k}."""
+    dt = 1e-5
+    s = synth.rates(dt, s5=1e3, s6=2e3, s7=3e3, s8=4e3, s9=5e3, s10=6e3, s11=7e3, s12=8e3,
+                    s13=9e3, s14=1e4, s15=2e4, s16=3e4)
+    G = S.amplification((1.3, 0.4, -0.2, 0.8), s, 0.01, 0.01, dt, 0.0, 0.0)
+    w = np.sort(np.linalg.eigvals(G).real)
+    want = np.sort(np.array([1.0] * 4 + [1 - dt * sk for sk in s[4:]]))
+    np.testing.assert_allclose(w, want, atol=1e-9)
+
+
+def test_sod_parameters_are_linearly_stable(S):
+    prob = synth.sod()
+    for st in ((1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.8)):
+        w, _ = S.max_growth(st, prob.s, prob.dx, prob.dy, prob.dt, n=12)
+        assert w <= 1.0 + 1e-9, (st, w)
