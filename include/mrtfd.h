@@ -73,6 +73,11 @@ extern "C" {
                           parts, three products, FP32 accumulation; the rest
                           FP32 (nodes next to a side use the FP32 path)      */
 
+/* ---- collision operator ------------------------------------------------ */
+#define MRTFD_COLLISION_MRT 0 /* Eq. (3): M^-1 S-hat (f-hat - f-hat^eq)            */
+#define MRTFD_COLLISION_SRT 1 /* single relaxation time S = I/tau (Sect. II):
+                                 s_5 (f - f^eq); s_6..s_16 must equal s_5    */
+
 /* ---- kernel choice for the step ---------------------------------------- */
 #define MRTFD_KERNEL_AUTO 0   /* autotuned among the variants below            */
 #define MRTFD_KERNEL_SIMPLE 1 /* one thread per node, 64x4 tiles, neighbours
@@ -108,6 +113,7 @@ typedef struct mrtfd_params {
     int32_t rows;       /* rows per wave for MRTFD_KERNEL_ROWS (1 or 2),
                            0 = auto                                          */
     int32_t graph_steps;/* steps per captured HIP graph, 0 = no graph        */
+    int32_t collision;  /* MRTFD_COLLISION_MRT or _SRT                        */
 } mrtfd_params;
 
 typedef struct mrtfd_ctx mrtfd_ctx;

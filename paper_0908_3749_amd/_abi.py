@@ -30,6 +30,9 @@ BC_KINDS = {"periodic": MRTFD_BC_PERIODIC, "dirichlet": MRTFD_BC_DIRICHLET,
 MRTFD_FP32 = 0
 MRTFD_BF16X3 = 1
 
+MRTFD_COLLISION_MRT = 0
+MRTFD_COLLISION_SRT = 1
+
 MRTFD_KERNEL_AUTO = 0
 MRTFD_KERNEL_SIMPLE = 1
 MRTFD_KERNEL_ROWS = 2
@@ -60,6 +63,7 @@ class mrtfd_params(C.Structure):
         ("side", mrtfd_side * 4),
         ("precision", C.c_int32), ("kernel", C.c_int32),
         ("rows", C.c_int32), ("graph_steps", C.c_int32),
+        ("collision", C.c_int32),
     ]
 
 

@@ -267,6 +267,8 @@ void fill_consts(const Model &m, const mrtfd_params &p, Consts &K)
             K.cqa[a][b] = cs(12 + a, rqa[b]);
             K.cqd[a][b] = cs(14 + a, rqd[b]);
         }
+    K.srt = p.collision == MRTFD_COLLISION_SRT;
+    K.dts = (float)(dt * p.s[4]);
     for (int q = 0; q < NQ; ++q) {
         const double a = m.v[q][0] * dt / p.dx, b = m.v[q][1] * dt / p.dy;
         K.lw[q][0] = (float)(0.5 * (a * a - a));
@@ -339,6 +341,15 @@ int check(const mrtfd_params *p, char *msg, size_t len)
     if (cfl > 1.0) return fail(MRTFD_ERR_UNSTABLE, "Courant number 6 dt / min(dx,dy) = %g exceeds 1", cfl);
     if (p->precision != MRTFD_FP32 && p->precision != MRTFD_BF16X3)
         return fail(MRTFD_ERR_ARG, "unknown precision mode %d", p->precision);
+    if (p->collision != MRTFD_COLLISION_MRT && p->collision != MRTFD_COLLISION_SRT)
+        return fail(MRTFD_ERR_ARG, "unknown collision %d", p->collision);
+    if (p->collision == MRTFD_COLLISION_SRT) {
+        for (int k = 5; k < NQ; ++k)
+            if (p->s[k] != p->s[4])
+                return fail(MRTFD_ERR_ARG, "single relaxation time needs s_6..s_16 equal to s_5");
+        if (p->precision == MRTFD_BF16X3)
+            return fail(MRTFD_ERR_UNSUPPORTED, "single relaxation time has no matrix-core mode");
+    }
     if (p->kernel < MRTFD_KERNEL_AUTO || p->kernel > MRTFD_KERNEL_ROWS)
         return fail(MRTFD_ERR_ARG, "unknown kernel %d", p->kernel);
     if (p->rows != 0 && p->rows != 1 && p->rows != 2)

@@ -45,6 +45,9 @@ struct Consts {
     // + cN (fN - f) + cS (fS - f), cE = (a^2 - a)/2, cW = (a^2 + a)/2 with
     // a = v_x dt / dx (likewise N/S with b = v_y dt / dy).
     float lw[NQ][4];  // cE, cW, cN, cS
+    // single relaxation time: dt C = dts (f - f^eq), dts = dt / tau
+    int srt;
+    float dts;
 };
 
 // Device layout of one copy of f: 16 planes, each (ny + 2) rows of `pitch`

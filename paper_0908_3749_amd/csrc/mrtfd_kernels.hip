@@ -136,8 +136,8 @@ __device__ __forceinline__ Eq equilibria(float rho, float jx, float jy, float e)
     return q;
 }
 
-// dC = dt * C of Eq. (3) for one node.
-__device__ __forceinline__ void collide(const Consts &K, const float (&f)[NQ], float (&dC)[NQ])
+// dC = dt * C of Eq. (3) for one node (multiple relaxation times).
+__device__ __forceinline__ void collide_mrt(const Consts &K, const float (&f)[NQ], float (&dC)[NQ])
 {
     float m[NQ];
     moments(K, f, m);
@@ -163,11 +163,10 @@ __device__ __forceinline__ void collide(const Consts &K, const float (&f)[NQ], f
 }
 
 // f^eq = M^-1 f-hat^eq of a macroscopic state (initial and boundary nodes).
-__device__ __forceinline__ void feq_velocity(const Consts &K, float rho, float ux, float uy,
-                                             float T, float (&f)[NQ])
+// f^eq = M^-1 f-hat^eq of the conserved moments (rho, j, e).
+__device__ __forceinline__ void feq_of_moments(const Consts &K, float rho, float jx, float jy,
+                                               float e, float (&f)[NQ])
 {
-    const float jx = rho * ux, jy = rho * uy;
-    const float e = rho * fma_(0.5f, fma_(ux, ux, uy * uy), T);
     const Eq q = equilibria(rho, jx, jy, e);
     const float h0[4] = {rho, e, q.e11, 0.0f};
     const float hx[4] = {jx, q.e7, q.e9, 0.0f};
@@ -187,6 +186,36 @@ __device__ __forceinline__ void feq_velocity(const Consts &K, float rho, float u
     group_inv<true>(A[1], X[1], Y[1], Q[1], f[4], f[5], f[6], f[7]);
     group_inv<false>(A[2], X[2], Y[2], Q[2], f[8], f[9], f[10], f[11]);
     group_inv<false>(A[3], X[3], Y[3], Q[3], f[12], f[13], f[14], f[15]);
+}
+
+// f^eq of a macroscopic state (rho, u1, u2, T): initial and boundary nodes.
+__device__ __forceinline__ void feq_velocity(const Consts &K, float rho, float ux, float uy,
+                                             float T, float (&f)[NQ])
+{
+    const float jx = rho * ux, jy = rho * uy;
+    const float e = rho * fma_(0.5f, fma_(ux, ux, uy * uy), T);
+    feq_of_moments(K, rho, jx, jy, e, f);
+}
+
+// Single relaxation time, S = I / tau (Sect. II): dt C = (dt / tau) (f - f^eq)
+// with f^eq of the node's own conserved moments; no transform of the
+// nonequilibrium part is needed.
+__device__ __forceinline__ void collide_srt(const Consts &K, const float (&f)[NQ], float (&dC)[NQ])
+{
+    float rho, jx, jy, e, fe[NQ];
+    conserved(K, f, rho, jx, jy, e);
+    feq_of_moments(K, rho, jx, jy, e, fe);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) dC[q] = K.dts * (f[q] - fe[q]);
+}
+
+template <bool SRT>
+__device__ __forceinline__ void collide(const Consts &K, const float (&f)[NQ], float (&dC)[NQ])
+{
+    if constexpr (SRT)
+        collide_srt(K, f, dC);
+    else
+        collide_mrt(K, f, dC);
 }
 
 // (rho, u1, u2, T) of one node.
@@ -297,6 +326,7 @@ __device__ __forceinline__ void ghost_of(const Consts &K, const Ghosts &G, doubl
 // boundary rule handled.  The Lax-Wendroff terms are added in the order east,
 // west, north, south for every population, the order lw_update uses, so all
 // kernel variants agree bit for bit.
+template <bool SRT>
 __device__ __forceinline__ void node_update(const Field &F, const Consts &K, const Ghosts &G,
                                             const float *__restrict__ fin,
                                             float *__restrict__ fout, int i, int j, double t)
@@ -307,7 +337,7 @@ __device__ __forceinline__ void node_update(const Field &F, const Consts &K, con
     for (int q = 0; q < NQ; ++q) fc[q] = fin[F.at(q, i, j)];
     {
         float dC[NQ];
-        collide(K, fc, dC);
+        collide<SRT>(K, fc, dC);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) out[q] = fc[q] - dC[q];
     }
@@ -378,6 +408,7 @@ __device__ __forceinline__ double step_time(const Ghosts &G, const long long *d_
 
 // One thread per node, 64x4 nodes per block; neighbours read straight from
 // global memory (the caches absorb the re-reads).
+template <bool SRT>
 __global__ __launch_bounds__(256) void k_step_simple(Field F, Consts K, Ghosts G,
                                                      const float *__restrict__ fin,
                                                      float *__restrict__ fout,
@@ -386,7 +417,7 @@ __global__ __launch_bounds__(256) void k_step_simple(Field F, Consts K, Ghosts G
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (i >= F.nx || j >= F.ny) return;
-    node_update(F, K, G, fin, fout, i, j, step_time(G, d_step, k));
+    node_update<SRT>(F, K, G, fin, fout, i, j, step_time(G, d_step, k));
 }
 
 // Wavefront shifts across all 64 lanes (DPP wave_shr:1 / wave_shl:1, CDNA).
@@ -430,7 +461,7 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsign
 // others have only interior neighbours.  Addressing is by buffer
 // instructions: one per-lane byte offset shared by all loads of a column, plus
 // a wave-uniform offset for (plane, row).
-template <int R>
+template <int R, bool SRT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
                  float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
@@ -452,7 +483,7 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
         if (x < F.nx) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (y0 + r < F.ny) node_update(F, K, G, fin, fout, x, y0 + r, t);
+                if (y0 + r < F.ny) node_update<SRT>(F, K, G, fin, fout, x, y0 + r, t);
         }
         return;
     }
@@ -478,7 +509,7 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         float dC[NQ];
-        collide(K, v[r + 1], dC);
+        collide<SRT>(K, v[r + 1], dC);
         Unroll<NQ>::run([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             float fE = 0.f, fW = 0.f;
@@ -551,7 +582,7 @@ __global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
     const int col = b % ncol, rb = b / ncol;
     const int x0 = col * 64, yb = rb * 4, x = x0 + lane, y = yb + wv;
     if (col == 0 || x0 + 64 >= F.nx || yb == 0 || yb + 4 >= F.ny) {  // uniform over the block
-        if (x < F.nx && y < F.ny) node_update(F, K, G, fin, fout, x, y, step_time(G, d_step, k));
+        if (x < F.nx && y < F.ny) node_update<false>(F, K, G, fin, fout, x, y, step_time(G, d_step, k));
         return;
     }
     const unsigned vo = 4u * (unsigned)(F.xoff + x);
@@ -686,7 +717,7 @@ __global__ __launch_bounds__(256) void k_tubes(TubeGrid TG, Consts K,
             float fc[NQ], dC[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) fc[q] = buf[src][q][y][c];
-            collide(K, fc, dC);
+            collide<false>(K, fc, dC);
             Unroll<NQ>::run([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 float fE = 0.f, fW = 0.f, fN = 0.f, fS = 0.f;
@@ -911,7 +942,10 @@ hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, 
                               float *fout, const long long *d_step, int k, hipStream_t s)
 {
     dim3 grid(blocks_for(F.nx, 64), blocks_for(F.ny, 4));
-    hipLaunchKernelGGL(k_step_simple, grid, dim3(256), 0, s, F, K, G, fin, fout, d_step, k);
+    if (K.srt)
+        hipLaunchKernelGGL(k_step_simple<true>, grid, dim3(256), 0, s, F, K, G, fin, fout, d_step, k);
+    else
+        hipLaunchKernelGGL(k_step_simple<false>, grid, dim3(256), 0, s, F, K, G, fin, fout, d_step, k);
     return hipGetLastError();
 }
 
@@ -927,8 +961,12 @@ hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, co
     switch (rows) {
 #define MRTFD_ROWS(Rr)                                                                             \
     case Rr:                                                                                       \
-        hipLaunchKernelGGL(k_step_rows<Rr>, dim3(nb), dim3(256), 0, s, F, K, G, fin, fout, bytes,  \
-                           ncol, nrg, nb, d_step, k);                                              \
+        if (K.srt)                                                                                 \
+            hipLaunchKernelGGL((k_step_rows<Rr, true>), dim3(nb), dim3(256), 0, s, F, K, G, fin,   \
+                               fout, bytes, ncol, nrg, nb, d_step, k);                             \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_step_rows<Rr, false>), dim3(nb), dim3(256), 0, s, F, K, G, fin,  \
+                               fout, bytes, ncol, nrg, nb, d_step, k);                             \
         break;
         MRTFD_ROWS(1)
         MRTFD_ROWS(2)

@@ -104,6 +104,14 @@ def test_validation_rejects_bad_params(abi):
     p = _params(prob)
     p.rows = 3
     assert check_params(p)[0] == abi.MRTFD_ERR_ARG
+    p = _params(prob, collision="srt")  # the Sod rates are not all equal
+    assert check_params(p)[0] == abi.MRTFD_ERR_ARG
+    p = _params(prob, collision="srt")
+    for k in range(4, 16):
+        p.s[k] = 4e4
+    assert check_params(p)[0] == abi.MRTFD_OK
+    p.precision = abi.MRTFD_BF16X3
+    assert check_params(p)[0] == abi.MRTFD_ERR_UNSUPPORTED
 
 
 def test_create_rejects_bad_workspace_without_gpu(abi):

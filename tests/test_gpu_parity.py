@@ -359,3 +359,28 @@ def test_bf16x3_couette_strip(gpu):
     print("couette 256x256 500 steps rel L1: fp32", e32, "bf16x3", e16)
     for k in ("rho", "p"):
         assert e16[k] <= 1e-4, (k, e16[k])
+
+
+def test_single_relaxation_time_mode(gpu):
+    """S = I / tau (Sect. II): the SRT path, s (f - f^eq) in velocity space,
+    matches the oracle's collision with all rates equal (which is the same
+    operator, Eq. 3 with S-hat = I / tau) within the FP32 bounds, one step and
+    300 steps; and it agrees with the MRT path at equal rates to FP32
+    rounding."""
+    nx, ny = 150, 37
+    s_all = [0.0] * 4 + [1e5] * 12
+    f0 = synth.random_populations(nx, ny, seed=21)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, s_all, SIDE_SETS["reflect_extrapolate"], None)
+    want, _ = run_oracle(prob, f0, 1)
+    srt, _, _ = run_gpu(gpu, prob, f0, 1, collision="srt")
+    mrt, _, _ = run_gpu(gpu, prob, f0, 1, collision="mrt")
+    e1 = np.max(np.abs(srt - want)) / np.max(np.abs(want))
+    e2 = np.max(np.abs(srt - mrt)) / np.max(np.abs(want))
+    print(f"srt one step: vs oracle {e1:.2e}, vs mrt path {e2:.2e}")
+    assert e1 <= 2e-6 and e2 <= 2e-6
+    ic = synth.smooth_macro(nx, ny, seed=3, du=0.2, dr=0.1)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, s_all, SIDE_SETS["periodic"], ic)
+    _, want = run_oracle(prob, None, 300)
+    _, got, _ = run_gpu(gpu, prob, None, 300, collision="srt")
+    for k in ("rho", "ux", "uy", "p"):
+        assert metrics.rel_l1(got[k], want[k]) <= 1e-5, k
