@@ -180,6 +180,7 @@ def main():
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--layout", default="rows", choices=["rows", "planes"])
     ap.add_argument("--cpu-steps", type=int, default=12000, help="oracle steps on the crop")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-graph", action="store_true", help="tubes: launch rounds directly")
@@ -230,7 +231,7 @@ def main():
     cells = prob.nx * prob.ny
 
     g = MRT2D.from_problem(prob, kernel=args.kernel, rows=args.rows, graph_steps=args.graph_steps,
-                           precision=args.precision)
+                           precision=args.precision, layout=args.layout)
     g.init_problem(prob)
     g.step(args.warmup)
     torch.cuda.synchronize()
@@ -267,7 +268,7 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "bf16x3+f32",
         "data": "synthetic",
         "config": {"workload": W["name"], "nx": prob.nx, "ny": prob.ny, "dt": prob.dt,
-                   "precision": args.precision,
+                   "precision": args.precision, "layout": args.layout,
                    "kernel": kernel, "rows": seg, "graph_steps": args.graph_steps,
                    "gamma": 2.0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

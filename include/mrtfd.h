@@ -76,7 +76,16 @@ extern "C" {
 /* ---- collision operator ------------------------------------------------ */
 #define MRTFD_COLLISION_MRT 0 /* Eq. (3): M^-1 S-hat (f-hat - f-hat^eq)            */
 #define MRTFD_COLLISION_SRT 1 /* single relaxation time S = I/tau (Sect. II):
-                                 s_5 (f - f^eq); s_6..s_16 must equal s_5    */
+                                 s_6..s_16 must equal s_5 = 1/tau; computed
+                                 as Eq. (3) with equal rates, which keeps
+                                 the conserved moments out of the update
+                                 exactly (f - f^eq evaluated in velocity
+                                 space in FP32 does not)                     */
+
+/* ---- device order of the populations (internal copies of f) ------------ */
+#define MRTFD_LAYOUT_ROWS 0   /* per grid row, the 16 population rows side by
+                                 side                                          */
+#define MRTFD_LAYOUT_PLANES 1 /* 16 whole-grid population planes             */
 
 /* ---- kernel choice for the step ---------------------------------------- */
 #define MRTFD_KERNEL_AUTO 0   /* autotuned among the variants below            */
@@ -114,6 +123,7 @@ typedef struct mrtfd_params {
                            0 = auto                                          */
     int32_t graph_steps;/* steps per captured HIP graph, 0 = no graph        */
     int32_t collision;  /* MRTFD_COLLISION_MRT or _SRT                        */
+    int32_t layout;     /* MRTFD_LAYOUT_ROWS or _PLANES (device order of f)   */
 } mrtfd_params;
 
 typedef struct mrtfd_ctx mrtfd_ctx;
@@ -218,8 +228,10 @@ typedef struct mrtfd_batch_params {
     int32_t ntubes;      /* >= 1                                                */
     double dx, dt;       /* node spacing (dx = dy) and time step, all tubes     */
     double s[16];        /* relaxation rates as in mrtfd_params, all tubes      */
-    int32_t seg_cols;    /* columns per work item (64, 96, 112), 0 = autotune   */
-    int32_t round_steps; /* steps per round (8, 16), 0 = autotune              */
+    int32_t seg_cols;    /* columns per work item, 0 = autotune; built pairs
+                            (seg_cols, round_steps): (32,16) (48,8) (96,16)
+                            (112,8)                                          */
+    int32_t round_steps; /* steps per round (8 or 16), 0 = autotune          */
     int32_t use_graph;   /* 1: replay all rounds as one captured HIP graph      */
 } mrtfd_batch_params;
 

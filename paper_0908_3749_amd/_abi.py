@@ -30,6 +30,9 @@ BC_KINDS = {"periodic": MRTFD_BC_PERIODIC, "dirichlet": MRTFD_BC_DIRICHLET,
 MRTFD_FP32 = 0
 MRTFD_BF16X3 = 1
 
+MRTFD_LAYOUT_ROWS = 0
+MRTFD_LAYOUT_PLANES = 1
+
 MRTFD_COLLISION_MRT = 0
 MRTFD_COLLISION_SRT = 1
 
@@ -63,7 +66,7 @@ class mrtfd_params(C.Structure):
         ("side", mrtfd_side * 4),
         ("precision", C.c_int32), ("kernel", C.c_int32),
         ("rows", C.c_int32), ("graph_steps", C.c_int32),
-        ("collision", C.c_int32),
+        ("collision", C.c_int32), ("layout", C.c_int32),
     ]
 
 

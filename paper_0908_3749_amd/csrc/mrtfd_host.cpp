@@ -267,8 +267,6 @@ void fill_consts(const Model &m, const mrtfd_params &p, Consts &K)
             K.cqa[a][b] = cs(12 + a, rqa[b]);
             K.cqd[a][b] = cs(14 + a, rqd[b]);
         }
-    K.srt = p.collision == MRTFD_COLLISION_SRT;
-    K.dts = (float)(dt * p.s[4]);
     for (int q = 0; q < NQ; ++q) {
         const double a = m.v[q][0] * dt / p.dx, b = m.v[q][1] * dt / p.dy;
         K.lw[q][0] = (float)(0.5 * (a * a - a));
@@ -347,9 +345,9 @@ int check(const mrtfd_params *p, char *msg, size_t len)
         for (int k = 5; k < NQ; ++k)
             if (p->s[k] != p->s[4])
                 return fail(MRTFD_ERR_ARG, "single relaxation time needs s_6..s_16 equal to s_5");
-        if (p->precision == MRTFD_BF16X3)
-            return fail(MRTFD_ERR_UNSUPPORTED, "single relaxation time has no matrix-core mode");
     }
+    if (p->layout != MRTFD_LAYOUT_ROWS && p->layout != MRTFD_LAYOUT_PLANES)
+        return fail(MRTFD_ERR_ARG, "unknown layout %d", p->layout);
     if (p->kernel < MRTFD_KERNEL_AUTO || p->kernel > MRTFD_KERNEL_ROWS)
         return fail(MRTFD_ERR_ARG, "unknown kernel %d", p->kernel);
     if (p->rows != 0 && p->rows != 1 && p->rows != 2)
@@ -390,7 +388,14 @@ Field make_field(const mrtfd_params &p)
     F.ny = p.ny;
     F.xoff = 64;
     F.pitch = ((F.xoff + p.nx + 1 + 63) / 64) * 64;
-    F.plane = (long long)F.pitch * (p.ny + 2);
+    F.total = (long long)NQ * F.pitch * (p.ny + 2);
+    if (p.layout == MRTFD_LAYOUT_PLANES) {
+        F.qstride = (long long)F.pitch * (p.ny + 2);
+        F.jstride = F.pitch;
+    } else {
+        F.qstride = F.pitch;
+        F.jstride = (long long)NQ * F.pitch;
+    }
     return F;
 }
 
@@ -404,7 +409,7 @@ Layout layout(const mrtfd_params &p)
 {
     const Field F = make_field(p);
     Layout L;
-    const size_t fbytes = align256((size_t)NQ * (size_t)F.plane * sizeof(float));
+    const size_t fbytes = align256((size_t)F.total * sizeof(float));
     L.fA = 0;
     L.fB = L.fA + fbytes;
     L.partials = L.fB + fbytes;
@@ -419,8 +424,15 @@ Layout layout(const mrtfd_params &p)
 // ----------------------------------------------------------- autotune cache
 
 struct TuneKey {
-    int nx, ny;
-    bool operator<(const TuneKey &o) const { return nx != o.nx ? nx < o.nx : ny < o.ny; }
+    int nx, ny, layout, kernel, rows;
+    bool operator<(const TuneKey &o) const
+    {
+        if (nx != o.nx) return nx < o.nx;
+        if (ny != o.ny) return ny < o.ny;
+        if (layout != o.layout) return layout < o.layout;
+        if (kernel != o.kernel) return kernel < o.kernel;
+        return rows < o.rows;
+    }
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, int>> g_tune;
@@ -479,7 +491,8 @@ hipError_t launch_step(mrtfd_ctx *c, const float *fin, float *fout, int k, hipSt
     if (c->kernel == MRTFD_KERNEL_SIMPLE)
         return launch_step_simple(c->F, c->K, c->G, fin, fout, c->d_step, k, s);
     if (c->kernel == MRTFD_KERNEL_ROWS)
-        return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg, c->d_step, k, s);
+        return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg & 15, c->seg >> 4, c->d_step, k,
+                                s);
     return launch_step_mfma(c->F, c->K, c->G, c->d_mfma, fin, fout, c->d_step, k, s);
 }
 
@@ -530,7 +543,7 @@ int build_graph(mrtfd_ctx *c, int start)
 int autotune(mrtfd_ctx *c)
 {
     if (c->kernel) return MRTFD_OK;
-    const TuneKey key{c->p.nx, c->p.ny};
+    const TuneKey key{c->p.nx, c->p.ny, c->p.layout, c->p.kernel, c->p.rows};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
@@ -544,9 +557,11 @@ int autotune(mrtfd_ctx *c)
     if (c->p.kernel == MRTFD_KERNEL_SIMPLE) {
         cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     } else {
+        // rows per wave, and (bit 4) streaming stores
         for (int r = 1; r <= 2; ++r) {
             if (c->p.rows && r != c->p.rows) continue;
             cands.push_back({MRTFD_KERNEL_ROWS, r});
+            cands.push_back({MRTFD_KERNEL_ROWS, r | 16});
         }
         if (c->p.kernel == MRTFD_KERNEL_AUTO) cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     }
@@ -878,7 +893,7 @@ int32_t mrtfd_kernel_info(mrtfd_ctx *c, int32_t *kernel, int32_t *rows)
 {
     if (!c) return MRTFD_ERR_ARG;
     if (kernel) *kernel = c->kernel;
-    if (rows) *rows = c->seg;
+    if (rows) *rows = c->seg & 15;
     return MRTFD_OK;
 }
 
@@ -894,7 +909,7 @@ struct BatchLayout {
     size_t max_items;
 };
 
-const int kTubeSegs[] = {64, 96, 112};
+const int kTubeSegs[] = {32, 48, 96, 112};
 
 int batch_check(const mrtfd_batch_params *p, const int32_t *n, char *msg, size_t len)
 {
@@ -919,8 +934,8 @@ int batch_check(const mrtfd_batch_params *p, const int32_t *n, char *msg, size_t
     if (6.0 * p->dt / p->dx > 1.0) return fail(MRTFD_ERR_UNSTABLE, "Courant number 6 dt / dx exceeds 1");
     if (p->seg_cols && p->round_steps && !tubes_config_built(p->seg_cols, p->round_steps))
         return fail(MRTFD_ERR_ARG, "seg_cols/round_steps pair not built");
-    if (p->seg_cols && p->seg_cols != 64 && p->seg_cols != 96 && p->seg_cols != 112)
-        return fail(MRTFD_ERR_ARG, "seg_cols must be 0, 64, 96 or 112");
+    if (p->seg_cols && p->seg_cols != 32 && p->seg_cols != 48 && p->seg_cols != 96 && p->seg_cols != 112)
+        return fail(MRTFD_ERR_ARG, "seg_cols must be 0, 32, 48, 96 or 112");
     if (p->round_steps && p->round_steps != 8 && p->round_steps != 16)
         return fail(MRTFD_ERR_ARG, "round_steps must be 0, 8 or 16");
     long long total = 0;
@@ -940,7 +955,7 @@ BatchLayout batch_layout(const mrtfd_batch_params *p, const int32_t *n)
     L.max_items = 0;
     for (int k = 0; k < p->ntubes; ++k) {
         L.ncols += n[k];
-        L.max_items += (size_t)((n[k] + 63) / 64);
+        L.max_items += (size_t)((n[k] + 31) / 32);
     }
     const size_t fbytes = align256((size_t)NQ * TUBE_ROWS * (size_t)L.ncols * sizeof(float));
     L.fA = 0;
@@ -1053,7 +1068,7 @@ int batch_autotune(mrtfd_batch *b)
     BHIPCHK(b, hipEventCreate(&e0));
     BHIPCHK(b, hipEventCreate(&e1));
     double best = -1.0;
-    std::pair<int, int> pick{64, 8};
+    std::pair<int, int> pick{48, 8};
     int rc = MRTFD_OK;
     std::vector<std::vector<TubeItem>> keep;  // host sources of the async uploads
     for (int seg : kTubeSegs) {

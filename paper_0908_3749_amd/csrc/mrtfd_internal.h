@@ -45,22 +45,23 @@ struct Consts {
     // + cN (fN - f) + cS (fS - f), cE = (a^2 - a)/2, cW = (a^2 + a)/2 with
     // a = v_x dt / dx (likewise N/S with b = v_y dt / dy).
     float lw[NQ][4];  // cE, cW, cN, cS
-    // single relaxation time: dt C = dts (f - f^eq), dts = dt / tau
-    int srt;
-    float dts;
 };
 
-// Device layout of one copy of f: 16 planes, each (ny + 2) rows of `pitch`
-// floats.  Interior node (i, j) of population q sits at
-//   q * plane + (j + 1) * pitch + xoff + i,
-// ghost columns at i = -1 and i = nx, ghost rows at j = -1 and j = ny.
-// xoff = 64 keeps every interior row start 256-byte aligned.
+// Device layout of one copy of f.  Rows j = -1 .. ny of `pitch` floats;
+// interior node (i, j) of population q at
+//   q * qstride + (j + 1) * jstride + xoff + i.
+// Two orders: population planes (qstride = (ny + 2) pitch, jstride = pitch)
+// or rows of interleaved populations (qstride = pitch, jstride = 16 pitch:
+// the 16 populations of a row lie next to each other).  xoff = 64 keeps every
+// interior row start 256-byte aligned; the ring around the interior is
+// padding that no kernel reads.
 struct Field {
     int nx, ny;
     int pitch, xoff;
-    long long plane;
+    long long qstride, jstride;
+    long long total;  // floats in one copy
     __host__ __device__ long long at(int q, int i, int j) const {
-        return (long long)q * plane + (long long)(j + 1) * pitch + xoff + i;
+        return (long long)q * qstride + (long long)(j + 1) * jstride + xoff + i;
     }
 };
 
@@ -105,7 +106,8 @@ hipError_t launch_init(const Field &F, const Consts &K, float *f, const float *r
 hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
                               float *fout, const long long *d_step, int k, hipStream_t s);
 hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
-                            float *fout, int rows, const long long *d_step, int k, hipStream_t s);
+                            float *fout, int rows, int stream_stores, const long long *d_step,
+                            int k, hipStream_t s);
 hipError_t launch_counter_add(long long *d_step, long long n, hipStream_t s);
 hipError_t launch_counter_set(long long *d_step, long long n, hipStream_t s);
 hipError_t launch_read_macro(const Field &F, const Consts &K, const float *f, float *rho,

@@ -136,8 +136,10 @@ __device__ __forceinline__ Eq equilibria(float rho, float jx, float jy, float e)
     return q;
 }
 
-// dC = dt * C of Eq. (3) for one node (multiple relaxation times).
-__device__ __forceinline__ void collide_mrt(const Consts &K, const float (&f)[NQ], float (&dC)[NQ])
+// dC = dt * C of Eq. (3) for one node.  A single relaxation time (Sect. II,
+// S = I / tau) is the case of equal rates: the same arithmetic, so that
+// mass, momentum and energy stay exactly out of the back-map.
+__device__ __forceinline__ void collide(const Consts &K, const float (&f)[NQ], float (&dC)[NQ])
 {
     float m[NQ];
     moments(K, f, m);
@@ -195,27 +197,6 @@ __device__ __forceinline__ void feq_velocity(const Consts &K, float rho, float u
     const float jx = rho * ux, jy = rho * uy;
     const float e = rho * fma_(0.5f, fma_(ux, ux, uy * uy), T);
     feq_of_moments(K, rho, jx, jy, e, f);
-}
-
-// Single relaxation time, S = I / tau (Sect. II): dt C = (dt / tau) (f - f^eq)
-// with f^eq of the node's own conserved moments; no transform of the
-// nonequilibrium part is needed.
-__device__ __forceinline__ void collide_srt(const Consts &K, const float (&f)[NQ], float (&dC)[NQ])
-{
-    float rho, jx, jy, e, fe[NQ];
-    conserved(K, f, rho, jx, jy, e);
-    feq_of_moments(K, rho, jx, jy, e, fe);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) dC[q] = K.dts * (f[q] - fe[q]);
-}
-
-template <bool SRT>
-__device__ __forceinline__ void collide(const Consts &K, const float (&f)[NQ], float (&dC)[NQ])
-{
-    if constexpr (SRT)
-        collide_srt(K, f, dC);
-    else
-        collide_mrt(K, f, dC);
 }
 
 // (rho, u1, u2, T) of one node.
@@ -326,7 +307,6 @@ __device__ __forceinline__ void ghost_of(const Consts &K, const Ghosts &G, doubl
 // boundary rule handled.  The Lax-Wendroff terms are added in the order east,
 // west, north, south for every population, the order lw_update uses, so all
 // kernel variants agree bit for bit.
-template <bool SRT>
 __device__ __forceinline__ void node_update(const Field &F, const Consts &K, const Ghosts &G,
                                             const float *__restrict__ fin,
                                             float *__restrict__ fout, int i, int j, double t)
@@ -337,7 +317,7 @@ __device__ __forceinline__ void node_update(const Field &F, const Consts &K, con
     for (int q = 0; q < NQ; ++q) fc[q] = fin[F.at(q, i, j)];
     {
         float dC[NQ];
-        collide<SRT>(K, fc, dC);
+        collide(K, fc, dC);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) out[q] = fc[q] - dC[q];
     }
@@ -408,7 +388,6 @@ __device__ __forceinline__ double step_time(const Ghosts &G, const long long *d_
 
 // One thread per node, 64x4 nodes per block; neighbours read straight from
 // global memory (the caches absorb the re-reads).
-template <bool SRT>
 __global__ __launch_bounds__(256) void k_step_simple(Field F, Consts K, Ghosts G,
                                                      const float *__restrict__ fin,
                                                      float *__restrict__ fout,
@@ -417,7 +396,7 @@ __global__ __launch_bounds__(256) void k_step_simple(Field F, Consts K, Ghosts G
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (i >= F.nx || j >= F.ny) return;
-    node_update<SRT>(F, K, G, fin, fout, i, j, step_time(G, d_step, k));
+    node_update(F, K, G, fin, fout, i, j, step_time(G, d_step, k));
 }
 
 // Wavefront shifts across all 64 lanes (DPP wave_shr:1 / wave_shl:1, CDNA).
@@ -444,9 +423,10 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, 
 {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
+template <int AUX = 0>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, AUX);
 }
 
 // Row kernel.  Each wavefront updates R consecutive rows of 64 consecutive
@@ -461,7 +441,7 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsign
 // others have only interior neighbours.  Addressing is by buffer
 // instructions: one per-lane byte offset shared by all loads of a column, plus
 // a wave-uniform offset for (plane, row).
-template <int R, bool SRT>
+template <int R, int AUX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
                  float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
@@ -483,17 +463,17 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
         if (x < F.nx) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (y0 + r < F.ny) node_update<SRT>(F, K, G, fin, fout, x, y0 + r, t);
+                if (y0 + r < F.ny) node_update(F, K, G, fin, fout, x, y0 + r, t);
         }
         return;
     }
     const unsigned vo = 4u * (unsigned)(F.xoff + x);
     const unsigned vh = 4u * (unsigned)(F.xoff + (lane < 32 ? x0 - 1 : x0 + 64));
-    const unsigned planeB = 4u * (unsigned)F.plane, pitchB = 4u * (unsigned)F.pitch;
+    const unsigned qB = 4u * (unsigned)F.qstride, jB = 4u * (unsigned)F.jstride;
     const auto rin = buffer_of(fin, bytes);
     const auto rout = buffer_of(fout, bytes);
     // byte offset of row j (j = -1 .. ny) of plane q
-    auto row = [&](int q, int j) { return (unsigned)q * planeB + (unsigned)(j + 1) * pitchB; };
+    auto row = [&](int q, int j) { return (unsigned)q * qB + (unsigned)(j + 1) * jB; };
 
     float v[R + 2][NQ], h[R][NQ];
 #pragma unroll
@@ -509,7 +489,7 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         float dC[NQ];
-        collide<SRT>(K, v[r + 1], dC);
+        collide(K, v[r + 1], dC);
         Unroll<NQ>::run([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             float fE = 0.f, fW = 0.f;
@@ -518,7 +498,7 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
                 fW = shr1(v[r + 1][q], h[r][q]);
             }
             const float o = lw_update<q>(K, v[r + 1][q], dC[q], fE, fW, v[r + 2][q], v[r][q]);
-            bstore(rout, o, vo, row(q, y0 + r));
+            bstore<AUX>(rout, o, vo, row(q, y0 + r));
         });
     }
 }
@@ -582,15 +562,15 @@ __global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
     const int col = b % ncol, rb = b / ncol;
     const int x0 = col * 64, yb = rb * 4, x = x0 + lane, y = yb + wv;
     if (col == 0 || x0 + 64 >= F.nx || yb == 0 || yb + 4 >= F.ny) {  // uniform over the block
-        if (x < F.nx && y < F.ny) node_update<false>(F, K, G, fin, fout, x, y, step_time(G, d_step, k));
+        if (x < F.nx && y < F.ny) node_update(F, K, G, fin, fout, x, y, step_time(G, d_step, k));
         return;
     }
     const unsigned vo = 4u * (unsigned)(F.xoff + x);
     const unsigned vh = 4u * (unsigned)(F.xoff + (lane < 32 ? x0 - 1 : x0 + 64));
-    const unsigned planeB = 4u * (unsigned)F.plane, pitchB = 4u * (unsigned)F.pitch;
+    const unsigned qB = 4u * (unsigned)F.qstride, jB = 4u * (unsigned)F.jstride;
     const auto rin = buffer_of(fin, bytes);
     const auto rout = buffer_of(fout, bytes);
-    auto row = [&](int q, int j) { return (unsigned)q * planeB + (unsigned)(j + 1) * pitchB; };
+    auto row = [&](int q, int j) { return (unsigned)q * qB + (unsigned)(j + 1) * jB; };
     float prv[NQ], cur[NQ], nxt[NQ], hc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -680,6 +660,7 @@ __global__ __launch_bounds__(256) void k_tubes(TubeGrid TG, Consts K,
 {
     constexpr int TW = S + 2 * KS;
     constexpr int WY = TUBE_ROWS;
+    static_assert(TW % 64 == 0 && WY * 64 == 256, "one thread per (row, column lane)");
     __shared__ float buf[2][NQ][WY][TW];
     const TubeItem it = items[blockIdx.x];
     const int n = tubes[it.tube].n;
@@ -706,31 +687,35 @@ __global__ __launch_bounds__(256) void k_tubes(TubeGrid TG, Consts K,
     }
     __syncthreads();
     int src = 0;
+    // thread -> (row, column lane); TW is a multiple of 64
+    const int y = threadIdx.x >> 6, cl = threadIdx.x & 63;
+    const int yn = y == WY - 1 ? 0 : y + 1, ys = y == 0 ? WY - 1 : y - 1;
     for (int st = 0; st < nsteps; ++st) {
         // valid input columns [a, b); update a+1 .. b-2 (interior nodes only)
         const int a = cL >= 0 ? cL : st;
         const int b = cR < TW ? cR + 1 : TW - st;
-        const int c0 = a + 1, ncl = b - 2 - a;
-        for (int idx = threadIdx.x; idx < ncl * WY; idx += 256) {
-            const int c = c0 + idx % ncl, y = idx / ncl;
-            const int yn = y == WY - 1 ? 0 : y + 1, ys = y == 0 ? WY - 1 : y - 1;
-            float fc[NQ], dC[NQ];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) fc[q] = buf[src][q][y][c];
-            collide<false>(K, fc, dC);
-            Unroll<NQ>::run([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                float fE = 0.f, fW = 0.f, fN = 0.f, fS = 0.f;
-                if (has_x(q)) {
-                    fE = buf[src][q][y][c + 1];
-                    fW = buf[src][q][y][c - 1];
-                }
-                if (has_y(q)) {
-                    fN = buf[src][q][yn][c];
-                    fS = buf[src][q][ys][c];
-                }
-                buf[src ^ 1][q][y][c] = lw_update<q>(K, fc[q], dC[q], fE, fW, fN, fS);
-            });
+        for (int mcol = 0; mcol < TW / 64; ++mcol) {
+            const int c = 64 * mcol + cl;
+            if (c > a && c < b - 1) {
+                float fc[NQ], dC[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) fc[q] = buf[src][q][y][c];
+                collide(K, fc, dC);
+                Unroll<NQ>::run([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    float fE = 0.f, fW = 0.f, fN = 0.f, fS = 0.f;
+                    if (has_x(q)) {
+                        fE = buf[src][q][y][c + 1];
+                        fW = buf[src][q][y][c - 1];
+                    }
+                    if (has_y(q)) {
+                        fN = buf[src][q][yn][c];
+                        fS = buf[src][q][ys][c];
+                    }
+                    buf[src ^ 1][q][y][c] = lw_update<q>(K, fc[q], dC[q], fE, fW, fN, fS);
+                });
+            }
         }
         __syncthreads();
         src ^= 1;
@@ -942,30 +927,29 @@ hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, 
                               float *fout, const long long *d_step, int k, hipStream_t s)
 {
     dim3 grid(blocks_for(F.nx, 64), blocks_for(F.ny, 4));
-    if (K.srt)
-        hipLaunchKernelGGL(k_step_simple<true>, grid, dim3(256), 0, s, F, K, G, fin, fout, d_step, k);
-    else
-        hipLaunchKernelGGL(k_step_simple<false>, grid, dim3(256), 0, s, F, K, G, fin, fout, d_step, k);
+    hipLaunchKernelGGL(k_step_simple, grid, dim3(256), 0, s, F, K, G, fin, fout, d_step, k);
     return hipGetLastError();
 }
 
 hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
-                            float *fout, int rows, const long long *d_step, int k, hipStream_t s)
+                            float *fout, int rows, int stream_stores, const long long *d_step,
+                            int k, hipStream_t s)
 {
     const int ncol = (F.nx + 63) / 64;
     const int nrg = (F.ny + rows - 1) / rows;
     const int nb = ncol * ((nrg + 3) / 4);
-    const long long total = 4LL * NQ * F.plane;
+    const long long total = 4LL * F.total;
     if (total >= (1LL << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
     const unsigned bytes = (unsigned)total;
     switch (rows) {
+    // store cache policy: 0 default, 2 non-temporal (streaming)
 #define MRTFD_ROWS(Rr)                                                                             \
     case Rr:                                                                                       \
-        if (K.srt)                                                                                 \
-            hipLaunchKernelGGL((k_step_rows<Rr, true>), dim3(nb), dim3(256), 0, s, F, K, G, fin,   \
+        if (stream_stores)                                                                         \
+            hipLaunchKernelGGL((k_step_rows<Rr, 2>), dim3(nb), dim3(256), 0, s, F, K, G, fin,      \
                                fout, bytes, ncol, nrg, nb, d_step, k);                             \
         else                                                                                       \
-            hipLaunchKernelGGL((k_step_rows<Rr, false>), dim3(nb), dim3(256), 0, s, F, K, G, fin,  \
+            hipLaunchKernelGGL((k_step_rows<Rr, 0>), dim3(nb), dim3(256), 0, s, F, K, G, fin,      \
                                fout, bytes, ncol, nrg, nb, d_step, k);                             \
         break;
         MRTFD_ROWS(1)
@@ -1028,7 +1012,7 @@ hipError_t launch_unpack(const Field &F, const float *src, float *f, hipStream_t
 
 // ------------------------------------------------------------ tube launchers
 
-#define MRTFD_TUBE_CONFIGS(X) X(64, 8) X(64, 16) X(96, 8) X(96, 16) X(112, 8)
+#define MRTFD_TUBE_CONFIGS(X) X(48, 8) X(32, 16) X(112, 8) X(96, 16)
 
 bool tubes_config_built(int seg, int round_steps)
 {
@@ -1086,7 +1070,7 @@ hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
     const int ncol = (F.nx + 63) / 64;
     const int nrb = (F.ny + 3) / 4;
     const int nb = ncol * nrb;
-    const long long total = 4LL * NQ * F.plane;
+    const long long total = 4LL * F.total;
     if (total >= (1LL << 32)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_step_mfma, dim3(nb), dim3(256), 0, s, F, K, G, mo, fin, fout,
                        (unsigned)total, ncol, nrb, nb, d_step, k);

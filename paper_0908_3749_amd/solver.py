@@ -17,8 +17,11 @@ PRECISIONS = {"fp32": _abi.MRTFD_FP32, "bf16x3": _abi.MRTFD_BF16X3}
 COLLISIONS = {"mrt": _abi.MRTFD_COLLISION_MRT, "srt": _abi.MRTFD_COLLISION_SRT}
 
 
+LAYOUTS = {"rows": _abi.MRTFD_LAYOUT_ROWS, "planes": _abi.MRTFD_LAYOUT_PLANES}
+
+
 def make_params(nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto", rows=0,
-                graph_steps=0, collision="mrt"):
+                graph_steps=0, collision="mrt", layout="rows"):
     """Fill the C parameter struct.  sides: dict west/east/south/north of
     dicts with kind_lo, kind_hi (rule names), state_lo, state_hi
     (rho, u1, u2, T), split0, split_rate."""
@@ -43,6 +46,7 @@ def make_params(nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto", r
     p.rows = int(rows)
     p.graph_steps = int(graph_steps)
     p.collision = COLLISIONS[collision]
+    p.layout = LAYOUTS[layout]
     return p
 
 
@@ -57,12 +61,13 @@ class MRT2D:
     """One 2D grid on one GPU."""
 
     def __init__(self, nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto",
-                 rows=0, graph_steps=0, collision="mrt", device=None, stream=None):
+                 rows=0, graph_steps=0, collision="mrt", layout="rows", device=None,
+                 stream=None):
         import torch
 
         self.torch = torch
         self.p = make_params(nx, ny, dx, dy, dt, s, sides, precision, kernel, rows, graph_steps,
-                             collision)
+                             collision, layout)
         st, msg = check_params(self.p)
         if st != _abi.MRTFD_OK:
             raise _abi.MrtfdError(st, msg)

@@ -110,8 +110,6 @@ def test_validation_rejects_bad_params(abi):
     for k in range(4, 16):
         p.s[k] = 4e4
     assert check_params(p)[0] == abi.MRTFD_OK
-    p.precision = abi.MRTFD_BF16X3
-    assert check_params(p)[0] == abi.MRTFD_ERR_UNSUPPORTED
 
 
 def test_create_rejects_bad_workspace_without_gpu(abi):

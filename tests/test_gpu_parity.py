@@ -250,25 +250,37 @@ def test_init_matches_oracle(gpu, state):
     assert np.all(ratio <= 64), ratio
 
 
+def transform_scale(prob, f):
+    """max over nodes and populations of (|dt M^-1| |S| |M| |f|)_i + max_q |f_q|:
+    the magnitude that the FP32 collision of a node cancels down from (the
+    moments m_k = sum M_kq f_q and their equilibria, mapped back by dt M^-1 S),
+    plus the node's own populations."""
+    m = core.model()
+    A = np.abs(m.Minv) * prob.dt @ np.diag(np.abs(prob.s)) @ np.abs(m.M)
+    af = np.einsum("ik,kyx->iyx", A, np.abs(f))
+    return float(np.max(af + np.max(np.abs(f), axis=0, keepdims=True)))
+
+
 @pytest.mark.parametrize("config", ["mach3", "bubble"])
 def test_full_size_steps_match_oracle(gpu, config):
     """At the benchmark's full sizes (2048x512 Mach reflection, 4096x1024
     shock-bubble) and in its launch configuration (autotuned kernel, graph
     of 64 steps): a few steps from the oracle's initial state (rounded to
     FP32) agree with the whole-grid FP64 oracle node by node, within
-    8 u max|f| per step (the emulated FP32 node update errs by about 2 u
-    max|f|, the stored result by another 0.5 u)."""
+    4 n u S after n steps, S = transform_scale (each step's rounding is a few
+    u of the magnitudes the collision cancels)."""
     prob = synth.mach_reflection() if config == "mach3" else synth.shock_bubble()
     n = 4 if config == "mach3" else 2
     o = core.Grid(prob, nthreads=THREADS)
     o.init_problem()
     f0 = o.get_f().astype(np.float32)
     o.set_f(f0.astype(np.float64))
+    scale = transform_scale(prob, o.get_f())
     o.run(n)
     want = o.get_f()
     got, _, info = run_gpu(gpu, prob, f0, n, graph_steps=64)
     err = np.max(np.abs(got - want))
-    bound = 8 * n * U32 * np.max(np.abs(want))
+    bound = 4 * n * U32 * scale
     print(f"full size {config} {info}: max err {err:.3e}, bound {bound:.3e}")
     assert err <= bound
 
@@ -319,8 +331,10 @@ def test_couette_strip(gpu):
     print("couette 16x256 1000 steps rel L1", errs, "u Linf", metrics.linf(got["ux"], want["ux"]))
     for k in ("rho", "p"):
         assert errs[k] <= 1e-5, (k, errs[k])
-    assert metrics.linf(got["ux"], want["ux"]) <= 1e-6
-    assert metrics.linf(got["uy"], want["uy"]) <= 1e-6
+    # u = j / rho: j rounds by ~u sum_i |v_i f_i| ~ 2e-7 per step, and the
+    # errors of 1000 steps add up like a random walk (~30x)
+    assert metrics.linf(got["ux"], want["ux"]) <= 1e-5
+    assert metrics.linf(got["uy"], want["uy"]) <= 1e-5
 
 
 def test_bf16x3_one_step_error_bound(gpu):
@@ -362,11 +376,10 @@ def test_bf16x3_couette_strip(gpu):
 
 
 def test_single_relaxation_time_mode(gpu):
-    """S = I / tau (Sect. II): the SRT path, s (f - f^eq) in velocity space,
-    matches the oracle's collision with all rates equal (which is the same
-    operator, Eq. 3 with S-hat = I / tau) within the FP32 bounds, one step and
-    300 steps; and it agrees with the MRT path at equal rates to FP32
-    rounding."""
+    """S = I / tau (Sect. II): the single-relaxation-time mode is Eq. (3) with
+    all rates equal -- bit for bit the MRT path with equal rates -- and it
+    matches the oracle within the FP32 bounds (one step from arbitrary
+    populations; 300 steps of smooth flow)."""
     nx, ny = 150, 37
     s_all = [0.0] * 4 + [1e5] * 12
     f0 = synth.random_populations(nx, ny, seed=21)
@@ -374,13 +387,13 @@ def test_single_relaxation_time_mode(gpu):
     want, _ = run_oracle(prob, f0, 1)
     srt, _, _ = run_gpu(gpu, prob, f0, 1, collision="srt")
     mrt, _, _ = run_gpu(gpu, prob, f0, 1, collision="mrt")
-    e1 = np.max(np.abs(srt - want)) / np.max(np.abs(want))
-    e2 = np.max(np.abs(srt - mrt)) / np.max(np.abs(want))
-    print(f"srt one step: vs oracle {e1:.2e}, vs mrt path {e2:.2e}")
-    assert e1 <= 2e-6 and e2 <= 2e-6
+    assert np.array_equal(srt, mrt)
+    assert np.max(np.abs(srt - want)) <= 2e-6 * np.max(np.abs(want))
     ic = synth.smooth_macro(nx, ny, seed=3, du=0.2, dr=0.1)
     prob = synth.generic(nx, ny, 2e-3, 1e-5, s_all, SIDE_SETS["periodic"], ic)
     _, want = run_oracle(prob, None, 300)
     _, got, _ = run_gpu(gpu, prob, None, 300, collision="srt")
-    for k in ("rho", "ux", "uy", "p"):
-        assert metrics.rel_l1(got[k], want[k]) <= 1e-5, k
+    errs = {k: metrics.rel_l1(got[k], want[k]) for k in ("rho", "ux", "uy", "p")}
+    print("srt 300 steps rel L1", errs)
+    for k, v in errs.items():
+        assert v <= 1e-5, (k, v)
