@@ -152,7 +152,7 @@ def kernel_sha():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_entry(workload, kernel, seg, per_launch_cells):
+def traffic_entry(workload, kernel, seg, streaming, per_launch_cells):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel source, this workload and kernel variant."""
     try:
@@ -162,7 +162,8 @@ def traffic_entry(workload, kernel, seg, per_launch_cells):
         return None
     for e in rec.get("entries", []):
         if (e.get("source_sha") == kernel_sha() and e.get("workload") == workload
-                and e.get("kernel") == kernel and int(e.get("rows", 0)) == int(seg)):
+                and e.get("kernel") == kernel and int(e.get("rows", 0)) == int(seg)
+                and bool(e.get("streaming", False)) == bool(streaming)):
             fetch = e["fetch_kib_per_dispatch"] * 1024 * e["copy_factor_fetch"]
             write = e["write_kib_per_dispatch"] * 1024 * e["copy_factor_write"]
             return {"bytes_per_launch": fetch + write,
@@ -181,7 +182,7 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
     ap.add_argument("--layout", default="rows", choices=["rows", "planes"])
-    ap.add_argument("--cpu-steps", type=int, default=12000, help="oracle steps on the crop")
+    ap.add_argument("--cpu-steps", type=int, default=40000, help="oracle steps on the crop")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-graph", action="store_true", help="tubes: launch rounds directly")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -246,13 +247,14 @@ def main():
     ms_step = ms_total / steps
     mlups = cells * steps / (ms_total * 1e-3) / 1e6
     sums = g.sums()
-    kernel, seg = g.kernel_info()
+    kernel, seg, streaming = g.kernel_details()
     k_ms = g.kernel_time(50)
     g.close()
     achieved = BYTES_PER_UPDATE * cells / (k_ms * 1e-3) / 1e9
-    traffic = traffic_entry(W["name"], kernel, seg, cells)
+    traffic = traffic_entry(W["name"], kernel, seg, streaming, cells)
     print(f"bench: {W['name']} {steps} steps, {ms_step * 1e3:.2f} us/step, step kernel {kernel}"
-          f"/{seg} {k_ms * 1e3:.2f} us/launch, {mlups:.0f} MLUPS", file=sys.stderr, flush=True)
+          f"/{seg}{'/nt' if streaming else ''} {k_ms * 1e3:.2f} us/launch, {mlups:.0f} MLUPS",
+          file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -269,7 +271,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": W["name"], "nx": prob.nx, "ny": prob.ny, "dt": prob.dt,
                    "precision": args.precision, "layout": args.layout,
-                   "kernel": kernel, "rows": seg, "graph_steps": args.graph_steps,
+                   "kernel": kernel, "rows": seg, "streaming_stores": streaming,
+                   "graph_steps": args.graph_steps,
                    "gamma": 2.0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

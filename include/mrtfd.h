@@ -93,6 +93,8 @@ extern "C" {
                                  read from memory                              */
 #define MRTFD_KERNEL_ROWS 2   /* each wave: `rows` rows of 64 columns loaded
                                  once, west/east neighbours by lane shifts     */
+#define MRTFD_KERNEL_MFMA 3   /* reported only: the matrix-core kernel that
+                                 MRTFD_BF16X3 always uses                      */
 
 /* One side of the grid.  The rule is kind_lo at ghost nodes whose
  * along-side coordinate (x for the south/north sides, y for west/east) is
@@ -187,10 +189,9 @@ int32_t mrtfd_time(mrtfd_ctx *ctx, int64_t *step, double *t);
  * where they stopped. */
 int32_t mrtfd_set_step(mrtfd_ctx *ctx, int64_t step);
 
-/* The step kernel actually used (MRTFD_KERNEL_SIMPLE, _ROWS, or 3 for the
- * matrix-core kernel of MRTFD_BF16X3) and its rows per wave, after
- * autotuning (host outputs, may be NULL). */
-int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows);
+/* The step kernel actually used (MRTFD_KERNEL_SIMPLE, _ROWS or _MFMA), its rows per wave, and 1 if it writes with streaming (non-temporal)
+ * stores, else 0 -- after autotuning (host outputs, each may be NULL). */
+int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_t *streaming);
 
 /* Average duration in milliseconds of one launch of the step kernel alone
  * (without the boundary-node kernel), timed with HIP events over nlaunch >= 1

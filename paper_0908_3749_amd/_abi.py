@@ -39,6 +39,7 @@ MRTFD_COLLISION_SRT = 1
 MRTFD_KERNEL_AUTO = 0
 MRTFD_KERNEL_SIMPLE = 1
 MRTFD_KERNEL_ROWS = 2
+MRTFD_KERNEL_MFMA = 3
 
 
 class mrtfd_side(C.Structure):
@@ -85,7 +86,8 @@ _PROTOS = {
     "mrtfd_set_f": (C.c_int32, [_vp, _fp]),
     "mrtfd_time": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "mrtfd_set_step": (C.c_int32, [_vp, C.c_int64]),
-    "mrtfd_kernel_info": (C.c_int32, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "mrtfd_kernel_info": (C.c_int32, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]),
     "mrtfd_kernel_time": (C.c_int32, [_vp, C.c_int32, C.POINTER(C.c_double)]),
     "mrtfd_model": (C.c_int32, [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "mrtfd_struct_sizes": (C.c_int32, [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),

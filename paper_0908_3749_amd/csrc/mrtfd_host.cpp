@@ -348,7 +348,8 @@ int check(const mrtfd_params *p, char *msg, size_t len)
     }
     if (p->layout != MRTFD_LAYOUT_ROWS && p->layout != MRTFD_LAYOUT_PLANES)
         return fail(MRTFD_ERR_ARG, "unknown layout %d", p->layout);
-    if (p->kernel < MRTFD_KERNEL_AUTO || p->kernel > MRTFD_KERNEL_ROWS)
+    if (p->kernel != MRTFD_KERNEL_AUTO && p->kernel != MRTFD_KERNEL_SIMPLE &&
+        p->kernel != MRTFD_KERNEL_ROWS)
         return fail(MRTFD_ERR_ARG, "unknown kernel %d", p->kernel);
     if (p->rows != 0 && p->rows != 1 && p->rows != 2)
         return fail(MRTFD_ERR_ARG, "rows must be 0, 1 or 2");
@@ -554,10 +555,10 @@ int autotune(mrtfd_ctx *c)
         }
     }
     std::vector<std::pair<int, int>> cands;
+    // second: rows per wave, and (bit 4) streaming stores
     if (c->p.kernel == MRTFD_KERNEL_SIMPLE) {
         cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     } else {
-        // rows per wave, and (bit 4) streaming stores
         for (int r = 1; r <= 2; ++r) {
             if (c->p.rows && r != c->p.rows) continue;
             cands.push_back({MRTFD_KERNEL_ROWS, r});
@@ -730,7 +731,7 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         c->seg = p->rows;
     }
     if (p->precision == MRTFD_BF16X3) {
-        c->kernel = MRTFD_KERNEL_ROWS + 1;  // the matrix-core kernel (see launch_step)
+        c->kernel = MRTFD_KERNEL_MFMA;
         c->seg = 1;
     }
     hipError_t e = hipGetDevice(&c->device);
@@ -889,11 +890,12 @@ int32_t mrtfd_kernel_time(mrtfd_ctx *c, int32_t n, double *ms)
     return MRTFD_OK;
 }
 
-int32_t mrtfd_kernel_info(mrtfd_ctx *c, int32_t *kernel, int32_t *rows)
+int32_t mrtfd_kernel_info(mrtfd_ctx *c, int32_t *kernel, int32_t *rows, int32_t *streaming)
 {
     if (!c) return MRTFD_ERR_ARG;
     if (kernel) *kernel = c->kernel;
     if (rows) *rows = c->seg & 15;
+    if (streaming) *streaming = (c->seg >> 4) & 1;
     return MRTFD_OK;
 }
 

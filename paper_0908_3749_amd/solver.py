@@ -11,6 +11,8 @@ from ._abi import check, lib
 SIDES = ("west", "east", "south", "north")
 KERNELS = {"auto": _abi.MRTFD_KERNEL_AUTO, "simple": _abi.MRTFD_KERNEL_SIMPLE,
            "rows": _abi.MRTFD_KERNEL_ROWS}
+KERNEL_NAMES = {_abi.MRTFD_KERNEL_SIMPLE: "simple", _abi.MRTFD_KERNEL_ROWS: "rows",
+                _abi.MRTFD_KERNEL_MFMA: "mfma"}
 PRECISIONS = {"fp32": _abi.MRTFD_FP32, "bf16x3": _abi.MRTFD_BF16X3}
 
 
@@ -157,10 +159,14 @@ class MRT2D:
         check(lib().mrtfd_set_step(self._ctx, int(step)), self._ctx)
 
     def kernel_info(self):
-        k = C.c_int32()
-        s = C.c_int32()
-        check(lib().mrtfd_kernel_info(self._ctx, C.byref(k), C.byref(s)), self._ctx)
-        return {1: "simple", 2: "rows", 3: "mfma"}.get(k.value, "none"), s.value
+        """(kernel name, rows per wave) of the step kernel in use."""
+        return self.kernel_details()[:2]
+
+    def kernel_details(self):
+        """(kernel name, rows per wave, streaming stores) of the step kernel."""
+        k, s, st = C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().mrtfd_kernel_info(self._ctx, C.byref(k), C.byref(s), C.byref(st)), self._ctx)
+        return KERNEL_NAMES.get(k.value, "none"), s.value, bool(st.value)
 
     def kernel_time(self, nlaunch=20):
         """Average milliseconds per launch of the step kernel alone."""
