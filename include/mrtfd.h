@@ -162,7 +162,8 @@ int32_t mrtfd_init_macro(mrtfd_ctx *ctx, const float *d_rho, const float *d_ux,
 
 /* Advance nsteps >= 0 time steps (each: boundary nodes at time t_n = n dt
  * from f^n, then the fused collision + Lax-Wendroff + Euler update of every
- * interior node). */
+ * interior node).  While the kernel choice is open (see mrtfd_kernel_info)
+ * the first steps of a long enough call time the candidate variants. */
 int32_t mrtfd_step(mrtfd_ctx *ctx, int64_t nsteps);
 
 /* Macroscopic fields of the current state: rho = f-hat_1, u = j / rho,
@@ -189,16 +190,15 @@ int32_t mrtfd_time(mrtfd_ctx *ctx, int64_t *step, double *t);
  * where they stopped. */
 int32_t mrtfd_set_step(mrtfd_ctx *ctx, int64_t step);
 
-/* The step kernel actually used (MRTFD_KERNEL_SIMPLE, _ROWS or _MFMA), its rows per wave, and 1 if it writes with streaming (non-temporal)
- * stores, else 0 -- after autotuning (host outputs, each may be NULL). */
+/* The step kernel in use (MRTFD_KERNEL_SIMPLE, _ROWS or _MFMA), its rows
+ * per wave, and 1 if it writes with streaming (non-temporal) stores, else 0
+ * (host outputs, each may be NULL).  With MRTFD_KERNEL_AUTO, or _ROWS and
+ * rows = 0, the choice is made by timing the candidates on the first steps
+ * of the first mrtfd_step call long enough for a fair trial (a few dozen
+ * steps; results are bit-identical whichever runs) and is cached per grid
+ * size for later contexts; before that the rows kernel with one row per wave
+ * and plain stores runs. */
 int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_t *streaming);
-
-/* Average duration in milliseconds of one launch of the step kernel alone
- * (without the boundary-node kernel), timed with HIP events over nlaunch >= 1
- * back-to-back launches on the context's stream.  The trial launches read
- * the current state and write the spare copy, which the next step
- * overwrites, so the state is unchanged.  Synchronises the stream. */
-int32_t mrtfd_kernel_time(mrtfd_ctx *ctx, int32_t nlaunch, double *ms_per_launch);
 
 /* The library's FP64 model on the host: velocity set v[16][2] (Eq. 4), M
  * [16][16] (Eq. 5, row-major, M[k][i] = m_{k+1}(v_i)) and its inverse, as

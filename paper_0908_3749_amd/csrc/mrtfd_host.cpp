@@ -462,7 +462,8 @@ struct mrtfd_ctx {
     int cur = 0;                 // which copy holds the state
     long long step = 0;
     bool initialised = false;
-    int kernel = 0, seg = 0;     // chosen step kernel and its rows per wave
+    int kernel = 0, seg = 0;     // step kernel in use and its rows per wave
+    bool tuned = false;          // kernel/seg final (explicit, cached or timed)
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // by starting copy
     char err[512] = {0};
 };
@@ -538,12 +539,32 @@ int build_graph(mrtfd_ctx *c, int start)
     return MRTFD_OK;
 }
 
-// Pick the step kernel by timing each candidate for a few steps.  Trials read
-// the current copy and write the other one, which the next real step
-// overwrites, so the state is untouched.
-int autotune(mrtfd_ctx *c)
+// Advance the state by n direct launches (no graph).
+hipError_t direct_steps(mrtfd_ctx *c, long long n)
 {
-    if (c->kernel) return MRTFD_OK;
+    while (n > 0) {
+        const int k = (int)std::min<long long>(n, 1 << 20);
+        hipError_t e = enqueue_steps(c, c->cur, k, c->stream);
+        if (e != hipSuccess) return e;
+        if (k & 1) c->cur ^= 1;
+        c->step += k;
+        n -= k;
+    }
+    return hipSuccess;
+}
+
+// Pick the step kernel by timing each candidate on steps of the run itself.
+// Every variant computes the same bits, so trial steps are ordinary steps;
+// and timing them in the real alternation between the two copies sees the
+// caches as a long run does (repeated launches on one input would not: the
+// output of streaming stores, which bypass the last-level cache, is then
+// never read back).  Uses up to `avail` steps and reports how many it took
+// in *taken.  When `avail` is too short for a fair trial the default variant
+// stays in place and tuning waits for a longer call.
+int autotune(mrtfd_ctx *c, long long avail, long long *taken)
+{
+    *taken = 0;
+    if (c->tuned) return MRTFD_OK;
     const TuneKey key{c->p.nx, c->p.ny, c->p.layout, c->p.kernel, c->p.rows};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -551,6 +572,7 @@ int autotune(mrtfd_ctx *c)
         if (it != g_tune.end()) {
             c->kernel = it->second.first;
             c->seg = it->second.second;
+            c->tuned = true;
             return MRTFD_OK;
         }
     }
@@ -566,26 +588,28 @@ int autotune(mrtfd_ctx *c)
         }
         if (c->p.kernel == MRTFD_KERNEL_AUTO) cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     }
+    c->kernel = cands[0].first;
+    c->seg = cands[0].second;
     if (cands.size() == 1) {
-        c->kernel = cands[0].first;
-        c->seg = cands[0].second;
+        c->tuned = true;
         return MRTFD_OK;
     }
+    const double cells = (double)c->p.nx * c->p.ny;
+    const long long reps = 2 * (long long)std::max(2.0, std::min(16.0, 1e7 / cells));
+    const long long warm = 2;
+    if (avail < (long long)cands.size() * (reps + warm)) return MRTFD_OK;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    const double cells = (double)c->p.nx * c->p.ny;
-    const int reps = (int)std::max(3.0, std::min(50.0, 2e7 / cells));
     float best = 1e30f;
     std::pair<int, int> pick = cands[0];
     int rc = MRTFD_OK;
     for (auto cand : cands) {
         c->kernel = cand.first;
         c->seg = cand.second;
-        hipError_t e = launch_step(c, c->f[c->cur], c->f[c->cur ^ 1], 0, c->stream);  // warm-up
+        hipError_t e = direct_steps(c, warm);
         e = e == hipSuccess ? hipEventRecord(e0, c->stream) : e;
-        for (int r = 0; r < reps && e == hipSuccess; ++r)
-            e = launch_step(c, c->f[c->cur], c->f[c->cur ^ 1], 0, c->stream);
+        e = e == hipSuccess ? direct_steps(c, reps) : e;
         e = e == hipSuccess ? hipEventRecord(e1, c->stream) : e;
         e = e == hipSuccess ? hipEventSynchronize(e1) : e;
         float ms = 0.f;
@@ -594,6 +618,7 @@ int autotune(mrtfd_ctx *c)
             rc = set_err(c, MRTFD_ERR_HIP, "autotune: %s", hipGetErrorString(e));
             break;
         }
+        *taken += warm + reps;
         if (ms < best) {
             best = ms;
             pick = cand;
@@ -604,6 +629,7 @@ int autotune(mrtfd_ctx *c)
     c->kernel = pick.first;
     c->seg = pick.second;
     if (rc == MRTFD_OK) {
+        c->tuned = true;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[key] = pick;
     }
@@ -726,13 +752,17 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
             for (int q = 0; q < NQ; ++q) g.feq_hi[q] = (float)fe[q];
         }
     }
+    // default until tuned: rows kernel, one row per wave, plain stores
+    c->kernel = p->kernel == MRTFD_KERNEL_SIMPLE ? MRTFD_KERNEL_SIMPLE : MRTFD_KERNEL_ROWS;
+    c->seg = p->kernel == MRTFD_KERNEL_SIMPLE ? 0 : 1;
     if (p->kernel == MRTFD_KERNEL_ROWS && p->rows) {
-        c->kernel = MRTFD_KERNEL_ROWS;
         c->seg = p->rows;
+        c->tuned = true;
     }
     if (p->precision == MRTFD_BF16X3) {
         c->kernel = MRTFD_KERNEL_MFMA;
         c->seg = 1;
+        c->tuned = true;
     }
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
@@ -795,11 +825,13 @@ int32_t mrtfd_step(mrtfd_ctx *c, int64_t nsteps)
     if (nsteps < 0) return set_err(c, MRTFD_ERR_ARG, "nsteps must be >= 0");
     if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "step before init");
     if (nsteps == 0) return MRTFD_OK;
-    if (!c->kernel) {
-        int rc = autotune(c);
-        if (rc != MRTFD_OK) return rc;
-    }
     long long left = nsteps;
+    if (!c->tuned) {
+        long long taken = 0;
+        int rc = autotune(c, left, &taken);
+        if (rc != MRTFD_OK) return rc;
+        left -= taken;
+    }
     const int G = c->p.graph_steps;
     if (G > 0) {
         while (left >= G) {
@@ -812,13 +844,7 @@ int32_t mrtfd_step(mrtfd_ctx *c, int64_t nsteps)
             c->step += G;
         }
     }
-    while (left > 0) {
-        const int n = (int)std::min<long long>(left, 1 << 20);
-        HIPCHK(c, enqueue_steps(c, c->cur, n, c->stream));
-        if (n & 1) c->cur ^= 1;
-        left -= n;
-        c->step += n;
-    }
+    HIPCHK(c, direct_steps(c, left));
     return MRTFD_OK;
 }
 
@@ -861,32 +887,6 @@ int32_t mrtfd_set_step(mrtfd_ctx *c, int64_t step)
     if (step < 0) return set_err(c, MRTFD_ERR_ARG, "step must be >= 0");
     HIPCHK(c, launch_counter_set(c->d_step, step, c->stream));
     c->step = step;
-    return MRTFD_OK;
-}
-
-int32_t mrtfd_kernel_time(mrtfd_ctx *c, int32_t n, double *ms)
-{
-    if (!c || !ms || n < 1) return MRTFD_ERR_ARG;
-    if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "kernel_time before init");
-    if (!c->kernel) {
-        int rc = autotune(c);
-        if (rc != MRTFD_OK) return rc;
-    }
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
-    hipError_t e = launch_step(c, c->f[c->cur], c->f[c->cur ^ 1], 0, c->stream);
-    e = e == hipSuccess ? hipEventRecord(e0, c->stream) : e;
-    for (int r = 0; r < n && e == hipSuccess; ++r)
-        e = launch_step(c, c->f[c->cur], c->f[c->cur ^ 1], 0, c->stream);
-    e = e == hipSuccess ? hipEventRecord(e1, c->stream) : e;
-    e = e == hipSuccess ? hipEventSynchronize(e1) : e;
-    float t = 0.f;
-    e = e == hipSuccess ? hipEventElapsedTime(&t, e0, e1) : e;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (e != hipSuccess) return set_err(c, MRTFD_ERR_HIP, "kernel_time: %s", hipGetErrorString(e));
-    *ms = (double)t / n;
     return MRTFD_OK;
 }
 

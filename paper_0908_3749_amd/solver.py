@@ -168,12 +168,6 @@ class MRT2D:
         check(lib().mrtfd_kernel_info(self._ctx, C.byref(k), C.byref(s), C.byref(st)), self._ctx)
         return KERNEL_NAMES.get(k.value, "none"), s.value, bool(st.value)
 
-    def kernel_time(self, nlaunch=20):
-        """Average milliseconds per launch of the step kernel alone."""
-        ms = C.c_double()
-        check(lib().mrtfd_kernel_time(self._ctx, int(nlaunch), C.byref(ms)), self._ctx)
-        return ms.value
-
     def close(self):
         if self._ctx:
             lib().mrtfd_destroy(self._ctx)

@@ -169,6 +169,36 @@ def test_graph_replay_equals_direct_launches(gpu):
     assert np.array_equal(got, ref)
 
 
+def test_autotune_trial_steps_are_ordinary_steps(gpu):
+    """The autotuner times the candidate kernels on steps of the run itself:
+    a run that tunes (grid size unique to this test, so nothing is cached)
+    equals a run with a fixed kernel bit for bit, clock and time-dependent
+    boundary split included, whether the first call is too short to tune or
+    not; afterwards the choice is final and reported."""
+    nx, ny = 141, 43
+    f0 = synth.random_populations(nx, ny, seed=6)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["wall_split"], None)
+    ref, _, _ = run_gpu(gpu, prob, f0, 401, kernel="simple")
+    g = gpu.from_problem(prob, graph_steps=16)
+    g.set_f(f0)
+    g.step(1)                      # too short to tune: default kernel
+    assert g.kernel_details() == ("rows", 1, False)
+    g.step(400)                    # tunes on its first steps
+    kern, rows, streaming = g.kernel_details()
+    step, _ = g.time()
+    got = g.get_f_numpy()
+    g.close()
+    assert step == 401
+    assert (kern, rows) in {("rows", 1), ("rows", 2), ("simple", 0)}
+    assert np.array_equal(got, ref)
+    # a second context of the same size takes the cached choice at once
+    h = gpu.from_problem(prob)
+    h.set_f(f0)
+    h.step(1)
+    assert h.kernel_details() == (kern, rows, streaming)
+    h.close()
+
+
 def test_restart_is_bitwise(gpu):
     """Checkpoint/restart: 2N steps equal N steps, get_f, a fresh context
     with set_f and the clock restored, N more steps -- bit for bit, with a
