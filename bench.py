@@ -36,13 +36,17 @@ def workloads():
     import synth
 
     return {
+        # crop: the same set-up on a grid the oracle covers in 10-30 s for
+        # cpu_steps steps (mach3: the geometry scaled by 1/4, wedge corner at
+        # nx/4 as in the full grid)
         "mach3": dict(name="mach3_reflection_2048x512", make=lambda: synth.mach_reflection(),
-                      crop=lambda: synth.mach_reflection(nx=256, ny=64, x0_cells=64), steps=20000),
+                      crop=lambda: synth.mach_reflection(nx=512, ny=128), steps=20000, cpu_steps=10000),
         "bubble": dict(name="shock_bubble_4096x1024", make=lambda: synth.shock_bubble(),
-                       crop=lambda: synth.shock_bubble(nx=512, ny=128), steps=10000),
+                       crop=lambda: synth.shock_bubble(nx=512, ny=128), steps=10000, cpu_steps=10000),
         "couette": dict(name="couette_8192x2048", make=lambda: synth.couette(),
-                        crop=lambda: synth.couette(x_window=(0, 16)), steps=50000),
-        "sod": dict(name="sod_400x4", make=lambda: synth.sod(), crop=lambda: synth.sod(), steps=10000),
+                        crop=lambda: synth.couette(x_window=(0, 16)), steps=50000, cpu_steps=20000),
+        "sod": dict(name="sod_400x4", make=lambda: synth.sod(), crop=lambda: synth.sod(), steps=10000,
+                    cpu_steps=10000),
         "tubes": dict(name="tube_batch_512", make=None, crop=None, steps=None),
     }
 
@@ -184,7 +188,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
     ap.add_argument("--layout", default="rows", choices=["rows", "planes"])
-    ap.add_argument("--cpu-steps", type=int, default=40000, help="oracle steps on the crop")
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="oracle steps on the crop (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-graph", action="store_true", help="tubes: launch rounds directly")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -291,7 +296,7 @@ def main():
         from oracle import core, metrics
 
         crop = W["crop"]()
-        n_cpu = args.cpu_steps
+        n_cpu = args.cpu_steps if args.cpu_steps is not None else W["cpu_steps"]
         gc = MRT2D.from_problem(crop, kernel=args.kernel, rows=args.rows, precision=args.precision)
         gc.init_problem(crop)
         gc.step(n_cpu)
