@@ -191,6 +191,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="oracle steps on the crop (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--flux-budget", type=int, default=1, choices=[0, 1],
+                    help="1: every step also accumulates the FP64 outflow through the sides")
     ap.add_argument("--no-graph", action="store_true", help="tubes: launch rounds directly")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only time a plain device copy of MIB MiB (the reference for the HBM "
@@ -239,8 +241,10 @@ def main():
     cells = prob.nx * prob.ny
 
     g = MRT2D.from_problem(prob, kernel=args.kernel, rows=args.rows, graph_steps=args.graph_steps,
-                           precision=args.precision, layout=args.layout)
+                           precision=args.precision, layout=args.layout,
+                           flux_budget=bool(args.flux_budget))
     g.init_problem(prob)
+    sums0 = g.sums()
     g.step(args.warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -254,6 +258,14 @@ def main():
     ms_step = ms_total / steps
     mlups = cells * steps / (ms_total * 1e-3) / 1e6
     sums = g.sums()
+    budget = None
+    if args.flux_budget:
+        out = g.outflow()
+        resid = sums - sums0 + out.sum(axis=0)
+        scale = abs(sums0) + abs(sums) + abs(out).sum(axis=0)
+        budget = {"outflow_total": [float(v) for v in out.sum(axis=0)],
+                  "residual_over_scale": [float(f"{v:.3e}") for v in resid / scale],
+                  "note": "sums(end) - sums(start) + outflow, FP64, over warm-up and timed steps"}
     kernel, seg, streaming = g.kernel_details()
     g.close()
     # One step = one launch of the step kernel (plus one single-thread clock
@@ -282,7 +294,7 @@ def main():
         "config": {"workload": W["name"], "nx": prob.nx, "ny": prob.ny, "dt": prob.dt,
                    "precision": args.precision, "layout": args.layout,
                    "kernel": kernel, "rows": seg, "streaming_stores": streaming,
-                   "graph_steps": args.graph_steps,
+                   "graph_steps": args.graph_steps, "flux_budget": bool(args.flux_budget),
                    "gamma": 2.0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -290,6 +302,7 @@ def main():
                      "kernel_us": round(k_ms * 1e3, 3),
                      "algorithmic_bytes_per_launch": BYTES_PER_UPDATE * cells},
         "fp64_sums": [float(v) for v in sums],
+        "outflow_budget": budget,
     }
 
     if not args.no_cpu:

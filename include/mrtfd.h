@@ -126,6 +126,9 @@ typedef struct mrtfd_params {
     int32_t graph_steps;/* steps per captured HIP graph, 0 = no graph        */
     int32_t collision;  /* MRTFD_COLLISION_MRT or _SRT                        */
     int32_t layout;     /* MRTFD_LAYOUT_ROWS or _PLANES (device order of f)   */
+    int32_t flux_budget;/* 1: every step also adds the FP64 outflow through
+                           each side to a running total (mrtfd_outflow); one
+                           more small kernel per step. 0: off            */
 } mrtfd_params;
 
 typedef struct mrtfd_ctx mrtfd_ctx;
@@ -184,6 +187,20 @@ int32_t mrtfd_set_f(mrtfd_ctx *ctx, const float *d_f);
 
 /* Current step index and time t = step * dt (host outputs, may be NULL). */
 int32_t mrtfd_time(mrtfd_ctx *ctx, int64_t *step, double *t);
+
+/* Outflow budget (needs flux_budget = 1).  Over the interior the
+ * difference of Eq. (A.1b) is a difference of face values, so the node sums
+ * of rho, j1, j2, e (mrtfd_sums) change in each step by minus the face
+ * values summed over the outer faces (the collision, Eq. 3, conserves them).
+ * out[4*side + k] (host, 16 doubles) = the FP64 outflow of moment k (rho,
+ * j1, j2, e) through side (west, east, south, north) summed over the steps
+ * since the last mrtfd_init_macro / mrtfd_set_f: face values taken in FP64
+ * from the FP32 populations of each step, with the step's boundary ghosts
+ * (periodic sides: the periodic image, equal and opposite on the two sides).
+ * Then sums(now) - sums(start) + sum over sides of out = 0 up to the FP32
+ * rounding of the updates.  Synchronises the stream; MRTFD_ERR_STATE if the
+ * budget is off, MRTFD_ERR_NONFINITE if a total is not finite. */
+int32_t mrtfd_outflow(mrtfd_ctx *ctx, double out[16]);
 
 /* Set the clock to step index `step` >= 0 (t = step * dt), e.g. after
  * mrtfd_set_f on a restart, so that time-dependent boundary rules carry on

@@ -63,8 +63,9 @@ def lib():
         L.orc_read_macro.argtypes = [M, P] + [_dp] * 6
         L.orc_sums.argtypes = [M, P, _dp, _dp]
         L.orc_fill_ghosts.argtypes = [M, P, _dp, C.c_double]
-        L.orc_step.argtypes = [M, P, _dp, _dp, C.c_double, C.c_int]
-        L.orc_run.argtypes = [M, P, _dp, _dp, C.c_int64, C.c_int64, C.c_int]
+        L.orc_face_outflow.argtypes = [M, P, _dp, _dp]
+        L.orc_step.argtypes = [M, P, _dp, _dp, C.c_double, C.c_int, _dp]
+        L.orc_run.argtypes = [M, P, _dp, _dp, C.c_int64, C.c_int64, C.c_int, _dp]
         _lib = L
     return _lib
 
@@ -183,6 +184,9 @@ class Grid:
         self.work = np.zeros_like(self.f)
         self.step_index = 0
         self.nthreads = int(nthreads)
+        # outflow of (rho, j1, j2, e) node sums through west, east, south,
+        # north since the last init_macro / set_f
+        self.outflow = np.zeros((4, 4))
 
     @property
     def t(self):
@@ -194,6 +198,7 @@ class Grid:
         lib().orc_init_macro(model().ref, C.byref(self.p), *[_ptr(a) for a in arrs],
                              _ptr(self.f))
         self.step_index = 0
+        self.outflow = np.zeros((4, 4))
         lib().orc_fill_ghosts(model().ref, C.byref(self.p), _ptr(self.f), 0.0)
 
     def init_problem(self):
@@ -204,6 +209,7 @@ class Grid:
         """Set the interior from a packed [16][ny][nx] array."""
         f_packed = np.asarray(f_packed, dtype=np.float64)
         self.f[1:-1, 1:-1, :] = np.moveaxis(f_packed, 0, -1)
+        self.outflow = np.zeros((4, 4))
         lib().orc_fill_ghosts(model().ref, C.byref(self.p), _ptr(self.f), self.t)
 
     def get_f(self):
@@ -212,7 +218,7 @@ class Grid:
 
     def run(self, nsteps: int):
         lib().orc_run(model().ref, C.byref(self.p), _ptr(self.f), _ptr(self.work),
-                      self.step_index, int(nsteps), self.nthreads)
+                      self.step_index, int(nsteps), self.nthreads, _ptr(self.outflow))
         self.step_index += int(nsteps)
 
     def macro(self):

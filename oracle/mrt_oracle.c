@@ -404,10 +404,64 @@ void orc_fill_ghosts(const orc_model *m, const orc_params *p, double *f, double 
 
 /* One time step: fill the boundary nodes of fin at time t, then update every
  * interior node into fout. */
+/* ------------------------------------------------------------------------
+ * Outflow through the sides (a budget for the conserved moments).  The
+ * difference of Eq. (A.1b) along x is a difference of face values,
+ *   dt [v d f/dx] = (dt/dx) (Phi(x + dx/2) - Phi(x - dx/2)),
+ *   Phi(x + dx/2) = v (f(x) + f(x+dx)) / 2 - v^2 dt (f(x+dx) - f(x)) / (2 dx),
+ * and likewise along y, so over the interior the sums of the conserved
+ * moments m_1..m_4 (rho, j, e) change in one step by minus the face values
+ * summed over the outer faces (the collision conserves them, Eq. 3).  Added
+ * to out[side*4 + k]: the outflow of m_{k+1} through side (west, east,
+ * south, north) in the step that starts from f (ghosts filled at t_n).
+ * ---------------------------------------------------------------------- */
+static double face_value(double v, double h, double dt, double f_lo, double f_hi)
+{
+    /* Phi between the node at the lower coordinate (f_lo) and the higher one */
+    return v * (f_lo + f_hi) / 2.0 - v * v * dt * (f_hi - f_lo) / (2.0 * h);
+}
+
+void orc_face_outflow(const orc_model *m, const orc_params *p, const double *f, double out[16])
+{
+    const int nx = p->nx, ny = p->ny;
+    const double dx = p->dx, dy = p->dy, dt = p->dt;
+    for (int j = 0; j < ny; ++j) {
+        const double *gw = f + cell(p, -1, j), *f0 = f + cell(p, 0, j);
+        const double *fe = f + cell(p, nx - 1, j), *ge = f + cell(p, nx, j);
+        for (int i = 0; i < NQ; ++i) {
+            const double vx = m->v[i][0];
+            if (vx == 0.0) continue;
+            const double west = -(dt / dx) * face_value(vx, dx, dt, gw[i], f0[i]);
+            const double east = (dt / dx) * face_value(vx, dx, dt, fe[i], ge[i]);
+            for (int k = 0; k < 4; ++k) {
+                out[0 * 4 + k] += m->M[k][i] * west;
+                out[1 * 4 + k] += m->M[k][i] * east;
+            }
+        }
+    }
+    for (int a = 0; a < nx; ++a) {
+        const double *gs = f + cell(p, a, -1), *f0 = f + cell(p, a, 0);
+        const double *fn = f + cell(p, a, ny - 1), *gn = f + cell(p, a, ny);
+        for (int i = 0; i < NQ; ++i) {
+            const double vy = m->v[i][1];
+            if (vy == 0.0) continue;
+            const double south = -(dt / dy) * face_value(vy, dy, dt, gs[i], f0[i]);
+            const double north = (dt / dy) * face_value(vy, dy, dt, fn[i], gn[i]);
+            for (int k = 0; k < 4; ++k) {
+                out[2 * 4 + k] += m->M[k][i] * south;
+                out[3 * 4 + k] += m->M[k][i] * north;
+            }
+        }
+    }
+}
+
+/* One step.  If outflow is not NULL the step's outflow through the sides is
+ * added to it (see orc_face_outflow). */
 void orc_step(const orc_model *m, const orc_params *p, double *fin, double *fout, double t,
-              int nthreads)
+              int nthreads, double *outflow)
 {
     orc_fill_ghosts(m, p, fin, t);
+    if (outflow) orc_face_outflow(m, p, fin, outflow);
     const int nx = p->nx, ny = p->ny;
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (int j = 0; j < ny; ++j)
@@ -418,14 +472,15 @@ void orc_step(const orc_model *m, const orc_params *p, double *fin, double *fout
 }
 
 /* nsteps steps from step index step0 (time t = n dt at step n).  f holds the
- * state on entry and on return; work is a second buffer of the same size. */
+ * state on entry and on return; work is a second buffer of the same size.
+ * outflow (16 doubles, may be NULL) accumulates the outflow of every step. */
 void orc_run(const orc_model *m, const orc_params *p, double *f, double *work, int64_t step0,
-             int64_t nsteps, int nthreads)
+             int64_t nsteps, int nthreads, double *outflow)
 {
     const size_t n = (size_t)(p->nx + 2) * (size_t)(p->ny + 2) * NQ;
     double *a = f, *b = work;
     for (int64_t k = 0; k < nsteps; ++k) {
-        orc_step(m, p, a, b, (double)(step0 + k) * p->dt, nthreads);
+        orc_step(m, p, a, b, (double)(step0 + k) * p->dt, nthreads, outflow);
         double *t = a;
         a = b;
         b = t;

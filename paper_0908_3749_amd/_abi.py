@@ -68,6 +68,7 @@ class mrtfd_params(C.Structure):
         ("precision", C.c_int32), ("kernel", C.c_int32),
         ("rows", C.c_int32), ("graph_steps", C.c_int32),
         ("collision", C.c_int32), ("layout", C.c_int32),
+        ("flux_budget", C.c_int32),
     ]
 
 
@@ -80,6 +81,7 @@ _PROTOS = {
     "mrtfd_destroy": (C.c_int32, [_vp]),
     "mrtfd_init_macro": (C.c_int32, [_vp, _fp, _fp, _fp, _fp]),
     "mrtfd_step": (C.c_int32, [_vp, C.c_int64]),
+    "mrtfd_outflow": (C.c_int32, [_vp, C.POINTER(C.c_double)]),
     "mrtfd_read_macro": (C.c_int32, [_vp, _fp, _fp, _fp, _fp, _fp]),
     "mrtfd_sums": (C.c_int32, [_vp, C.POINTER(C.c_double)]),
     "mrtfd_get_f": (C.c_int32, [_vp, _fp]),

@@ -353,6 +353,8 @@ int check(const mrtfd_params *p, char *msg, size_t len)
         return fail(MRTFD_ERR_ARG, "unknown kernel %d", p->kernel);
     if (p->rows != 0 && p->rows != 1 && p->rows != 2)
         return fail(MRTFD_ERR_ARG, "rows must be 0, 1 or 2");
+    if (p->flux_budget != 0 && p->flux_budget != 1)
+        return fail(MRTFD_ERR_ARG, "flux_budget must be 0 or 1");
     if (p->graph_steps < 0 || (p->graph_steps % 2) != 0 || p->graph_steps > 4096)
         return fail(MRTFD_ERR_ARG, "graph_steps must be even, in [0, 4096]");
     for (int s = 0; s < 4; ++s) {
@@ -401,7 +403,7 @@ Field make_field(const mrtfd_params &p)
 }
 
 struct Layout {
-    size_t fA, fB, partials, sums, step, flag, mfma, total;
+    size_t fA, fB, partials, sums, step, flag, mfma, flux, outflow, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -418,7 +420,9 @@ Layout layout(const mrtfd_params &p)
     L.step = L.sums + 256;
     L.flag = L.step + 256;
     L.mfma = L.flag + 256;
-    L.total = L.mfma + align256(sizeof(MfmaOperands));
+    L.flux = L.mfma + align256(sizeof(MfmaOperands));
+    L.outflow = L.flux + (p.flux_budget ? align256(2 * ((size_t)p.nx + p.ny) * 4 * sizeof(double)) : 0);
+    L.total = L.outflow + 256;
     return L;
 }
 
@@ -456,6 +460,8 @@ struct mrtfd_ctx {
     int *d_flag = nullptr;
     MfmaOperands *d_mfma = nullptr;
     MfmaOperands h_mfma;
+    double *flux = nullptr, *outflow = nullptr;  // outflow budget slots and totals
+    FluxCoef FC;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream used only to capture graphs
     int device = 0;
@@ -503,6 +509,10 @@ hipError_t enqueue_steps(mrtfd_ctx *c, int start, int n, hipStream_t s)
 {
     int a = start;
     for (int k = 0; k < n; ++k) {
+        if (c->p.flux_budget) {
+            hipError_t e = launch_face_flux(c->F, c->K, c->G, c->FC, c->f[a], c->flux, c->d_step, k, s);
+            if (e != hipSuccess) return e;
+        }
         hipError_t e = launch_step(c, c->f[a], c->f[a ^ 1], k, s);
         if (e != hipSuccess) return e;
         a ^= 1;
@@ -719,7 +729,17 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     c->d_step = reinterpret_cast<long long *>(c->ws + L.step);
     c->d_flag = reinterpret_cast<int *>(c->ws + L.flag);
     c->d_mfma = reinterpret_cast<MfmaOperands *>(c->ws + L.mfma);
+    c->flux = reinterpret_cast<double *>(c->ws + L.flux);
+    c->outflow = reinterpret_cast<double *>(c->ws + L.outflow);
     fill_mfma(m, *p, c->h_mfma);
+    for (int q = 0; q < NQ; ++q) {
+        const double vx = m.v[q][0], vy = m.v[q][1];
+        c->FC.cx[q][0] = p->dt / p->dx * vx / 2.0;
+        c->FC.cx[q][1] = p->dt / p->dx * vx * vx * p->dt / (2.0 * p->dx);
+        c->FC.cy[q][0] = p->dt / p->dy * vy / 2.0;
+        c->FC.cy[q][1] = p->dt / p->dy * vy * vy * p->dt / (2.0 * p->dy);
+        for (int k = 0; k < 4; ++k) c->FC.w[k][q] = m.M[k][q];
+    }
     c->stream = static_cast<hipStream_t>(stream);
     fill_consts(m, *p, c->K);
     for (int k = 0; k < 4; ++k)
@@ -796,6 +816,8 @@ int32_t mrtfd_init_macro(mrtfd_ctx *c, const float *rho, const float *ux, const 
     c->cur = 0;
     HIPCHK(c, launch_init(c->F, c->K, c->f[0], rho, ux, uy, T, c->d_flag, c->stream));
     HIPCHK(c, launch_counter_set(c->d_step, 0, c->stream));
+    if (c->p.flux_budget)
+        HIPCHK(c, hipMemsetAsync(c->flux, 0, c->L.outflow - c->L.flux, c->stream));
     c->step = 0;
     c->initialised = true;
     return MRTFD_OK;
@@ -806,6 +828,8 @@ int32_t mrtfd_set_f(mrtfd_ctx *c, const float *src)
     if (!c) return MRTFD_ERR_ARG;
     if (!src) return set_err(c, MRTFD_ERR_ARG, "set_f: NULL array");
     HIPCHK(c, launch_unpack(c->F, src, c->f[c->cur], c->stream));
+    if (c->p.flux_budget)
+        HIPCHK(c, hipMemsetAsync(c->flux, 0, c->L.outflow - c->L.flux, c->stream));
     c->initialised = true;
     return MRTFD_OK;
 }
@@ -870,6 +894,21 @@ int32_t mrtfd_sums(mrtfd_ctx *c, double out[4])
     if (flag) return set_err(c, MRTFD_ERR_ARG, "initial state had rho <= 0, T <= 0 or non-finite values");
     for (int k = 0; k < 4; ++k)
         if (!std::isfinite(h[k])) return set_err(c, MRTFD_ERR_NONFINITE, "sum %d is not finite", k);
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_outflow(mrtfd_ctx *c, double out[16])
+{
+    if (!c || !out) return MRTFD_ERR_ARG;
+    if (!c->p.flux_budget) return set_err(c, MRTFD_ERR_STATE, "outflow needs flux_budget = 1 at create");
+    if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "outflow before init");
+    HIPCHK(c, launch_flux_totals(c->p.nx, c->p.ny, c->flux, c->outflow, c->stream));
+    double h[16];
+    HIPCHK(c, hipMemcpyAsync(h, c->outflow, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 16; ++k) out[k] = h[k];
+    for (int k = 0; k < 16; ++k)
+        if (!std::isfinite(h[k])) return set_err(c, MRTFD_ERR_NONFINITE, "outflow %d is not finite", k);
     return MRTFD_OK;
 }
 

@@ -887,6 +887,103 @@ __global__ __launch_bounds__(256) void k_sums_final(const double *__restrict__ p
     if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// Outflow budget.  One thread per node next to a side (west rows, east
+// rows, south columns, north columns).  The node beyond the side is the
+// boundary ghost (same rule and clock as the step) or, on a periodic side,
+// the periodic image; the face value of the Lax-Wendroff difference between
+// the two nodes, weighted by the conserved moments, is taken in FP64 from
+// the FP32 populations and added to the thread's own slot, so the totals do
+// not depend on scheduling.  Periodic faces are counted on both sides with
+// equal and opposite values.
+__global__ __launch_bounds__(256) void k_face_flux(Field F, Consts K, Ghosts G, FluxCoef C,
+                                                   const float *__restrict__ fin,
+                                                   double *__restrict__ slots,
+                                                   const long long *__restrict__ d_step, int k)
+{
+    const int nx = F.nx, ny = F.ny;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= 2 * (nx + ny)) return;
+    int sd, a;
+    if (t < ny) {
+        sd = 0, a = t;
+    } else if (t < 2 * ny) {
+        sd = 1, a = t - ny;
+    } else if (t < 2 * ny + nx) {
+        sd = 2, a = t - 2 * ny;
+    } else {
+        sd = 3, a = t - 2 * ny - nx;
+    }
+    // first and second interior node along the inward normal
+    int i1, j1, i2, j2;
+    if (sd == 0) i1 = 0, i2 = 1, j1 = j2 = a;
+    else if (sd == 1) i1 = nx - 1, i2 = nx - 2, j1 = j2 = a;
+    else if (sd == 2) j1 = 0, j2 = 1, i1 = i2 = a;
+    else j1 = ny - 1, j2 = ny - 2, i1 = i2 = a;
+    float n1[NQ], n2[NQ], g[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) n1[q] = fin[F.at(q, i1, j1)];
+    const bool per = sd < 2 ? G.per_x : G.per_y;
+    if (per) {
+        const int io = sd == 0 ? nx - 1 : sd == 1 ? 0 : a;
+        const int jo = sd == 2 ? ny - 1 : sd == 3 ? 0 : a;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) g[q] = fin[F.at(q, io, jo)];
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) n2[q] = fin[F.at(q, i2, j2)];
+        const double tm = step_time(G, d_step, k);
+        if (sd == 0) ghost_of<0>(K, G, tm, a, n1, n2, g);
+        else if (sd == 1) ghost_of<1>(K, G, tm, a, n1, n2, g);
+        else if (sd == 2) ghost_of<2>(K, G, tm, a, n1, n2, g);
+        else ghost_of<3>(K, G, tm, a, n1, n2, g);
+    }
+    // west/south: the ghost is at the lower coordinate and outflow is -phi
+    const bool low_side = sd == 0 || sd == 2;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (!(sd < 2 ? has_x(q) : has_y(q))) continue;
+        const double c0 = sd < 2 ? C.cx[q][0] : C.cy[q][0];
+        const double c1 = sd < 2 ? C.cx[q][1] : C.cy[q][1];
+        const double lo = low_side ? (double)g[q] : (double)n1[q];
+        const double hi = low_side ? (double)n1[q] : (double)g[q];
+        const double phi = c0 * (lo + hi) - c1 * (hi - lo);
+        const double o = low_side ? -phi : phi;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[m] += C.w[m][q] * o;
+    }
+    double *sl = slots + 4 * (long long)t;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) sl[m] += acc[m];
+}
+
+// Per-side totals of the slots, one block per side, fixed summation order.
+__global__ __launch_bounds__(256) void k_flux_totals(int nx, int ny,
+                                                     const double *__restrict__ slots,
+                                                     double *__restrict__ out)
+{
+    __shared__ double sh[4][256];
+    const int sd = blockIdx.x;
+    const int n = sd < 2 ? ny : nx;
+    const int off = sd == 0 ? 0 : sd == 1 ? ny : sd == 2 ? 2 * ny : 2 * ny + nx;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += 256) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[m] += slots[4 * (long long)(off + i) + m];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] = acc[m];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] += sh[m][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[4 * sd + threadIdx.x] = sh[threadIdx.x][0];
+}
+
 __global__ __launch_bounds__(256) void k_pack(Field F, const float *__restrict__ f,
                                               float *__restrict__ dst)
 {
@@ -993,6 +1090,22 @@ hipError_t launch_sums(const Field &F, const SumW &W, const float *f, double *pa
     const int nb = sums_blocks(F);
     hipLaunchKernelGGL(k_sums_partial, dim3(nb), dim3(256), 0, s, F, W, f, partials);
     hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_flux(const Field &F, const Consts &K, const Ghosts &G, const FluxCoef &C,
+                            const float *fin, double *slots, const long long *d_step, int k,
+                            hipStream_t s)
+{
+    const long long n = 2LL * (F.nx + F.ny);
+    hipLaunchKernelGGL(k_face_flux, dim3(blocks_for(n, 256)), dim3(256), 0, s, F, K, G, C, fin,
+                       slots, d_step, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_flux_totals(int nx, int ny, const double *slots, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flux_totals, dim3(4), dim3(256), 0, s, nx, ny, slots, out);
     return hipGetLastError();
 }
 

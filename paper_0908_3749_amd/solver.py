@@ -23,7 +23,7 @@ LAYOUTS = {"rows": _abi.MRTFD_LAYOUT_ROWS, "planes": _abi.MRTFD_LAYOUT_PLANES}
 
 
 def make_params(nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto", rows=0,
-                graph_steps=0, collision="mrt", layout="rows"):
+                graph_steps=0, collision="mrt", layout="rows", flux_budget=False):
     """Fill the C parameter struct.  sides: dict west/east/south/north of
     dicts with kind_lo, kind_hi (rule names), state_lo, state_hi
     (rho, u1, u2, T), split0, split_rate."""
@@ -49,6 +49,7 @@ def make_params(nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto", r
     p.graph_steps = int(graph_steps)
     p.collision = COLLISIONS[collision]
     p.layout = LAYOUTS[layout]
+    p.flux_budget = 1 if flux_budget else 0
     return p
 
 
@@ -63,13 +64,13 @@ class MRT2D:
     """One 2D grid on one GPU."""
 
     def __init__(self, nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto",
-                 rows=0, graph_steps=0, collision="mrt", layout="rows", device=None,
-                 stream=None):
+                 rows=0, graph_steps=0, collision="mrt", layout="rows", flux_budget=False,
+                 device=None, stream=None):
         import torch
 
         self.torch = torch
         self.p = make_params(nx, ny, dx, dy, dt, s, sides, precision, kernel, rows, graph_steps,
-                             collision, layout)
+                             collision, layout, flux_budget)
         st, msg = check_params(self.p)
         if st != _abi.MRTFD_OK:
             raise _abi.MrtfdError(st, msg)
@@ -132,6 +133,13 @@ class MRT2D:
         out = (C.c_double * 4)()
         check(lib().mrtfd_sums(self._ctx, out), self._ctx)
         return np.array(out[:])
+
+    def outflow(self):
+        """[side][k] FP64 outflow of (rho, j1, j2, e) through west, east,
+        south, north since the last init / set_f (needs flux_budget=True)."""
+        out = (C.c_double * 16)()
+        check(lib().mrtfd_outflow(self._ctx, out), self._ctx)
+        return np.array(out[:]).reshape(4, 4)
 
     def get_f(self):
         t = self.torch

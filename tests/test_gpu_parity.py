@@ -22,6 +22,7 @@ from oracle import core, metrics
 pytestmark = pytest.mark.gpu
 
 THREADS = max(1, min(16, os.cpu_count() or 1))
+U32 = 2.0 ** -24  # FP32 unit roundoff
 RATES = synth.rates(1e-5, s5=500, s6=700, s7=1000, s8=1100, s11=2500)
 VARIANTS = [("simple", 0), ("rows", 1), ("rows", 2)]
 
@@ -199,6 +200,40 @@ def test_autotune_trial_steps_are_ordinary_steps(gpu):
     h.close()
 
 
+@pytest.mark.parametrize("sides", ["wall_split", "reflect_extrapolate", "periodic"])
+def test_outflow_budget(gpu, sides):
+    """Outflow budget (flux_budget): the GPU's FP64 outflow through each side
+    matches the oracle's, periodic sides carry equal and opposite totals, the
+    step results are unchanged by the budget, and the GPU's own FP64 sums
+    close against its outflow up to the FP32 rounding of the updates."""
+    nx, ny, n = 150, 37, 300
+    ic = synth.smooth_macro(nx, ny, seed=12, du=0.2, dr=0.1)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS[sides], ic)
+    o = core.Grid(prob, nthreads=THREADS)
+    o.init_problem()
+    o.run(n)
+    g = gpu.from_problem(prob, flux_budget=True, graph_steps=16)
+    g.init_problem(prob)
+    s0 = g.sums()
+    g.step(n)
+    s1 = g.sums()
+    out = g.outflow()
+    f_budget = g.get_f_numpy()
+    g.close()
+    plain, _, _ = run_gpu(gpu, prob, None, n, graph_steps=16)
+    assert np.array_equal(f_budget, plain)
+    err = np.abs(out - o.outflow)
+    tol = 1e-5 * (np.abs(o.outflow).sum() + 1e-3 * np.abs(s0).sum() / (nx * ny))
+    print(f"{sides}: outflow\n{out}\nmax |gpu - oracle| {err.max():.3e} (tol {tol:.3e})")
+    assert np.all(err <= tol)
+    if sides == "periodic":
+        assert np.array_equal(out[0], -out[1]) and np.array_equal(out[2], -out[3])
+    resid = s1 - s0 + out.sum(axis=0)
+    scale = np.abs(s0) + np.abs(s1) + np.abs(out).sum(axis=0)
+    print(f"{sides}: GPU budget residual / scale {resid / scale}")
+    assert np.all(np.abs(resid) <= 4 * n * U32 * scale)
+
+
 def test_restart_is_bitwise(gpu):
     """Checkpoint/restart: 2N steps equal N steps, get_f, a fresh context
     with set_f and the clock restored, N more steps -- bit for bit, with a
@@ -252,7 +287,6 @@ def test_error_paths(gpu):
     g.close()
 
 
-U32 = 2.0 ** -24  # FP32 unit roundoff
 
 
 @pytest.mark.parametrize("state", [(1.0, 0.0, 0.0, 1.0), (0.125, 0.3, -0.2, 0.8),

@@ -289,3 +289,76 @@ def test_split_side_moves_with_time():
     rho = [ghost_macro(g, "north", a)[0] for a in range(nx)]
     np.testing.assert_allclose(rho[:6], [2.0] * 6, rtol=1e-12)
     assert all(abs(r - 2.0) > 0.1 for r in rho[6:])
+
+
+# ---------------------------------------------------------------- outflow budget
+
+def test_outflow_of_a_uniform_state_is_the_euler_flux():
+    """Uniform state with every side held at that state: nothing changes, and
+    the outflow per step through a side is the Euler flux of the state times
+    the side's node count times dt/h -- rho u_n, rho u u_n + P n, (e + P) u_n
+    -- with the sign of the outward normal (closed forms of the equilibrium's
+    moments, Eq. 14)."""
+    nx, ny, dx, dt = 12, 10, 0.01, 2e-4
+    rho, ux, uy, T = 1.3, 0.4, -0.2, 0.9
+    st = (rho, ux, uy, T)
+    sides = {k: synth.side("dirichlet", st) for k in synth.SIDES}
+    prob = synth.generic(nx, ny, dx, dt, synth.rates(dt, s5=300.0), sides,
+                         synth.uniform_ic(nx, ny, *st))
+    g = core.Grid(prob)
+    g.init_problem()
+    g.run(1)
+    P = rho * T
+    e = rho * (T + 0.5 * (ux * ux + uy * uy))
+    flux_x = np.array([rho * ux, rho * ux * ux + P, rho * ux * uy, (e + P) * ux])
+    flux_y = np.array([rho * uy, rho * ux * uy, rho * uy * uy + P, (e + P) * uy])
+    c = dt / dx
+    np.testing.assert_allclose(g.outflow[1], ny * c * flux_x, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(g.outflow[0], -ny * c * flux_x, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(g.outflow[3], nx * c * flux_y, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(g.outflow[2], -nx * c * flux_y, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("which", ["sod", "mach3_crop", "mixed_rules"])
+def test_outflow_budget_closes(which):
+    """Over the interior, the sums of rho, j, e change by minus the outflow
+    through the sides (the A.1b difference in flux form; the collision
+    conserves them): closes to FP64 round-off on open boundaries of every
+    kind, over many steps and time-dependent rule switches."""
+    if which == "sod":
+        prob = synth.sod(nx=200)
+        n = 400
+    elif which == "mach3_crop":
+        prob = synth.mach_reflection(nx=96, ny=32, x0_cells=24)
+        n = 300
+    else:
+        nx, ny = 40, 30
+        sides = {"west": synth.side("extrapolate"), "east": synth.side("wall", (1.0, 0.0, 0.3, 1.2)),
+                 "south": synth.split_side("dirichlet", (1.5, 0.2, 0.1, 1.1), "reflect",
+                                           (1.0, 0.0, 0.0, 1.0), 0.1, 3.0),
+                 "north": synth.side("extrapolate")}
+        ic = synth.smooth_macro(nx, ny, seed=9, du=0.3, dr=0.2)
+        prob = synth.generic(nx, ny, 0.01, 1e-4, synth.rates(1e-4, s5=800.0, s7=2e3), sides, ic)
+        n = 300
+    g = core.Grid(prob)
+    g.init_problem()
+    s0 = g.sums()
+    g.run(n)
+    s1 = g.sums()
+    out = g.outflow.sum(axis=0)
+    scale = np.abs(s0) + np.abs(s1) + np.abs(g.outflow).sum(axis=0) + 1.0
+    resid = (s1 - s0 + out) / scale
+    print(which, "budget residual", resid, "outflow", out)
+    assert np.all(np.abs(resid) <= 1e-12), resid
+    assert np.any(np.abs(out) > 1e-6 * scale)  # the sides do carry flux
+
+
+def test_periodic_sides_have_no_net_outflow():
+    nx, ny = 24, 16
+    ic = synth.smooth_macro(nx, ny, seed=4)
+    prob = periodic_problem(nx, ny, synth.rates(2e-4, s5=500.0), ic=ic)
+    g = core.Grid(prob)
+    g.init_problem()
+    g.run(50)
+    np.testing.assert_array_equal(g.outflow[0], -g.outflow[1])
+    np.testing.assert_array_equal(g.outflow[2], -g.outflow[3])
