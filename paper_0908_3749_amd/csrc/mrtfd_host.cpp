@@ -403,7 +403,7 @@ Field make_field(const mrtfd_params &p)
 }
 
 struct Layout {
-    size_t fA, fB, partials, sums, step, flag, mfma, flux, outflow, total;
+    size_t fA, fB, partials, sums, step, flag, mfma, fcoef, flux, outflow, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -420,7 +420,8 @@ Layout layout(const mrtfd_params &p)
     L.step = L.sums + 256;
     L.flag = L.step + 256;
     L.mfma = L.flag + 256;
-    L.flux = L.mfma + align256(sizeof(MfmaOperands));
+    L.fcoef = L.mfma + align256(sizeof(MfmaOperands));
+    L.flux = L.fcoef + align256(sizeof(FluxCoef));
     L.outflow = L.flux + (p.flux_budget ? align256(2 * ((size_t)p.nx + p.ny) * 4 * sizeof(double)) : 0);
     L.total = L.outflow + 256;
     return L;
@@ -461,7 +462,7 @@ struct mrtfd_ctx {
     MfmaOperands *d_mfma = nullptr;
     MfmaOperands h_mfma;
     double *flux = nullptr, *outflow = nullptr;  // outflow budget slots and totals
-    FluxCoef FC;
+    FluxCoef FC, *d_fcoef = nullptr;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream used only to capture graphs
     int device = 0;
@@ -509,10 +510,6 @@ hipError_t enqueue_steps(mrtfd_ctx *c, int start, int n, hipStream_t s)
 {
     int a = start;
     for (int k = 0; k < n; ++k) {
-        if (c->p.flux_budget) {
-            hipError_t e = launch_face_flux(c->F, c->K, c->G, c->FC, c->f[a], c->flux, c->d_step, k, s);
-            if (e != hipSuccess) return e;
-        }
         hipError_t e = launch_step(c, c->f[a], c->f[a ^ 1], k, s);
         if (e != hipSuccess) return e;
         a ^= 1;
@@ -730,6 +727,7 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     c->d_flag = reinterpret_cast<int *>(c->ws + L.flag);
     c->d_mfma = reinterpret_cast<MfmaOperands *>(c->ws + L.mfma);
     c->flux = reinterpret_cast<double *>(c->ws + L.flux);
+    c->d_fcoef = reinterpret_cast<FluxCoef *>(c->ws + L.fcoef);
     c->outflow = reinterpret_cast<double *>(c->ws + L.outflow);
     fill_mfma(m, *p, c->h_mfma);
     for (int q = 0; q < NQ; ++q) {
@@ -747,6 +745,8 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     c->G.dt = p->dt;
     c->G.per_x = p->side[0].kind_lo == MRTFD_BC_PERIODIC;
     c->G.per_y = p->side[2].kind_lo == MRTFD_BC_PERIODIC;
+    c->G.fc = c->d_fcoef;
+    c->G.flux = p->flux_budget ? c->flux : nullptr;
     for (int s = 0; s < 4; ++s) {
         const mrtfd_side &S = p->side[s];
         GhostSide &g = c->G.side[s];
@@ -789,6 +789,8 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_mfma, &c->h_mfma, sizeof(MfmaOperands), hipMemcpyHostToDevice,
                            c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_fcoef, &c->FC, sizeof(FluxCoef), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         delete c;
