@@ -127,8 +127,9 @@ typedef struct mrtfd_params {
     int32_t collision;  /* MRTFD_COLLISION_MRT or _SRT                        */
     int32_t layout;     /* MRTFD_LAYOUT_ROWS or _PLANES (device order of f)   */
     int32_t flux_budget;/* 1: every step also adds the FP64 outflow through
-                           each side to a running total (mrtfd_outflow),
-                           in extra blocks of the step kernel. 0: off    */
+                           each side to a running total (mrtfd_outflow):
+                           a small kernel on a library-owned stream that
+                           runs beside the step kernel. 0: off           */
 } mrtfd_params;
 
 typedef struct mrtfd_ctx mrtfd_ctx;

@@ -403,7 +403,7 @@ Field make_field(const mrtfd_params &p)
 }
 
 struct Layout {
-    size_t fA, fB, partials, sums, step, flag, mfma, fcoef, flux, outflow, total;
+    size_t fA, fB, partials, sums, step, flag, mfma, flux, outflow, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -420,8 +420,7 @@ Layout layout(const mrtfd_params &p)
     L.step = L.sums + 256;
     L.flag = L.step + 256;
     L.mfma = L.flag + 256;
-    L.fcoef = L.mfma + align256(sizeof(MfmaOperands));
-    L.flux = L.fcoef + align256(sizeof(FluxCoef));
+    L.flux = L.mfma + align256(sizeof(MfmaOperands));
     L.outflow = L.flux + (p.flux_budget ? align256(2 * ((size_t)p.nx + p.ny) * 4 * sizeof(double)) : 0);
     L.total = L.outflow + 256;
     return L;
@@ -462,9 +461,13 @@ struct mrtfd_ctx {
     MfmaOperands *d_mfma = nullptr;
     MfmaOperands h_mfma;
     double *flux = nullptr, *outflow = nullptr;  // outflow budget slots and totals
-    FluxCoef FC, *d_fcoef = nullptr;
+    FluxCoef FC;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream used only to capture graphs
+    // outflow budget: its kernel runs on `side`, beside the step kernel that
+    // reads the same state (fork and join by the two events)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int device = 0;
     int cur = 0;                 // which copy holds the state
     long long step = 0;
@@ -506,11 +509,24 @@ hipError_t launch_step(mrtfd_ctx *c, const float *fin, float *fout, int k, hipSt
 }
 
 // Enqueue n steps starting from copy `start`, then advance the device clock.
+// With the outflow budget on, step k's budget kernel runs on the side stream
+// concurrently with step k's update (both only read copy a), and step k + 1
+// waits for both.  Under graph capture the side stream joins the capture
+// through the fork event and is joined back before the capture ends.
 hipError_t enqueue_steps(mrtfd_ctx *c, int start, int n, hipStream_t s)
 {
     int a = start;
     for (int k = 0; k < n; ++k) {
-        hipError_t e = launch_step(c, c->f[a], c->f[a ^ 1], k, s);
+        hipError_t e = hipSuccess;
+        if (c->p.flux_budget) {
+            e = hipEventRecord(c->ev_fork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_fork, 0);
+            if (e == hipSuccess)
+                e = launch_face_flux(c->F, c->K, c->G, c->FC, c->f[a], c->flux, c->d_step, k, c->side);
+            if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->side);
+        }
+        if (e == hipSuccess) e = launch_step(c, c->f[a], c->f[a ^ 1], k, s);
+        if (e == hipSuccess && c->p.flux_budget) e = hipStreamWaitEvent(s, c->ev_join, 0);
         if (e != hipSuccess) return e;
         a ^= 1;
     }
@@ -524,6 +540,17 @@ void drop_graphs(mrtfd_ctx *c)
             (void)hipGraphExecDestroy(c->graph[k]);
             c->graph[k] = nullptr;
         }
+}
+
+// Graphs, private streams and events, then the context itself.
+void release(mrtfd_ctx *c)
+{
+    drop_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    delete c;
 }
 
 int build_graph(mrtfd_ctx *c, int start)
@@ -727,7 +754,6 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     c->d_flag = reinterpret_cast<int *>(c->ws + L.flag);
     c->d_mfma = reinterpret_cast<MfmaOperands *>(c->ws + L.mfma);
     c->flux = reinterpret_cast<double *>(c->ws + L.flux);
-    c->d_fcoef = reinterpret_cast<FluxCoef *>(c->ws + L.fcoef);
     c->outflow = reinterpret_cast<double *>(c->ws + L.outflow);
     fill_mfma(m, *p, c->h_mfma);
     for (int q = 0; q < NQ; ++q) {
@@ -745,8 +771,6 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     c->G.dt = p->dt;
     c->G.per_x = p->side[0].kind_lo == MRTFD_BC_PERIODIC;
     c->G.per_y = p->side[2].kind_lo == MRTFD_BC_PERIODIC;
-    c->G.fc = c->d_fcoef;
-    c->G.flux = p->flux_budget ? c->flux : nullptr;
     for (int s = 0; s < 4; ++s) {
         const mrtfd_side &S = p->side[s];
         GhostSide &g = c->G.side[s];
@@ -785,15 +809,18 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         c->tuned = true;
     }
     hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess && p->flux_budget) {
+        e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_mfma, &c->h_mfma, sizeof(MfmaOperands), hipMemcpyHostToDevice,
                            c->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(c->d_fcoef, &c->FC, sizeof(FluxCoef), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
-        delete c;
+        release(c);
         return MRTFD_ERR_HIP;
     }
     *out = c;
@@ -803,9 +830,7 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
 int32_t mrtfd_destroy(mrtfd_ctx *c)
 {
     if (!c) return MRTFD_ERR_ARG;
-    drop_graphs(c);
-    if (c->cap) (void)hipStreamDestroy(c->cap);
-    delete c;
+    release(c);
     return MRTFD_OK;
 }
 

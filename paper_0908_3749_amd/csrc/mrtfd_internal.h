@@ -86,24 +86,10 @@ struct GhostSide {
     double h;                        // node spacing along the side
 };
 
-// Outflow budget (FP64).  cx[q] = {(dt/dx) v_qx / 2, (dt/dx) v_qx^2 dt / (2 dx)}
-// and likewise cy along y: the face value of the A.1b difference between a
-// node at the lower coordinate (lo) and the next one (hi) is
-// cx[q][0] (lo + hi) - cx[q][1] (hi - lo).  w[k][q] = m_{k+1}(v_q), k < 4.
-struct FluxCoef {
-    double cx[NQ][2], cy[NQ][2];
-    double w[4][NQ];
-};
-
 struct Ghosts {
     GhostSide side[4];  // west, east, south, north
     double dt;
     int per_x, per_y;   // periodic in x (west/east) / in y (south/north)
-    // Outflow budget, or nullptr when off: each node next to a side adds its
-    // outflow of (rho, j1, j2, e) through its outer face to its own slot of
-    // 4 doubles (west rows, east rows, south columns, north columns).
-    const FluxCoef *fc;
-    double *flux;
 };
 
 hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
@@ -122,7 +108,20 @@ hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, 
 hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
                             float *fout, int rows, int stream_stores, const long long *d_step,
                             int k, hipStream_t s);
-// Per-side totals of the outflow slots (Ghosts::flux) into out[16].
+// Outflow budget (FP64).  cx[q] = {(dt/dx) v_qx / 2, (dt/dx) v_qx^2 dt / (2 dx)}
+// and likewise cy along y: the face value of the A.1b difference between a
+// node at the lower coordinate (lo) and the next one (hi) is
+// cx[q][0] (lo + hi) - cx[q][1] (hi - lo).  w[k][q] = m_{k+1}(v_q), k < 4.
+struct FluxCoef {
+    double cx[NQ][2], cy[NQ][2];
+    double w[4][NQ];
+};
+// Per step: add each side node's outflow of (rho, j1, j2, e) to its slot
+// (slots: 4 doubles per node, west rows, east rows, south columns, north
+// columns).  Then, on demand, the per-side totals into out[16].
+hipError_t launch_face_flux(const Field &F, const Consts &K, const Ghosts &G, const FluxCoef &C,
+                            const float *fin, double *slots, const long long *d_step, int k,
+                            hipStream_t s);
 hipError_t launch_flux_totals(int nx, int ny, const double *slots, double *out, hipStream_t s);
 
 hipError_t launch_counter_add(long long *d_step, long long n, hipStream_t s);

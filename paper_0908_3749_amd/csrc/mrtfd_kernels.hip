@@ -386,90 +386,15 @@ __device__ __forceinline__ double step_time(const Ghosts &G, const long long *d_
     return (double)(*d_step + k) * G.dt;
 }
 
-// Outflow budget, one thread per node next to a side (t: west rows, east
-// rows, south columns, north columns).  The node beyond the side is the
-// boundary ghost (same rule and clock as the step) or, on a periodic side,
-// the periodic image; the face value of the Lax-Wendroff difference between
-// the two nodes, weighted by the conserved moments, is taken in FP64 from
-// the FP32 populations and added to the thread's own slot, so the totals do
-// not depend on scheduling.  On the west and south sides the outer node has
-// the lower coordinate and the outflow is minus the face value; periodic
-// faces are counted on both sides, equal and opposite.  The step kernels run
-// this in extra blocks at the front of their grid, beside the node updates
-// (the budget reads only the step's input copy).
-__device__ __forceinline__ void face_outflow(const Field &F, const Consts &K, const Ghosts &G,
-                                             const float *__restrict__ fin, int t, double tm)
-{
-    const int nx = F.nx, ny = F.ny;
-    if (t >= 2 * (nx + ny)) return;
-    int sd, a;
-    if (t < ny) {
-        sd = 0, a = t;
-    } else if (t < 2 * ny) {
-        sd = 1, a = t - ny;
-    } else if (t < 2 * ny + nx) {
-        sd = 2, a = t - 2 * ny;
-    } else {
-        sd = 3, a = t - 2 * ny - nx;
-    }
-    // first and second interior node along the inward normal
-    int i1, j1, i2, j2;
-    if (sd == 0) i1 = 0, i2 = 1, j1 = j2 = a;
-    else if (sd == 1) i1 = nx - 1, i2 = nx - 2, j1 = j2 = a;
-    else if (sd == 2) j1 = 0, j2 = 1, i1 = i2 = a;
-    else j1 = ny - 1, j2 = ny - 2, i1 = i2 = a;
-    float n1[NQ], n2[NQ], g[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) n1[q] = fin[F.at(q, i1, j1)];
-    if (sd < 2 ? G.per_x : G.per_y) {
-        const int io = sd == 0 ? nx - 1 : sd == 1 ? 0 : a;
-        const int jo = sd == 2 ? ny - 1 : sd == 3 ? 0 : a;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) g[q] = fin[F.at(q, io, jo)];
-    } else {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) n2[q] = fin[F.at(q, i2, j2)];
-        if (sd == 0) ghost_of<0>(K, G, tm, a, n1, n2, g);
-        else if (sd == 1) ghost_of<1>(K, G, tm, a, n1, n2, g);
-        else if (sd == 2) ghost_of<2>(K, G, tm, a, n1, n2, g);
-        else ghost_of<3>(K, G, tm, a, n1, n2, g);
-    }
-    const FluxCoef &C = *G.fc;
-    const bool low = sd == 0 || sd == 2;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        if (!(sd < 2 ? has_x(q) : has_y(q))) continue;
-        const double c0 = sd < 2 ? C.cx[q][0] : C.cy[q][0];
-        const double c1 = sd < 2 ? C.cx[q][1] : C.cy[q][1];
-        const double lo = low ? (double)g[q] : (double)n1[q];
-        const double hi = low ? (double)n1[q] : (double)g[q];
-        const double phi = c0 * (lo + hi) - c1 * (hi - lo);
-        const double o = low ? -phi : phi;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) acc[m] += C.w[m][q] * o;
-    }
-    double *sl = G.flux + 4 * (long long)t;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) sl[m] += acc[m];
-}
-
 // One thread per node, 64x4 nodes per block; neighbours read straight from
-// global memory (the caches absorb the re-reads).  The first `fb` rows of
-// blocks compute the outflow budget instead.
+// global memory (the caches absorb the re-reads).
 __global__ __launch_bounds__(256) void k_step_simple(Field F, Consts K, Ghosts G,
                                                      const float *__restrict__ fin,
                                                      float *__restrict__ fout,
-                                                     const long long *__restrict__ d_step, int k,
-                                                     int fb)
+                                                     const long long *__restrict__ d_step, int k)
 {
-    if ((int)blockIdx.y < fb) {
-        face_outflow(F, K, G, fin, (blockIdx.y * gridDim.x + blockIdx.x) * 256 + threadIdx.x,
-                     step_time(G, d_step, k));
-        return;
-    }
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = (blockIdx.y - fb) * 4 + (threadIdx.x >> 6);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (i >= F.nx || j >= F.ny) return;
     node_update(F, K, G, fin, fout, i, j, step_time(G, d_step, k));
 }
@@ -520,19 +445,14 @@ template <int R, int AUX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
                  float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
-                 const long long *__restrict__ d_step, int k, int fb)
+                 const long long *__restrict__ d_step, int k)
 {
-    // the first fb blocks (a multiple of 8) compute the outflow budget
-    if ((int)blockIdx.x < fb) {
-        face_outflow(F, K, G, fin, blockIdx.x * 256 + threadIdx.x, step_time(G, d_step, k));
-        return;
-    }
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // Consecutive blocks land on different XCDs (round robin over 8); give
     // each XCD a contiguous range of blocks so that neighbouring tiles, which
     // share halo rows and columns, share an L2.
-    int b = blockIdx.x - fb;
+    int b = blockIdx.x;
     if ((nblocks & 7) == 0) b = (b & 7) * (nblocks >> 3) + (b >> 3);
     const int col = b % ncol;
     const int rg = (b / ncol) * 4 + wv;
@@ -632,18 +552,12 @@ __global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
                                                    const float *__restrict__ fin,
                                                    float *__restrict__ fout, unsigned bytes,
                                                    int ncol, int nrb, int nblocks,
-                                                   const long long *__restrict__ d_step, int k,
-                                                   int fb)
+                                                   const long long *__restrict__ d_step, int k)
 {
     __shared__ float stage[4][64][NQ + 4];
-    // the first fb blocks (a multiple of 8) compute the outflow budget
-    if ((int)blockIdx.x < fb) {
-        face_outflow(F, K, G, fin, blockIdx.x * 256 + threadIdx.x, step_time(G, d_step, k));
-        return;
-    }
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int b = blockIdx.x - fb;
+    int b = blockIdx.x;
     if ((nblocks & 7) == 0) b = (b & 7) * (nblocks >> 3) + (b >> 3);
     const int col = b % ncol, rb = b / ncol;
     const int x0 = col * 64, yb = rb * 4, x = x0 + lane, y = yb + wv;
@@ -973,6 +887,76 @@ __global__ __launch_bounds__(256) void k_sums_final(const double *__restrict__ p
     if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// Outflow budget.  One thread per node next to a side (west rows, east
+// rows, south columns, north columns).  The node beyond the side is the
+// boundary ghost (same rule and clock as the step) or, on a periodic side,
+// the periodic image; the face value of the Lax-Wendroff difference between
+// the two nodes, weighted by the conserved moments, is taken in FP64 from
+// the FP32 populations and added to the thread's own slot, so the totals do
+// not depend on scheduling.  Periodic faces are counted on both sides with
+// equal and opposite values.
+__global__ __launch_bounds__(256) void k_face_flux(Field F, Consts K, Ghosts G, FluxCoef C,
+                                                   const float *__restrict__ fin,
+                                                   double *__restrict__ slots,
+                                                   const long long *__restrict__ d_step, int k)
+{
+    const int nx = F.nx, ny = F.ny;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= 2 * (nx + ny)) return;
+    int sd, a;
+    if (t < ny) {
+        sd = 0, a = t;
+    } else if (t < 2 * ny) {
+        sd = 1, a = t - ny;
+    } else if (t < 2 * ny + nx) {
+        sd = 2, a = t - 2 * ny;
+    } else {
+        sd = 3, a = t - 2 * ny - nx;
+    }
+    // first and second interior node along the inward normal
+    int i1, j1, i2, j2;
+    if (sd == 0) i1 = 0, i2 = 1, j1 = j2 = a;
+    else if (sd == 1) i1 = nx - 1, i2 = nx - 2, j1 = j2 = a;
+    else if (sd == 2) j1 = 0, j2 = 1, i1 = i2 = a;
+    else j1 = ny - 1, j2 = ny - 2, i1 = i2 = a;
+    float n1[NQ], n2[NQ], g[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) n1[q] = fin[F.at(q, i1, j1)];
+    const bool per = sd < 2 ? G.per_x : G.per_y;
+    if (per) {
+        const int io = sd == 0 ? nx - 1 : sd == 1 ? 0 : a;
+        const int jo = sd == 2 ? ny - 1 : sd == 3 ? 0 : a;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) g[q] = fin[F.at(q, io, jo)];
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) n2[q] = fin[F.at(q, i2, j2)];
+        const double tm = step_time(G, d_step, k);
+        if (sd == 0) ghost_of<0>(K, G, tm, a, n1, n2, g);
+        else if (sd == 1) ghost_of<1>(K, G, tm, a, n1, n2, g);
+        else if (sd == 2) ghost_of<2>(K, G, tm, a, n1, n2, g);
+        else ghost_of<3>(K, G, tm, a, n1, n2, g);
+    }
+    // west/south: the ghost is at the lower coordinate and outflow is -phi
+    const bool low_side = sd == 0 || sd == 2;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (!(sd < 2 ? has_x(q) : has_y(q))) continue;
+        const double c0 = sd < 2 ? C.cx[q][0] : C.cy[q][0];
+        const double c1 = sd < 2 ? C.cx[q][1] : C.cy[q][1];
+        const double lo = low_side ? (double)g[q] : (double)n1[q];
+        const double hi = low_side ? (double)n1[q] : (double)g[q];
+        const double phi = c0 * (lo + hi) - c1 * (hi - lo);
+        const double o = low_side ? -phi : phi;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[m] += C.w[m][q] * o;
+    }
+    double *sl = slots + 4 * (long long)t;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) sl[m] += acc[m];
+}
+
 // Per-side totals of the slots, one block per side, fixed summation order.
 __global__ __launch_bounds__(256) void k_flux_totals(int nx, int ny,
                                                      const double *__restrict__ slots,
@@ -1036,22 +1020,11 @@ hipError_t launch_init(const Field &F, const Consts &K, float *f, const float *r
     return hipGetLastError();
 }
 
-// Blocks of 256 threads the outflow budget needs (0 when it is off), rounded
-// up to a multiple of `mult`.
-inline int budget_blocks(const Field &F, const Ghosts &G, int mult)
-{
-    if (!G.flux) return 0;
-    const int n = (int)blocks_for(2LL * (F.nx + F.ny), 256);
-    return (n + mult - 1) / mult * mult;
-}
-
 hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
                               float *fout, const long long *d_step, int k, hipStream_t s)
 {
-    const unsigned nbx = blocks_for(F.nx, 64);
-    const int fb = G.flux ? (int)blocks_for(budget_blocks(F, G, 1), nbx) : 0;  // rows of blocks
-    dim3 grid(nbx, blocks_for(F.ny, 4) + fb);
-    hipLaunchKernelGGL(k_step_simple, grid, dim3(256), 0, s, F, K, G, fin, fout, d_step, k, fb);
+    dim3 grid(blocks_for(F.nx, 64), blocks_for(F.ny, 4));
+    hipLaunchKernelGGL(k_step_simple, grid, dim3(256), 0, s, F, K, G, fin, fout, d_step, k);
     return hipGetLastError();
 }
 
@@ -1065,17 +1038,16 @@ hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, co
     const long long total = 4LL * F.total;
     if (total >= (1LL << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
     const unsigned bytes = (unsigned)total;
-    const int fb = budget_blocks(F, G, 8);
     switch (rows) {
     // store cache policy: 0 default, 2 non-temporal (streaming)
 #define MRTFD_ROWS(Rr)                                                                             \
     case Rr:                                                                                       \
         if (stream_stores)                                                                         \
-            hipLaunchKernelGGL((k_step_rows<Rr, 2>), dim3(nb + fb), dim3(256), 0, s, F, K, G, fin, \
-                               fout, bytes, ncol, nrg, nb, d_step, k, fb);                         \
+            hipLaunchKernelGGL((k_step_rows<Rr, 2>), dim3(nb), dim3(256), 0, s, F, K, G, fin,      \
+                               fout, bytes, ncol, nrg, nb, d_step, k);                             \
         else                                                                                       \
-            hipLaunchKernelGGL((k_step_rows<Rr, 0>), dim3(nb + fb), dim3(256), 0, s, F, K, G, fin, \
-                               fout, bytes, ncol, nrg, nb, d_step, k, fb);                         \
+            hipLaunchKernelGGL((k_step_rows<Rr, 0>), dim3(nb), dim3(256), 0, s, F, K, G, fin,      \
+                               fout, bytes, ncol, nrg, nb, d_step, k);                             \
         break;
         MRTFD_ROWS(1)
         MRTFD_ROWS(2)
@@ -1118,6 +1090,16 @@ hipError_t launch_sums(const Field &F, const SumW &W, const float *f, double *pa
     const int nb = sums_blocks(F);
     hipLaunchKernelGGL(k_sums_partial, dim3(nb), dim3(256), 0, s, F, W, f, partials);
     hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_flux(const Field &F, const Consts &K, const Ghosts &G, const FluxCoef &C,
+                            const float *fin, double *slots, const long long *d_step, int k,
+                            hipStream_t s)
+{
+    const long long n = 2LL * (F.nx + F.ny);
+    hipLaunchKernelGGL(k_face_flux, dim3(blocks_for(n, 256)), dim3(256), 0, s, F, K, G, C, fin,
+                       slots, d_step, k);
     return hipGetLastError();
 }
 
@@ -1203,9 +1185,8 @@ hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
     const int nb = ncol * nrb;
     const long long total = 4LL * F.total;
     if (total >= (1LL << 32)) return hipErrorInvalidValue;
-    const int fb = budget_blocks(F, G, 8);
-    hipLaunchKernelGGL(k_step_mfma, dim3(nb + fb), dim3(256), 0, s, F, K, G, mo, fin, fout,
-                       (unsigned)total, ncol, nrb, nb, d_step, k, fb);
+    hipLaunchKernelGGL(k_step_mfma, dim3(nb), dim3(256), 0, s, F, K, G, mo, fin, fout,
+                       (unsigned)total, ncol, nrb, nb, d_step, k);
     return hipGetLastError();
 }
 

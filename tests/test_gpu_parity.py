@@ -222,6 +222,11 @@ def test_outflow_budget(gpu, sides):
     g.close()
     plain, _, _ = run_gpu(gpu, prob, None, n, graph_steps=16)
     assert np.array_equal(f_budget, plain)
+    h = gpu.from_problem(prob, flux_budget=True, graph_steps=0)  # direct launches
+    h.init_problem(prob)
+    h.step(n)
+    assert np.array_equal(h.outflow(), out)
+    h.close()
     err = np.abs(out - o.outflow)
     tol = 1e-5 * (np.abs(o.outflow).sum() + 1e-3 * np.abs(s0).sum() / (nx * ny))
     print(f"{sides}: outflow\n{out}\nmax |gpu - oracle| {err.max():.3e} (tol {tol:.3e})")
