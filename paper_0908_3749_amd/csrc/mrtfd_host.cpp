@@ -349,10 +349,14 @@ int check(const mrtfd_params *p, char *msg, size_t len)
     if (p->layout != MRTFD_LAYOUT_ROWS && p->layout != MRTFD_LAYOUT_PLANES)
         return fail(MRTFD_ERR_ARG, "unknown layout %d", p->layout);
     if (p->kernel != MRTFD_KERNEL_AUTO && p->kernel != MRTFD_KERNEL_SIMPLE &&
-        p->kernel != MRTFD_KERNEL_ROWS)
+        p->kernel != MRTFD_KERNEL_ROWS && p->kernel != MRTFD_KERNEL_MARCH)
         return fail(MRTFD_ERR_ARG, "unknown kernel %d", p->kernel);
-    if (p->rows != 0 && p->rows != 1 && p->rows != 2)
+    if (p->kernel == MRTFD_KERNEL_MARCH) {
+        if (p->rows != 0 && p->rows != 2 && p->rows != 4 && p->rows != 8)
+            return fail(MRTFD_ERR_ARG, "rows must be 0, 2, 4 or 8 for the marching kernel");
+    } else if (p->rows != 0 && p->rows != 1 && p->rows != 2) {
         return fail(MRTFD_ERR_ARG, "rows must be 0, 1 or 2");
+    }
     if (p->flux_budget != 0 && p->flux_budget != 1)
         return fail(MRTFD_ERR_ARG, "flux_budget must be 0 or 1");
     if (p->graph_steps < 0 || (p->graph_steps % 2) != 0 || p->graph_steps > 4096)
@@ -505,6 +509,9 @@ hipError_t launch_step(mrtfd_ctx *c, const float *fin, float *fout, int k, hipSt
     if (c->kernel == MRTFD_KERNEL_ROWS)
         return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg & 15, c->seg >> 4, c->d_step, k,
                                 s);
+    if (c->kernel == MRTFD_KERNEL_MARCH)
+        return launch_step_march(c->F, c->K, c->G, fin, fout, c->seg & 15, c->seg >> 4, c->d_step,
+                                 k, s);
     return launch_step_mfma(c->F, c->K, c->G, c->d_mfma, fin, fout, c->d_step, k, s);
 }
 
@@ -615,11 +622,18 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
     if (c->p.kernel == MRTFD_KERNEL_SIMPLE) {
         cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     } else {
-        for (int r = 1; r <= 2; ++r) {
-            if (c->p.rows && r != c->p.rows) continue;
-            cands.push_back({MRTFD_KERNEL_ROWS, r});
-            cands.push_back({MRTFD_KERNEL_ROWS, r | 16});
-        }
+        if (c->p.kernel != MRTFD_KERNEL_MARCH)
+            for (int r = 1; r <= 2; ++r) {
+                if (c->p.rows && r != c->p.rows) continue;
+                cands.push_back({MRTFD_KERNEL_ROWS, r});
+                cands.push_back({MRTFD_KERNEL_ROWS, r | 16});
+            }
+        if (c->p.kernel == MRTFD_KERNEL_MARCH || c->p.kernel == MRTFD_KERNEL_AUTO)
+            for (int r : {2, 4, 8}) {
+                if (c->p.kernel == MRTFD_KERNEL_MARCH && c->p.rows && r != c->p.rows) continue;
+                cands.push_back({MRTFD_KERNEL_MARCH, r});
+                cands.push_back({MRTFD_KERNEL_MARCH, r | 16});
+            }
         if (c->p.kernel == MRTFD_KERNEL_AUTO) cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     }
     c->kernel = cands[0].first;
@@ -799,7 +813,11 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     // default until tuned: rows kernel, one row per wave, plain stores
     c->kernel = p->kernel == MRTFD_KERNEL_SIMPLE ? MRTFD_KERNEL_SIMPLE : MRTFD_KERNEL_ROWS;
     c->seg = p->kernel == MRTFD_KERNEL_SIMPLE ? 0 : 1;
-    if (p->kernel == MRTFD_KERNEL_ROWS && p->rows) {
+    if (p->kernel == MRTFD_KERNEL_MARCH) {
+        c->kernel = MRTFD_KERNEL_MARCH;
+        c->seg = p->rows ? p->rows : 4;
+    }
+    if ((p->kernel == MRTFD_KERNEL_ROWS || p->kernel == MRTFD_KERNEL_MARCH) && p->rows) {
         c->seg = p->rows;
         c->tuned = true;
     }

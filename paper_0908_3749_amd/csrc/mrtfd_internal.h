@@ -92,6 +92,11 @@ struct Ghosts {
     int per_x, per_y;   // periodic in x (west/east) / in y (south/north)
 };
 
+// Marching variant: each wave walks `rows` (2, 4 or 8) rows with the next
+// row's loads in flight.
+hipError_t launch_step_march(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
+                             float *fout, int rows, int stream_stores, const long long *d_step,
+                             int k, hipStream_t s);
 hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
                             const MfmaOperands *mo, const float *fin, float *fout,
                             const long long *d_step, int k, hipStream_t s);

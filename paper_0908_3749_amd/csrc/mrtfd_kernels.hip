@@ -503,6 +503,92 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
     }
 }
 
+// Marching kernel.  Each wave owns R consecutive rows of 64 columns and walks
+// up through them with a three-row window in registers: the whole row being
+// updated, the y-moving populations of the rows below and above, and the
+// row's two outside columns (halo).  While row y is updated, the loads for
+// row y + 1 (its populations with no y component and its halo) and for the
+// y-moving populations of row y + 2 are already in flight, so each wave
+// overlaps its own memory latency with its arithmetic; every population of
+// the grid is loaded once per wave that needs it.  West/east neighbours by
+// DPP as in the row kernel; waves with a node on a side take node_update.
+// Same arithmetic and operation order as every other variant.
+template <int R, int AUX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_step_march(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
+                  float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
+                  const long long *__restrict__ d_step, int k)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int b = blockIdx.x;
+    if ((nblocks & 7) == 0) b = (b & 7) * (nblocks >> 3) + (b >> 3);
+    const int col = b % ncol;
+    const int rg = (b / ncol) * 4 + wv;
+    if (rg >= nrg) return;
+    const int x0 = col * 64, y0 = rg * R, x = x0 + lane;
+    if (col == 0 || x0 + 64 >= F.nx || y0 == 0 || y0 + R >= F.ny) {
+        const double t = step_time(G, d_step, k);
+        if (x < F.nx) {
+#pragma unroll 1
+            for (int r = 0; r < R; ++r)
+                if (y0 + r < F.ny) node_update(F, K, G, fin, fout, x, y0 + r, t);
+        }
+        return;
+    }
+    // interior wave: rows y0 - 1 .. y0 + R exist
+    const unsigned vo = 4u * (unsigned)(F.xoff + x);
+    const unsigned vh = 4u * (unsigned)(F.xoff + (lane < 32 ? x0 - 1 : x0 + 64));
+    const unsigned qB = 4u * (unsigned)F.qstride, jB = 4u * (unsigned)F.jstride;
+    const auto rin = buffer_of(fin, bytes);
+    const auto rout = buffer_of(fout, bytes);
+    auto row = [&](int q, int j) { return (unsigned)q * qB + (unsigned)(j + 1) * jB; };
+
+    // C: row y (all populations); P, N: y-moving populations of rows y - 1
+    // and y + 1; H: x-moving populations of the two outside columns of row y
+    float C[NQ], P[NQ], N[NQ], H[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        C[q] = bload(rin, vo, row(q, y0));
+        P[q] = has_y(q) ? bload(rin, vo, row(q, y0 - 1)) : 0.f;
+        N[q] = has_y(q) ? bload(rin, vo, row(q, y0 + 1)) : 0.f;
+        H[q] = has_x(q) ? bload(rin, vh, row(q, y0)) : 0.f;
+    }
+    Unroll<R>::run([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        const int y = y0 + r;
+        float N2[NQ], X[NQ], H2[NQ];
+        if (r + 1 < R) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                N2[q] = has_y(q) ? bload(rin, vo, row(q, y + 2)) : 0.f;
+                X[q] = has_y(q) ? 0.f : bload(rin, vo, row(q, y + 1));
+                H2[q] = has_x(q) ? bload(rin, vh, row(q, y + 1)) : 0.f;
+            }
+        }
+        float dC[NQ];
+        collide(K, C, dC);
+        Unroll<NQ>::run([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            float fE = 0.f, fW = 0.f;
+            if (has_x(q)) {
+                fE = shl1(C[q], H[q]);
+                fW = shr1(C[q], H[q]);
+            }
+            bstore<AUX>(rout, lw_update<q>(K, C[q], dC[q], fE, fW, N[q], P[q]), vo, row(q, y));
+        });
+        if (r + 1 < R) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                P[q] = has_y(q) ? C[q] : 0.f;
+                C[q] = has_y(q) ? N[q] : X[q];
+                N[q] = N2[q];
+                H[q] = H2[q];
+            }
+        }
+    });
+}
+
 // ------------------------------------------------- split-BF16 matrix cores
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
@@ -1187,6 +1273,36 @@ hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
     if (total >= (1LL << 32)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_step_mfma, dim3(nb), dim3(256), 0, s, F, K, G, mo, fin, fout,
                        (unsigned)total, ncol, nrb, nb, d_step, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_march(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
+                             float *fout, int rows, int stream_stores, const long long *d_step,
+                             int k, hipStream_t s)
+{
+    const int ncol = (F.nx + 63) / 64;
+    const int nrg = (F.ny + rows - 1) / rows;
+    const int nb = ncol * ((nrg + 3) / 4);
+    const long long total = 4LL * F.total;
+    if (total >= (1LL << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
+    const unsigned bytes = (unsigned)total;
+    switch (rows) {
+#define MRTFD_MARCH(Rr)                                                                            \
+    case Rr:                                                                                       \
+        if (stream_stores)                                                                         \
+            hipLaunchKernelGGL((k_step_march<Rr, 2>), dim3(nb), dim3(256), 0, s, F, K, G, fin,     \
+                               fout, bytes, ncol, nrg, nb, d_step, k);                             \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_step_march<Rr, 0>), dim3(nb), dim3(256), 0, s, F, K, G, fin,     \
+                               fout, bytes, ncol, nrg, nb, d_step, k);                             \
+        break;
+        MRTFD_MARCH(2)
+        MRTFD_MARCH(4)
+        MRTFD_MARCH(8)
+#undef MRTFD_MARCH
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

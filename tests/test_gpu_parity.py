@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 THREADS = max(1, min(16, os.cpu_count() or 1))
 U32 = 2.0 ** -24  # FP32 unit roundoff
 RATES = synth.rates(1e-5, s5=500, s6=700, s7=1000, s8=1100, s11=2500)
-VARIANTS = [("simple", 0), ("rows", 1), ("rows", 2)]
+VARIANTS = [("simple", 0), ("rows", 1), ("rows", 2), ("march", 2), ("march", 4), ("march", 8)]
 
 SIDE_SETS = {
     "periodic": {k: synth.side("periodic") for k in synth.SIDES},
