@@ -190,7 +190,7 @@ def main():
                     help="untimed steps; they hold the kernel autotune (up to 5 x 34 steps) "
                          "and the graph capture")
     ap.add_argument("--config", default="mach3", choices=sorted(workloads()))
-    ap.add_argument("--kernel", default="auto", choices=["auto", "simple", "rows", "march"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "simple", "rows"])
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])

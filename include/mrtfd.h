@@ -95,8 +95,6 @@ extern "C" {
                                  once, west/east neighbours by lane shifts     */
 #define MRTFD_KERNEL_MFMA 3   /* reported only: the matrix-core kernel that
                                  MRTFD_BF16X3 always uses                      */
-#define MRTFD_KERNEL_MARCH 4  /* each wave walks `rows` rows (2, 4 or 8) of 64
-                                 columns with the next row's loads in flight */
 
 /* One side of the grid.  The rule is kind_lo at ghost nodes whose
  * along-side coordinate (x for the south/north sides, y for west/east) is
@@ -123,8 +121,8 @@ typedef struct mrtfd_params {
     mrtfd_side side[4];
     int32_t precision;  /* MRTFD_FP32 or MRTFD_BF16X3                        */
     int32_t kernel;     /* MRTFD_KERNEL_*                                    */
-    int32_t rows;       /* rows per wave: MRTFD_KERNEL_ROWS 1 or 2,
-                           MRTFD_KERNEL_MARCH 2, 4 or 8; 0 = auto           */
+    int32_t rows;       /* rows per wave for MRTFD_KERNEL_ROWS (1 or 2),
+                           0 = auto                                          */
     int32_t graph_steps;/* steps per captured HIP graph, 0 = no graph        */
     int32_t collision;  /* MRTFD_COLLISION_MRT or _SRT                        */
     int32_t layout;     /* MRTFD_LAYOUT_ROWS or _PLANES (device order of f)   */
@@ -210,7 +208,7 @@ int32_t mrtfd_outflow(mrtfd_ctx *ctx, double out[16]);
  * where they stopped. */
 int32_t mrtfd_set_step(mrtfd_ctx *ctx, int64_t step);
 
-/* The step kernel in use (MRTFD_KERNEL_SIMPLE, _ROWS, _MFMA or _MARCH), its rows
+/* The step kernel in use (MRTFD_KERNEL_SIMPLE, _ROWS or _MFMA), its rows
  * per wave, and 1 if it writes with streaming (non-temporal) stores, else 0
  * (host outputs, each may be NULL).  With MRTFD_KERNEL_AUTO, or _ROWS and
  * rows = 0, the choice is made by timing the candidates on the first steps

@@ -40,7 +40,6 @@ MRTFD_KERNEL_AUTO = 0
 MRTFD_KERNEL_SIMPLE = 1
 MRTFD_KERNEL_ROWS = 2
 MRTFD_KERNEL_MFMA = 3
-MRTFD_KERNEL_MARCH = 4
 
 
 class mrtfd_side(C.Structure):

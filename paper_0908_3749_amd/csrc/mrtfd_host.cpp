@@ -349,14 +349,10 @@ int check(const mrtfd_params *p, char *msg, size_t len)
     if (p->layout != MRTFD_LAYOUT_ROWS && p->layout != MRTFD_LAYOUT_PLANES)
         return fail(MRTFD_ERR_ARG, "unknown layout %d", p->layout);
     if (p->kernel != MRTFD_KERNEL_AUTO && p->kernel != MRTFD_KERNEL_SIMPLE &&
-        p->kernel != MRTFD_KERNEL_ROWS && p->kernel != MRTFD_KERNEL_MARCH)
+        p->kernel != MRTFD_KERNEL_ROWS)
         return fail(MRTFD_ERR_ARG, "unknown kernel %d", p->kernel);
-    if (p->kernel == MRTFD_KERNEL_MARCH) {
-        if (p->rows != 0 && p->rows != 2 && p->rows != 4 && p->rows != 8)
-            return fail(MRTFD_ERR_ARG, "rows must be 0, 2, 4 or 8 for the marching kernel");
-    } else if (p->rows != 0 && p->rows != 1 && p->rows != 2) {
+    if (p->rows != 0 && p->rows != 1 && p->rows != 2)
         return fail(MRTFD_ERR_ARG, "rows must be 0, 1 or 2");
-    }
     if (p->flux_budget != 0 && p->flux_budget != 1)
         return fail(MRTFD_ERR_ARG, "flux_budget must be 0 or 1");
     if (p->graph_steps < 0 || (p->graph_steps % 2) != 0 || p->graph_steps > 4096)
@@ -407,7 +403,7 @@ Field make_field(const mrtfd_params &p)
 }
 
 struct Layout {
-    size_t fA, fB, partials, sums, step, flag, mfma, flux, outflow, total;
+    size_t fA, fB, partials, sums, step, flag, mfma, kcopy, gcopy, flux, outflow, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -424,7 +420,9 @@ Layout layout(const mrtfd_params &p)
     L.step = L.sums + 256;
     L.flag = L.step + 256;
     L.mfma = L.flag + 256;
-    L.flux = L.mfma + align256(sizeof(MfmaOperands));
+    L.kcopy = L.mfma + align256(sizeof(MfmaOperands));
+    L.gcopy = L.kcopy + align256(sizeof(Consts));
+    L.flux = L.gcopy + align256(sizeof(Ghosts));
     L.outflow = L.flux + (p.flux_budget ? align256(2 * ((size_t)p.nx + p.ny) * 4 * sizeof(double)) : 0);
     L.total = L.outflow + 256;
     return L;
@@ -509,9 +507,6 @@ hipError_t launch_step(mrtfd_ctx *c, const float *fin, float *fout, int k, hipSt
     if (c->kernel == MRTFD_KERNEL_ROWS)
         return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg & 15, c->seg >> 4, c->d_step, k,
                                 s);
-    if (c->kernel == MRTFD_KERNEL_MARCH)
-        return launch_step_march(c->F, c->K, c->G, fin, fout, c->seg & 15, c->seg >> 4, c->d_step,
-                                 k, s);
     return launch_step_mfma(c->F, c->K, c->G, c->d_mfma, fin, fout, c->d_step, k, s);
 }
 
@@ -622,18 +617,11 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
     if (c->p.kernel == MRTFD_KERNEL_SIMPLE) {
         cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     } else {
-        if (c->p.kernel != MRTFD_KERNEL_MARCH)
-            for (int r = 1; r <= 2; ++r) {
-                if (c->p.rows && r != c->p.rows) continue;
-                cands.push_back({MRTFD_KERNEL_ROWS, r});
-                cands.push_back({MRTFD_KERNEL_ROWS, r | 16});
-            }
-        if (c->p.kernel == MRTFD_KERNEL_MARCH || c->p.kernel == MRTFD_KERNEL_AUTO)
-            for (int r : {2, 4, 8}) {
-                if (c->p.kernel == MRTFD_KERNEL_MARCH && c->p.rows && r != c->p.rows) continue;
-                cands.push_back({MRTFD_KERNEL_MARCH, r});
-                cands.push_back({MRTFD_KERNEL_MARCH, r | 16});
-            }
+        for (int r = 1; r <= 2; ++r) {
+            if (c->p.rows && r != c->p.rows) continue;
+            cands.push_back({MRTFD_KERNEL_ROWS, r});
+            cands.push_back({MRTFD_KERNEL_ROWS, r | 16});
+        }
         if (c->p.kernel == MRTFD_KERNEL_AUTO) cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     }
     c->kernel = cands[0].first;
@@ -783,6 +771,8 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     for (int k = 0; k < 4; ++k)
         for (int q = 0; q < NQ; ++q) c->W.w[k][q] = m.M[k][q];
     c->G.dt = p->dt;
+    c->G.kd = reinterpret_cast<const Consts *>(c->ws + L.kcopy);
+    c->G.gd = reinterpret_cast<const Ghosts *>(c->ws + L.gcopy);
     c->G.per_x = p->side[0].kind_lo == MRTFD_BC_PERIODIC;
     c->G.per_y = p->side[2].kind_lo == MRTFD_BC_PERIODIC;
     for (int s = 0; s < 4; ++s) {
@@ -813,11 +803,7 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     // default until tuned: rows kernel, one row per wave, plain stores
     c->kernel = p->kernel == MRTFD_KERNEL_SIMPLE ? MRTFD_KERNEL_SIMPLE : MRTFD_KERNEL_ROWS;
     c->seg = p->kernel == MRTFD_KERNEL_SIMPLE ? 0 : 1;
-    if (p->kernel == MRTFD_KERNEL_MARCH) {
-        c->kernel = MRTFD_KERNEL_MARCH;
-        c->seg = p->rows ? p->rows : 4;
-    }
-    if ((p->kernel == MRTFD_KERNEL_ROWS || p->kernel == MRTFD_KERNEL_MARCH) && p->rows) {
+    if (p->kernel == MRTFD_KERNEL_ROWS && p->rows) {
         c->seg = p->rows;
         c->tuned = true;
     }
@@ -836,6 +822,10 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_mfma, &c->h_mfma, sizeof(MfmaOperands), hipMemcpyHostToDevice,
                            c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + L.kcopy, &c->K, sizeof(Consts), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + L.gcopy, &c->G, sizeof(Ghosts), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         release(c);

@@ -90,13 +90,13 @@ struct Ghosts {
     GhostSide side[4];  // west, east, south, north
     double dt;
     int per_x, per_y;   // periodic in x (west/east) / in y (south/north)
+    // device copies of the step constants and of this struct: the boundary
+    // paths of the step kernels read these, so that the interior path keeps
+    // the kernel arguments to itself
+    const Consts *kd;
+    const Ghosts *gd;
 };
 
-// Marching variant: each wave walks `rows` (2, 4 or 8) rows with the next
-// row's loads in flight.
-hipError_t launch_step_march(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
-                             float *fout, int rows, int stream_stores, const long long *d_step,
-                             int k, hipStream_t s);
 hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
                             const MfmaOperands *mo, const float *fin, float *fout,
                             const long long *d_step, int k, hipStream_t s);

@@ -436,13 +436,131 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsign
 // issued before any arithmetic.  West/east neighbours come from the adjacent
 // lanes by DPP; the two columns just outside the wave come from one extra
 // load per population and row (lanes 0-31 read column x0-1, lanes 32-63
-// column x0+64, so lane 0 and lane 63 hold what they need).  Waves with a node
-// on a side of the grid take node_update, which knows the boundary rules; the
-// others have only interior neighbours.  Addressing is by buffer
-// instructions: one per-lane byte offset shared by all loads of a column, plus
-// a wave-uniform offset for (plane, row).
+// column x0+64, so lane 0 and lane 63 hold what they need).  Addressing is by
+// buffer instructions: one per-lane byte offset shared by all loads of a
+// column, plus a wave-uniform offset for (plane, row).
+//
+// Waves at a side of the grid run the same steps in a branch of their own
+// (rows_edge); what lies beyond the side is put into the registers that
+// would hold the missing neighbours: on a
+// periodic side the loads are redirected to the periodic image, otherwise
+// the boundary ghost (ghost_of, the same function and inputs as node_update)
+// replaces the south or north neighbour row, the west halo of lane 0, or the
+// east neighbour of the last column (the halo of lane 63, or the values of
+// the lane just past the last column, whose own result is not stored).  Only
+// a wave whose last column is alone in it (nx = 1 mod 64), which has no
+// second column for an east ghost, takes node_update.
+// The row kernel's path for a wave at a side of the grid (see k_step_rows).
 template <int R, int AUX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const Ghosts &G,
+                                          const float *__restrict__ fin, float *__restrict__ fout,
+                                          unsigned bytes, int x0, int y0, int lane,
+                                          const long long *__restrict__ d_step, int k)
+{
+    const int nx = F.nx, ny = F.ny, x = x0 + lane;
+    const bool west = x0 == 0, east = x0 + 64 >= nx;
+    const bool south = y0 == 0, north = y0 + R >= ny;
+    const int e = nx - 1 - x0;  // lane of the last column, when east
+    // lanes past the last column read the periodic image on a periodic x side
+    const int xl = (x >= nx && G.per_x) ? x - nx : x;
+    int xh = lane < 32 ? x0 - 1 : x0 + 64;
+    if (G.per_x && west && lane < 32) xh = nx - 1;
+    if (G.per_x && east && e == 63 && lane >= 32) xh = 0;
+    const unsigned vo = 4u * (unsigned)(F.xoff + xl);
+    const unsigned vh = 4u * (unsigned)(F.xoff + xh);
+    const unsigned qB = 4u * (unsigned)F.qstride, jB = 4u * (unsigned)F.jstride;
+    const auto rin = buffer_of(fin, bytes);
+    const auto rout = buffer_of(fout, bytes);
+    // byte offset of row j (j = -1 .. ny) of plane q
+    auto row = [&](int q, int j) { return (unsigned)q * qB + (unsigned)(j + 1) * jB; };
+    // rows -1 and ny of a periodic y side are the opposite edge rows
+    auto jrow = [&](int j) { return !G.per_y ? j : j == -1 ? ny - 1 : j == ny ? 0 : j; };
+
+    float v[R + 2][NQ], h[R][NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        v[0][q] = has_y(q) ? bload(rin, vo, row(q, jrow(y0 - 1))) : 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            v[r + 1][q] = bload(rin, vo, row(q, jrow(y0 + r)));
+            h[r][q] = has_x(q) ? bload(rin, vh, row(q, y0 + r)) : 0.f;
+        }
+        v[R + 1][q] = has_y(q) ? bload(rin, vo, row(q, jrow(y0 + R))) : 0.f;
+    }
+    const bool edge = (west && !G.per_x) || (east && !G.per_x) || (south && !G.per_y) ||
+                      (north && !G.per_y);
+    const double t = edge ? step_time(G, d_step, k) : 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = y0 + r;
+        if (y >= ny) break;
+        if (edge) {
+            float g[NQ], n2[NQ];
+            if (y == 0 && !G.per_y) {  // south ghost replaces the row below
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)  // row 1: a wave row when R > 1
+                    n2[q] = (R > 1 || has_y(q)) ? v[r + 2][q] : bload(rin, vo, row(q, 1));
+                ghost_of<2>(K, G, t, x, v[r + 1], n2, g);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    if (has_y(q)) v[r][q] = g[q];
+            }
+            if (y == ny - 1 && !G.per_y) {  // north ghost replaces the row above
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)  // row ny - 2: a wave row when r > 0
+                    n2[q] = (r >= 1 || has_y(q)) ? v[r][q] : bload(rin, vo, row(q, ny - 2));
+                ghost_of<3>(K, G, t, x, v[r + 1], n2, g);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    if (has_y(q)) v[r + 2][q] = g[q];
+            }
+            if (west && !G.per_x) {  // west ghost: the halo of lane 0
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) n2[q] = shl1(v[r + 1][q], 0.f);
+                ghost_of<0>(K, G, t, y, v[r + 1], n2, g);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    if (has_x(q) && lane == 0) h[r][q] = g[q];
+            }
+            if (east && !G.per_x) {
+                if (e == 63) {  // east ghost: the halo of lane 63
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) n2[q] = shr1(v[r + 1][q], 0.f);
+                    ghost_of<1>(K, G, t, y, v[r + 1], n2, g);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        if (has_x(q) && lane == 63) h[r][q] = g[q];
+                } else {  // east ghost: the values of the lane past the last column
+                    float n1[NQ];
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        n1[q] = shr1(v[r + 1][q], 0.f);
+                        n2[q] = shr1(n1[q], 0.f);
+                    }
+                    ghost_of<1>(K, G, t, y, n1, n2, g);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        if (x == nx) v[r + 1][q] = g[q];
+                }
+            }
+        }
+        float dC[NQ];
+        collide(K, v[r + 1], dC);
+        Unroll<NQ>::run([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            float fE = 0.f, fW = 0.f;
+            if (has_x(q)) {
+                fE = shl1(v[r + 1][q], h[r][q]);
+                fW = shr1(v[r + 1][q], h[r][q]);
+            }
+            const float o = lw_update<q>(K, v[r + 1][q], dC[q], fE, fW, v[r + 2][q], v[r][q]);
+            if (x < nx) bstore<AUX>(rout, o, vo, row(q, y));
+        });
+    }
+}
+
+template <int R, int AUX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 1 ? 5 : 4, 8)))
 void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
                  float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
                  const long long *__restrict__ d_step, int k)
@@ -459,11 +577,18 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
     if (rg >= nrg) return;
     const int x0 = col * 64, y0 = rg * R, x = x0 + lane;
     if (col == 0 || x0 + 64 >= F.nx || y0 == 0 || y0 + R >= F.ny) {
-        const double t = step_time(G, d_step, k);
-        if (x < F.nx) {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (y0 + r < F.ny) node_update(F, K, G, fin, fout, x, y0 + r, t);
+        // constants from the device copies (see Ghosts::kd)
+        const Consts &Kd = *G.kd;
+        const Ghosts &Gd = *G.gd;
+        if (x0 + 1 == F.nx) {  // a last column alone in its wave
+            const double t = step_time(Gd, d_step, k);
+            if (x < F.nx) {
+#pragma unroll 1
+                for (int r = 0; r < R; ++r)
+                    if (y0 + r < F.ny) node_update(F, Kd, Gd, fin, fout, x, y0 + r, t);
+            }
+        } else {
+            rows_edge<R, AUX>(F, Kd, Gd, fin, fout, bytes, x0, y0, lane, d_step, k);
         }
         return;
     }
@@ -501,92 +626,6 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
             bstore<AUX>(rout, o, vo, row(q, y0 + r));
         });
     }
-}
-
-// Marching kernel.  Each wave owns R consecutive rows of 64 columns and walks
-// up through them with a three-row window in registers: the whole row being
-// updated, the y-moving populations of the rows below and above, and the
-// row's two outside columns (halo).  While row y is updated, the loads for
-// row y + 1 (its populations with no y component and its halo) and for the
-// y-moving populations of row y + 2 are already in flight, so each wave
-// overlaps its own memory latency with its arithmetic; every population of
-// the grid is loaded once per wave that needs it.  West/east neighbours by
-// DPP as in the row kernel; waves with a node on a side take node_update.
-// Same arithmetic and operation order as every other variant.
-template <int R, int AUX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
-void k_step_march(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
-                  float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
-                  const long long *__restrict__ d_step, int k)
-{
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int b = blockIdx.x;
-    if ((nblocks & 7) == 0) b = (b & 7) * (nblocks >> 3) + (b >> 3);
-    const int col = b % ncol;
-    const int rg = (b / ncol) * 4 + wv;
-    if (rg >= nrg) return;
-    const int x0 = col * 64, y0 = rg * R, x = x0 + lane;
-    if (col == 0 || x0 + 64 >= F.nx || y0 == 0 || y0 + R >= F.ny) {
-        const double t = step_time(G, d_step, k);
-        if (x < F.nx) {
-#pragma unroll 1
-            for (int r = 0; r < R; ++r)
-                if (y0 + r < F.ny) node_update(F, K, G, fin, fout, x, y0 + r, t);
-        }
-        return;
-    }
-    // interior wave: rows y0 - 1 .. y0 + R exist
-    const unsigned vo = 4u * (unsigned)(F.xoff + x);
-    const unsigned vh = 4u * (unsigned)(F.xoff + (lane < 32 ? x0 - 1 : x0 + 64));
-    const unsigned qB = 4u * (unsigned)F.qstride, jB = 4u * (unsigned)F.jstride;
-    const auto rin = buffer_of(fin, bytes);
-    const auto rout = buffer_of(fout, bytes);
-    auto row = [&](int q, int j) { return (unsigned)q * qB + (unsigned)(j + 1) * jB; };
-
-    // C: row y (all populations); P, N: y-moving populations of rows y - 1
-    // and y + 1; H: x-moving populations of the two outside columns of row y
-    float C[NQ], P[NQ], N[NQ], H[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        C[q] = bload(rin, vo, row(q, y0));
-        P[q] = has_y(q) ? bload(rin, vo, row(q, y0 - 1)) : 0.f;
-        N[q] = has_y(q) ? bload(rin, vo, row(q, y0 + 1)) : 0.f;
-        H[q] = has_x(q) ? bload(rin, vh, row(q, y0)) : 0.f;
-    }
-    Unroll<R>::run([&](auto rc) {
-        constexpr int r = decltype(rc)::value;
-        const int y = y0 + r;
-        float N2[NQ], X[NQ], H2[NQ];
-        if (r + 1 < R) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                N2[q] = has_y(q) ? bload(rin, vo, row(q, y + 2)) : 0.f;
-                X[q] = has_y(q) ? 0.f : bload(rin, vo, row(q, y + 1));
-                H2[q] = has_x(q) ? bload(rin, vh, row(q, y + 1)) : 0.f;
-            }
-        }
-        float dC[NQ];
-        collide(K, C, dC);
-        Unroll<NQ>::run([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            float fE = 0.f, fW = 0.f;
-            if (has_x(q)) {
-                fE = shl1(C[q], H[q]);
-                fW = shr1(C[q], H[q]);
-            }
-            bstore<AUX>(rout, lw_update<q>(K, C[q], dC[q], fE, fW, N[q], P[q]), vo, row(q, y));
-        });
-        if (r + 1 < R) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                P[q] = has_y(q) ? C[q] : 0.f;
-                C[q] = has_y(q) ? N[q] : X[q];
-                N[q] = N2[q];
-                H[q] = H2[q];
-            }
-        }
-    });
 }
 
 // ------------------------------------------------- split-BF16 matrix cores
@@ -1273,36 +1312,6 @@ hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
     if (total >= (1LL << 32)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_step_mfma, dim3(nb), dim3(256), 0, s, F, K, G, mo, fin, fout,
                        (unsigned)total, ncol, nrb, nb, d_step, k);
-    return hipGetLastError();
-}
-
-hipError_t launch_step_march(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
-                             float *fout, int rows, int stream_stores, const long long *d_step,
-                             int k, hipStream_t s)
-{
-    const int ncol = (F.nx + 63) / 64;
-    const int nrg = (F.ny + rows - 1) / rows;
-    const int nb = ncol * ((nrg + 3) / 4);
-    const long long total = 4LL * F.total;
-    if (total >= (1LL << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
-    const unsigned bytes = (unsigned)total;
-    switch (rows) {
-#define MRTFD_MARCH(Rr)                                                                            \
-    case Rr:                                                                                       \
-        if (stream_stores)                                                                         \
-            hipLaunchKernelGGL((k_step_march<Rr, 2>), dim3(nb), dim3(256), 0, s, F, K, G, fin,     \
-                               fout, bytes, ncol, nrg, nb, d_step, k);                             \
-        else                                                                                       \
-            hipLaunchKernelGGL((k_step_march<Rr, 0>), dim3(nb), dim3(256), 0, s, F, K, G, fin,     \
-                               fout, bytes, ncol, nrg, nb, d_step, k);                             \
-        break;
-        MRTFD_MARCH(2)
-        MRTFD_MARCH(4)
-        MRTFD_MARCH(8)
-#undef MRTFD_MARCH
-    default:
-        return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 

@@ -10,9 +10,9 @@ from ._abi import check, lib
 
 SIDES = ("west", "east", "south", "north")
 KERNELS = {"auto": _abi.MRTFD_KERNEL_AUTO, "simple": _abi.MRTFD_KERNEL_SIMPLE,
-           "rows": _abi.MRTFD_KERNEL_ROWS, "march": _abi.MRTFD_KERNEL_MARCH}
+           "rows": _abi.MRTFD_KERNEL_ROWS}
 KERNEL_NAMES = {_abi.MRTFD_KERNEL_SIMPLE: "simple", _abi.MRTFD_KERNEL_ROWS: "rows",
-                _abi.MRTFD_KERNEL_MFMA: "mfma", _abi.MRTFD_KERNEL_MARCH: "march"}
+                _abi.MRTFD_KERNEL_MFMA: "mfma"}
 PRECISIONS = {"fp32": _abi.MRTFD_FP32, "bf16x3": _abi.MRTFD_BF16X3}
 
 
