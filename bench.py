@@ -163,7 +163,7 @@ def kernel_sha():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_entry(workload, kernel, seg, streaming, per_launch_cells):
+def traffic_entry(workload, kernel, seg, streaming, tile_order, per_launch_cells):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel source, this workload and kernel variant."""
     try:
@@ -174,7 +174,8 @@ def traffic_entry(workload, kernel, seg, streaming, per_launch_cells):
     for e in rec.get("entries", []):
         if (e.get("source_sha") == kernel_sha() and e.get("workload") == workload
                 and e.get("kernel") == kernel and int(e.get("rows", 0)) == int(seg)
-                and bool(e.get("streaming", False)) == bool(streaming)):
+                and bool(e.get("streaming", False)) == bool(streaming)
+                and int(e.get("tile_order", 0)) == int(tile_order)):
             fetch = e["fetch_kib_per_dispatch"] * 1024 * e["copy_factor_fetch"]
             write = e["write_kib_per_dispatch"] * 1024 * e["copy_factor_write"]
             return {"bytes_per_launch": fetch + write,
@@ -277,7 +278,7 @@ def main():
     ms_step = ms_total / steps
     mlups = cells * steps / (ms_total * 1e-3) / 1e6
     sums = g.sums()
-    kernel, seg, streaming = g.kernel_details()
+    kernel, seg, streaming, tile_order = g.kernel_variant()
     g.close()
     budget = None
     if args.flux_budget:
@@ -294,9 +295,10 @@ def main():
     # the timed region is the step time.
     k_ms = ms_step
     achieved = BYTES_PER_UPDATE * cells / (k_ms * 1e-3) / 1e9
-    traffic = traffic_entry(W["name"], kernel, seg, streaming, cells)
+    traffic = traffic_entry(W["name"], kernel, seg, streaming, tile_order, cells)
     print(f"bench: {W['name']} {steps} steps, {ms_step * 1e3:.2f} us/step, step kernel {kernel}"
-          f"/{seg}{'/nt' if streaming else ''}, {mlups:.0f} MLUPS, {achieved:.0f} GB/s",
+          f"/{seg}{'/nt' if streaming else ''}{'/colbands' if tile_order else ''}, {mlups:.0f} MLUPS, "
+          f"{achieved:.0f} GB/s",
           file=sys.stderr, flush=True)
 
     out = {
@@ -315,6 +317,7 @@ def main():
         "config": {"workload": W["name"], "nx": prob.nx, "ny": prob.ny, "dt": prob.dt,
                    "precision": args.precision, "layout": args.layout,
                    "kernel": kernel, "rows": seg, "streaming_stores": streaming,
+                   "tile_order": tile_order,
                    "graph_steps": args.graph_steps,
                    "gamma": 2.0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

@@ -209,14 +209,17 @@ int32_t mrtfd_outflow(mrtfd_ctx *ctx, double out[16]);
 int32_t mrtfd_set_step(mrtfd_ctx *ctx, int64_t step);
 
 /* The step kernel in use (MRTFD_KERNEL_SIMPLE, _ROWS or _MFMA), its rows
- * per wave, and 1 if it writes with streaming (non-temporal) stores, else 0
- * (host outputs, each may be NULL).  With MRTFD_KERNEL_AUTO, or _ROWS and
+ * per wave, 1 if it writes with streaming (non-temporal) stores, else 0, and
+ * the order in which tiles go to the chip's eight L2 domains: 0 = each takes
+ * a band of whole tile rows, 1 = a band of tile columns (host outputs, each
+ * may be NULL).  With MRTFD_KERNEL_AUTO, or _ROWS and
  * rows = 0, the choice is made by timing the candidates on the first steps
  * of the first mrtfd_step call long enough for a fair trial (a few dozen
  * steps; results are bit-identical whichever runs) and is cached per grid
  * size for later contexts; before that the rows kernel with one row per wave
  * and plain stores runs. */
-int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_t *streaming);
+int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_t *streaming,
+                          int32_t *tile_order);
 
 /* The library's FP64 model on the host: velocity set v[16][2] (Eq. 4), M
  * [16][16] (Eq. 5, row-major, M[k][i] = m_{k+1}(v_i)) and its inverse, as

@@ -89,7 +89,7 @@ _PROTOS = {
     "mrtfd_time": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "mrtfd_set_step": (C.c_int32, [_vp, C.c_int64]),
     "mrtfd_kernel_info": (C.c_int32, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                      C.POINTER(C.c_int32)]),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "mrtfd_model": (C.c_int32, [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "mrtfd_struct_sizes": (C.c_int32, [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "mrtfd_status_string": (C.c_char_p, [C.c_int32]),

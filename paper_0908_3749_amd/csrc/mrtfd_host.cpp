@@ -505,8 +505,8 @@ hipError_t launch_step(mrtfd_ctx *c, const float *fin, float *fout, int k, hipSt
     if (c->kernel == MRTFD_KERNEL_SIMPLE)
         return launch_step_simple(c->F, c->K, c->G, fin, fout, c->d_step, k, s);
     if (c->kernel == MRTFD_KERNEL_ROWS)
-        return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg & 15, c->seg >> 4, c->d_step, k,
-                                s);
+        return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg & 15, (c->seg >> 4) & 1,
+                                (c->seg >> 5) & 1, c->d_step, k, s);
     return launch_step_mfma(c->F, c->K, c->G, c->d_mfma, fin, fout, c->d_step, k, s);
 }
 
@@ -613,14 +613,18 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
         }
     }
     std::vector<std::pair<int, int>> cands;
-    // second: rows per wave, and (bit 4) streaming stores
+    // second: rows per wave, (bit 4) streaming stores, (bit 5) tile order by
+    // column bands
     if (c->p.kernel == MRTFD_KERNEL_SIMPLE) {
         cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     } else {
+        const bool bands = ((c->p.nx + 63) / 64) % 8 == 0;
         for (int r = 1; r <= 2; ++r) {
             if (c->p.rows && r != c->p.rows) continue;
-            cands.push_back({MRTFD_KERNEL_ROWS, r});
-            cands.push_back({MRTFD_KERNEL_ROWS, r | 16});
+            for (int o = 0; o <= (bands ? 1 : 0); ++o) {
+                cands.push_back({MRTFD_KERNEL_ROWS, r | (o << 5)});
+                cands.push_back({MRTFD_KERNEL_ROWS, r | 16 | (o << 5)});
+            }
         }
         if (c->p.kernel == MRTFD_KERNEL_AUTO) cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     }
@@ -964,12 +968,14 @@ int32_t mrtfd_set_step(mrtfd_ctx *c, int64_t step)
     return MRTFD_OK;
 }
 
-int32_t mrtfd_kernel_info(mrtfd_ctx *c, int32_t *kernel, int32_t *rows, int32_t *streaming)
+int32_t mrtfd_kernel_info(mrtfd_ctx *c, int32_t *kernel, int32_t *rows, int32_t *streaming,
+                          int32_t *tile_order)
 {
     if (!c) return MRTFD_ERR_ARG;
     if (kernel) *kernel = c->kernel;
     if (rows) *rows = c->seg & 15;
     if (streaming) *streaming = (c->seg >> 4) & 1;
+    if (tile_order) *tile_order = (c->seg >> 5) & 1;
     return MRTFD_OK;
 }
 

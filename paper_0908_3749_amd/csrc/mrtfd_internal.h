@@ -110,9 +110,12 @@ hipError_t launch_init(const Field &F, const Consts &K, float *f, const float *r
 // rules read the clock from there).
 hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
                               float *fout, const long long *d_step, int k, hipStream_t s);
+// rows per wave (1 or 2); stream_stores: non-temporal stores; order: tiles
+// to XCDs in bands of tile rows (0) or of tile columns (1, when the number of
+// tile columns divides by 8; else 0).
 hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
-                            float *fout, int rows, int stream_stores, const long long *d_step,
-                            int k, hipStream_t s);
+                            float *fout, int rows, int stream_stores, int order,
+                            const long long *d_step, int k, hipStream_t s);
 // Outflow budget (FP64).  cx[q] = {(dt/dx) v_qx / 2, (dt/dx) v_qx^2 dt / (2 dx)}
 // and likewise cy along y: the face value of the A.1b difference between a
 // node at the lower coordinate (lo) and the next one (hi) is

@@ -563,17 +563,27 @@ template <int R, int AUX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 1 ? 5 : 4, 8)))
 void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
                  float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
-                 const long long *__restrict__ d_step, int k)
+                 const long long *__restrict__ d_step, int k, int order)
 {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // Consecutive blocks land on different XCDs (round robin over 8); give
-    // each XCD a contiguous range of blocks so that neighbouring tiles, which
-    // share halo rows and columns, share an L2.
+    // each XCD a contiguous range of tiles so that neighbouring tiles, which
+    // share halo rows and columns, share an L2: a band of whole tile rows
+    // (order 0), or of ncol/8 tile columns (order 1, taken when the tile
+    // columns and blocks divide by 8).
     int b = blockIdx.x;
     if ((nblocks & 7) == 0) b = (b & 7) * (nblocks >> 3) + (b >> 3);
-    const int col = b % ncol;
-    const int rg = (b / ncol) * 4 + wv;
+    int col, rb;
+    if (order == 1) {
+        const int cw = ncol >> 3, nrb = nblocks / ncol;
+        col = (b / (nrb * cw)) * cw + b % cw;
+        rb = (b / cw) % nrb;
+    } else {
+        col = b % ncol;
+        rb = b / ncol;
+    }
+    const int rg = rb * 4 + wv;
     if (rg >= nrg) return;
     const int x0 = col * 64, y0 = rg * R, x = x0 + lane;
     if (col == 0 || x0 + 64 >= F.nx || y0 == 0 || y0 + R >= F.ny) {
@@ -1154,12 +1164,13 @@ hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, 
 }
 
 hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
-                            float *fout, int rows, int stream_stores, const long long *d_step,
-                            int k, hipStream_t s)
+                            float *fout, int rows, int stream_stores, int order,
+                            const long long *d_step, int k, hipStream_t s)
 {
     const int ncol = (F.nx + 63) / 64;
     const int nrg = (F.ny + rows - 1) / rows;
     const int nb = ncol * ((nrg + 3) / 4);
+    const int ord = (order == 1 && (ncol & 7) == 0) ? 1 : 0;  // column bands need ncol % 8 == 0
     const long long total = 4LL * F.total;
     if (total >= (1LL << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
     const unsigned bytes = (unsigned)total;
@@ -1169,10 +1180,10 @@ hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, co
     case Rr:                                                                                       \
         if (stream_stores)                                                                         \
             hipLaunchKernelGGL((k_step_rows<Rr, 2>), dim3(nb), dim3(256), 0, s, F, K, G, fin,      \
-                               fout, bytes, ncol, nrg, nb, d_step, k);                             \
+                               fout, bytes, ncol, nrg, nb, d_step, k, ord);                        \
         else                                                                                       \
             hipLaunchKernelGGL((k_step_rows<Rr, 0>), dim3(nb), dim3(256), 0, s, F, K, G, fin,      \
-                               fout, bytes, ncol, nrg, nb, d_step, k);                             \
+                               fout, bytes, ncol, nrg, nb, d_step, k, ord);                        \
         break;
         MRTFD_ROWS(1)
         MRTFD_ROWS(2)

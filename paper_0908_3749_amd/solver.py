@@ -172,9 +172,14 @@ class MRT2D:
 
     def kernel_details(self):
         """(kernel name, rows per wave, streaming stores) of the step kernel."""
-        k, s, st = C.c_int32(), C.c_int32(), C.c_int32()
-        check(lib().mrtfd_kernel_info(self._ctx, C.byref(k), C.byref(s), C.byref(st)), self._ctx)
-        return KERNEL_NAMES.get(k.value, "none"), s.value, bool(st.value)
+        return self.kernel_variant()[:3]
+
+    def kernel_variant(self):
+        """(kernel name, rows per wave, streaming stores, tile order)."""
+        k, s, st, o = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().mrtfd_kernel_info(self._ctx, C.byref(k), C.byref(s), C.byref(st), C.byref(o)),
+              self._ctx)
+        return KERNEL_NAMES.get(k.value, "none"), s.value, bool(st.value), o.value
 
     def close(self):
         if self._ctx:

@@ -188,13 +188,14 @@ def test_graph_replay_equals_direct_launches(gpu):
     assert np.array_equal(got, ref)
 
 
-def test_autotune_trial_steps_are_ordinary_steps(gpu):
+@pytest.mark.parametrize("nx,ny", [(141, 43), (500, 40)])
+def test_autotune_trial_steps_are_ordinary_steps(gpu, nx, ny):
     """The autotuner times the candidate kernels on steps of the run itself:
-    a run that tunes (grid size unique to this test, so nothing is cached)
-    equals a run with a fixed kernel bit for bit, clock and time-dependent
-    boundary split included, whether the first call is too short to tune or
-    not; afterwards the choice is final and reported."""
-    nx, ny = 141, 43
+    a run that tunes (grid sizes unique to this test, so nothing is cached;
+    500 columns make 8 tile columns, so both tile orders run) equals a run
+    with a fixed kernel bit for bit, clock and time-dependent boundary split
+    included, whether the first call is too short to tune or not; afterwards
+    the choice is final and reported."""
     f0 = synth.random_populations(nx, ny, seed=6)
     prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["wall_split"], None)
     ref, _, _ = run_gpu(gpu, prob, f0, 401, kernel="simple")
