@@ -635,7 +635,7 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
         return MRTFD_OK;
     }
     const double cells = (double)c->p.nx * c->p.ny;
-    const long long reps = 2 * (long long)std::max(2.0, std::min(16.0, 1e7 / cells));
+    const long long reps = 2 * (long long)std::max(4.0, std::min(16.0, 1e7 / cells));
     const long long warm = 2;
     if (avail < (long long)cands.size() * (reps + warm)) return MRTFD_OK;
     hipEvent_t e0, e1;
