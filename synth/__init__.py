@@ -297,7 +297,7 @@ def generic(nx, ny, dx, dt, s, sides, ic, nsteps=0, name="generic"):
 
 
 def tube_batch(ntubes=512, nmin=200, nmax=8000, seed=12345, dx=0.002, dt=1e-5,
-               cfl_fraction=0.8, star_fn=None, min_star_density=0.05):
+               cfl_fraction=0.8, star_fn=None, min_star_density=0.05, max_temperature=200.0):
     """Independent 1D Riemann problems, each n_k x 4 cells, periodic in y and
     f = f^eq of its initial states at both ends, interface at the middle.
     n_k ~ U{nmin..nmax}; per side rho ~ U[0.1,5], u ~ U[-2,2], p ~ U[0.1,100],
@@ -305,22 +305,27 @@ def tube_batch(ntubes=512, nmin=200, nmax=8000, seed=12345, dx=0.002, dt=1e-5,
 
     Each tube runs to t_end = cfl_fraction * (n_k/2) dx / S_max, where S_max
     is its fastest wave speed.  star_fn(left, right) -> (S_max, min star
-    density) is supplied by the caller (an exact Riemann solver); draws with
-    vacuum (star_fn raising ValueError) or a star density below
-    min_star_density are redrawn."""
+    density, max star temperature) is supplied by the caller (an exact
+    Riemann solver); draws with vacuum (star_fn raising ValueError), a star
+    density below min_star_density, or a temperature T = p / rho above
+    max_temperature in an end or star state are redrawn.  (With these rates
+    and this grid the linear stability screen of Sect. IV finds growing
+    modes for the 16-velocity model above T of about 200.)"""
     rng = np.random.default_rng(seed)
     tubes = []
     while len(tubes) < ntubes:
         n = int(rng.integers(nmin, nmax + 1))
         L = (rng.uniform(0.1, 5.0), rng.uniform(-2.0, 2.0), rng.uniform(0.1, 100.0))
         R = (rng.uniform(0.1, 5.0), rng.uniform(-2.0, 2.0), rng.uniform(0.1, 100.0))
+        if max(L[2] / L[0], R[2] / R[0]) > max_temperature:
+            continue
         smax = None
         if star_fn is not None:
             try:
-                smax, rmin = star_fn(L, R)
+                smax, rmin, tmax = star_fn(L, R)
             except ValueError:
                 continue
-            if rmin < min_star_density:
+            if rmin < min_star_density or tmax > max_temperature:
                 continue
         steps = None
         if smax is not None:

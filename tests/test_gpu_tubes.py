@@ -17,7 +17,8 @@ THREADS = max(1, min(16, os.cpu_count() or 1))
 
 def star_fn(L, R):
     W = riemann.wave_speeds(L, R)
-    return riemann.max_signal_speed(L, R), min(W["rho_star_left"], W["rho_star_right"])
+    return (riemann.max_signal_speed(L, R), min(W["rho_star_left"], W["rho_star_right"]),
+            W["pstar"] / min(W["rho_star_left"], W["rho_star_right"]))
 
 
 @pytest.fixture(scope="module")

@@ -69,3 +69,35 @@ def test_sod_parameters_are_linearly_stable(S):
     for st in ((1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.8)):
         w, _ = S.max_growth(st, prob.s, prob.dx, prob.dy, prob.dt, n=12)
         assert w <= 1.0 + 1e-9, (st, w)
+
+
+def test_default_tube_batch_is_linearly_stable(S):
+    """Every tube of the seeded 512-tube batch stays in the range where the
+    screen finds no mode that grows materially over the tube's own run: at
+    both end states and both star states, max |omega| ** steps <= 4 for the
+    batch's rates, dx and dt (coarse phase grid).  Hot states (T above about
+    200, redrawn by the generator) would give max |omega| up to 1.1, i.e.
+    growth by e^100 over a few thousand steps; a few cold, fast states
+    (T < 1, Mach > 2) sit at 1 + 1e-5 and stay below 3x over their runs."""
+    from oracle import riemann
+
+    def star(L, R):
+        W = riemann.wave_speeds(L, R)
+        return (riemann.max_signal_speed(L, R), min(W["rho_star_left"], W["rho_star_right"]),
+                W["pstar"] / min(W["rho_star_left"], W["rho_star_right"]))
+
+    batch = synth.tube_batch(star_fn=star)
+    dx, dt, s = batch["dx"], batch["dt"], batch["s"]
+    worst = 0.0
+    import math
+    for t in batch["tubes"]:
+        L, R = t["left"], t["right"]
+        W = riemann.wave_speeds(L, R)
+        states = [(L[0], L[1], L[2] / L[0]), (R[0], R[1], R[2] / R[0]),
+                  (W["rho_star_left"], W["ustar"], W["pstar"] / W["rho_star_left"]),
+                  (W["rho_star_right"], W["ustar"], W["pstar"] / W["rho_star_right"])]
+        for rho, u, T in states:
+            w, _ = S.max_growth((rho, u, 0.0, T), s, dx, dx, dt, n=4)
+            worst = max(worst, t["steps"] * math.log(max(w, 1.0)))
+    print("largest growth over a run", math.exp(worst))
+    assert math.exp(worst) <= 4.0
