@@ -251,9 +251,8 @@ typedef struct mrtfd_batch_params {
     double dx, dt;       /* node spacing (dx = dy) and time step, all tubes     */
     double s[16];        /* relaxation rates as in mrtfd_params, all tubes      */
     int32_t seg_cols;    /* columns per work item, 0 = autotune; built pairs
-                            (seg_cols, round_steps): (32,16) (48,8) (96,16)
-                            (112,8)                                          */
-    int32_t round_steps; /* steps per round (8 or 16), 0 = autotune          */
+                            (seg_cols, round_steps): (32,16) (48,8) (56,4)   */
+    int32_t round_steps; /* steps per round (4, 8 or 16), 0 = autotune       */
     int32_t use_graph;   /* 1: replay all rounds as one captured HIP graph      */
 } mrtfd_batch_params;
 

@@ -991,7 +991,7 @@ struct BatchLayout {
     size_t max_items;
 };
 
-const int kTubeSegs[] = {32, 48, 96, 112};
+const int kTubeSegs[] = {32, 48, 56};
 
 int batch_check(const mrtfd_batch_params *p, const int32_t *n, char *msg, size_t len)
 {
@@ -1016,10 +1016,10 @@ int batch_check(const mrtfd_batch_params *p, const int32_t *n, char *msg, size_t
     if (6.0 * p->dt / p->dx > 1.0) return fail(MRTFD_ERR_UNSTABLE, "Courant number 6 dt / dx exceeds 1");
     if (p->seg_cols && p->round_steps && !tubes_config_built(p->seg_cols, p->round_steps))
         return fail(MRTFD_ERR_ARG, "seg_cols/round_steps pair not built");
-    if (p->seg_cols && p->seg_cols != 32 && p->seg_cols != 48 && p->seg_cols != 96 && p->seg_cols != 112)
-        return fail(MRTFD_ERR_ARG, "seg_cols must be 0, 32, 48, 96 or 112");
-    if (p->round_steps && p->round_steps != 8 && p->round_steps != 16)
-        return fail(MRTFD_ERR_ARG, "round_steps must be 0, 8 or 16");
+    if (p->seg_cols && p->seg_cols != 32 && p->seg_cols != 48 && p->seg_cols != 56)
+        return fail(MRTFD_ERR_ARG, "seg_cols must be 0, 32, 48 or 56");
+    if (p->round_steps && p->round_steps != 4 && p->round_steps != 8 && p->round_steps != 16)
+        return fail(MRTFD_ERR_ARG, "round_steps must be 0, 4, 8 or 16");
     long long total = 0;
     for (int k = 0; k < p->ntubes; ++k) {
         if (n[k] < 3) return fail(MRTFD_ERR_ARG, "tube %d has %d < 3 columns", k, n[k]);
@@ -1155,7 +1155,7 @@ int batch_autotune(mrtfd_batch *b)
     std::vector<std::vector<TubeItem>> keep;  // host sources of the async uploads
     for (int seg : kTubeSegs) {
         if (b->p.seg_cols && seg != b->p.seg_cols) continue;
-        for (int ks : {8, 16}) {
+        for (int ks : {4, 8, 16}) {
             if (b->p.round_steps && ks != b->p.round_steps) continue;
             if (!tubes_config_built(seg, ks)) continue;
             keep.emplace_back();

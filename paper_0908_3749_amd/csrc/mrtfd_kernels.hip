@@ -777,15 +777,20 @@ __global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
 // ------------------------------------------------------------- tube batches
 
 // Temporal blocking of one work item (columns [x0, x0 + S) of a tube) over KS
-// steps in LDS.  The block loads columns x0 - KS .. x0 + S + KS of all rows and
-// populations once, then advances them KS steps in LDS: after each step the
-// outermost valid column on each side goes stale (a trapezoid), except at the
-// ends of the tube, where the column beyond the end holds the constant
-// boundary equilibrium for every step.  After the last step the S owned
-// columns are written back.  Each node's update is the same arithmetic as the
-// single-grid kernels (collide, then the east/west/north/south terms in that
-// order), so a tube run here equals the same tube run as a grid, bit for bit.
-// LDS: 2 copies x 16 populations x 4 rows x (S + 2 KS) floats.
+// steps.  The block covers the 4 rows of columns x0 - KS .. x0 + S + KS - 1
+// (64 columns: one wave per row, one lane per column) and keeps each node's
+// 16 populations in registers for the whole round: west/east neighbours come
+// from the adjacent lanes by DPP, north/south neighbours (the rows are
+// periodic) from the other waves through LDS, where each step publishes the
+// populations that move in y.  After each step the outermost valid column on
+// each side goes stale (a trapezoid), except at the ends of the tube, where
+// the column beyond the end holds the constant boundary equilibrium for every
+// step.  After the last step the S owned columns are written back.  Each
+// node's update is the same arithmetic as the single-grid kernels (collide,
+// then the east/west/north/south terms in that order), so a tube run here
+// equals the same tube run as a grid, bit for bit.
+__host__ __device__ constexpr int yslot(int q) { return q < 8 ? q >> 1 : q - 4; }  // has_y(q)
+
 template <int S, int KS>
 __global__ __launch_bounds__(256) void k_tubes(TubeGrid TG, Consts K,
                                                const TubeInfo *__restrict__ tubes,
@@ -795,8 +800,8 @@ __global__ __launch_bounds__(256) void k_tubes(TubeGrid TG, Consts K,
 {
     constexpr int TW = S + 2 * KS;
     constexpr int WY = TUBE_ROWS;
-    static_assert(TW % 64 == 0 && WY * 64 == 256, "one thread per (row, column lane)");
-    __shared__ float buf[2][NQ][WY][TW];
+    static_assert(TW == 64 && WY * 64 == 256, "one wave per row, one lane per column");
+    __shared__ float ybuf[2][12][WY][TW];  // y-moving populations, by step parity
     const TubeItem it = items[blockIdx.x];
     const int n = tubes[it.tube].n;
     const int start = tubes[it.tube].start;
@@ -804,63 +809,53 @@ __global__ __launch_bounds__(256) void k_tubes(TubeGrid TG, Consts K,
     const int xbase = it.x0 - KS;  // tube column of tile column 0
     const int cL = -1 - xbase;     // tile column of the west boundary node (x = -1)
     const int cR = n - xbase;      // tile column of the east boundary node (x = n)
-    const float *feqL = tubes[it.tube].feq_left;
-    const float *feqR = tubes[it.tube].feq_right;
-    for (int idx = threadIdx.x; idx < NQ * WY * TW; idx += 256) {
-        const int q = idx / (WY * TW), rem = idx % (WY * TW);
-        const int y = rem / TW, c = rem % TW;
-        const int x = xbase + c;
+    const int y = threadIdx.x >> 6, c = threadIdx.x & 63;
+    const int yn = y == WY - 1 ? 0 : y + 1, ys = y == 0 ? WY - 1 : y - 1;
+    const int x = xbase + c;
+    const long long base = (long long)y * TG.ncols + start + x;
+    float f[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
         float v = 0.f;
         if (x >= 0 && x < n)
-            v = fin[(long long)q * TG.plane + (long long)y * TG.ncols + start + x];
+            v = fin[(long long)q * TG.plane + base];
         else if (x == -1)
-            v = feqL[q];
+            v = tubes[it.tube].feq_left[q];
         else if (x == n)
-            v = feqR[q];
-        buf[0][q][y][c] = v;
-        buf[1][q][y][c] = v;
+            v = tubes[it.tube].feq_right[q];
+        f[q] = v;
     }
-    __syncthreads();
-    int src = 0;
-    // thread -> (row, column lane); TW is a multiple of 64
-    const int y = threadIdx.x >> 6, cl = threadIdx.x & 63;
-    const int yn = y == WY - 1 ? 0 : y + 1, ys = y == 0 ? WY - 1 : y - 1;
     for (int st = 0; st < nsteps; ++st) {
         // valid input columns [a, b); update a+1 .. b-2 (interior nodes only)
         const int a = cL >= 0 ? cL : st;
         const int b = cR < TW ? cR + 1 : TW - st;
+        const bool upd = c > a && c < b - 1;
+        float(*yb)[WY][TW] = ybuf[st & 1];
 #pragma unroll
-        for (int mcol = 0; mcol < TW / 64; ++mcol) {
-            const int c = 64 * mcol + cl;
-            if (c > a && c < b - 1) {
-                float fc[NQ], dC[NQ];
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) fc[q] = buf[src][q][y][c];
-                collide(K, fc, dC);
-                Unroll<NQ>::run([&](auto qc) {
-                    constexpr int q = decltype(qc)::value;
-                    float fE = 0.f, fW = 0.f, fN = 0.f, fS = 0.f;
-                    if (has_x(q)) {
-                        fE = buf[src][q][y][c + 1];
-                        fW = buf[src][q][y][c - 1];
-                    }
-                    if (has_y(q)) {
-                        fN = buf[src][q][yn][c];
-                        fS = buf[src][q][ys][c];
-                    }
-                    buf[src ^ 1][q][y][c] = lw_update<q>(K, fc[q], dC[q], fE, fW, fN, fS);
-                });
-            }
-        }
+        for (int q = 0; q < NQ; ++q)
+            if (has_y(q)) yb[yslot(q)][y][c] = f[q];
         __syncthreads();
-        src ^= 1;
+        float dC[NQ], g[NQ];
+        collide(K, f, dC);
+        Unroll<NQ>::run([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            float fE = 0.f, fW = 0.f, fN = 0.f, fS = 0.f;
+            if (has_x(q)) {  // lanes 0 and 63 are never updated
+                fE = shl1(f[q], 0.f);
+                fW = shr1(f[q], 0.f);
+            }
+            if (has_y(q)) {
+                fN = yb[yslot(q)][yn][c];
+                fS = yb[yslot(q)][ys][c];
+            }
+            g[q] = lw_update<q>(K, f[q], dC[q], fE, fW, fN, fS);
+        });
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) f[q] = upd ? g[q] : f[q];
     }
-    for (int idx = threadIdx.x; idx < NQ * WY * S; idx += 256) {
-        const int q = idx / (WY * S), rem = idx % (WY * S);
-        const int y = rem / S, c = KS + rem % S;
-        const int x = xbase + c;
-        if (x >= 0 && x < n)
-            fout[(long long)q * TG.plane + (long long)y * TG.ncols + start + x] = buf[src][q][y][c];
+    if (c >= KS && c < KS + S && x >= 0 && x < n) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) fout[(long long)q * TG.plane + base] = f[q];
     }
 }
 
@@ -1261,7 +1256,7 @@ hipError_t launch_unpack(const Field &F, const float *src, float *f, hipStream_t
 
 // ------------------------------------------------------------ tube launchers
 
-#define MRTFD_TUBE_CONFIGS(X) X(48, 8) X(32, 16) X(112, 8) X(96, 16)
+#define MRTFD_TUBE_CONFIGS(X) X(48, 8) X(32, 16) X(56, 4)
 
 bool tubes_config_built(int seg, int round_steps)
 {

@@ -50,8 +50,8 @@ def single_grid(P, batch, k):
     return f
 
 
-@pytest.mark.parametrize("cfg", [dict(), dict(seg_cols=48, round_steps=8), dict(seg_cols=96, round_steps=16),
-                                 dict(seg_cols=112, round_steps=8, use_graph=True),
+@pytest.mark.parametrize("cfg", [dict(), dict(seg_cols=48, round_steps=8), dict(seg_cols=56, round_steps=4),
+                                 dict(seg_cols=48, round_steps=8, use_graph=True),
                                  dict(seg_cols=32, round_steps=16, use_graph=True)])
 def test_batch_equals_single_grid_bitwise(gpu, small_batch, cfg):
     B = gpu.TubeBatch.from_description(small_batch, **cfg)
