@@ -326,6 +326,18 @@ int check(const mrtfd_params *p, char *msg, size_t len)
     if (p->nx < 3 || p->ny < 3) return fail(MRTFD_ERR_ARG, "nx and ny must be >= 3 (got %d, %d)", p->nx, p->ny);
     if ((long long)p->nx * p->ny > (1LL << 31))
         return fail(MRTFD_ERR_ARG, "grid of %lld nodes is too large", (long long)p->nx * p->ny);
+    {
+        // the row and matrix-core kernels address one copy of f with 32-bit
+        // byte offsets: (ny + 2) rows of 16 x pitch floats must stay below 4 GiB
+        const long long pitch = ((long long)p->nx + 65 + 63) / 64 * 64;
+        const long long bytes = 4LL * NQ * pitch * ((long long)p->ny + 2);
+        if (bytes >= (1LL << 32) && p->kernel != MRTFD_KERNEL_SIMPLE)
+            return fail(MRTFD_ERR_ARG,
+                        "grid %d x %d needs %lld bytes per copy of f: above 4 GiB only "
+                        "MRTFD_KERNEL_SIMPLE (FP32) runs it", p->nx, p->ny, bytes);
+        if (bytes >= (1LL << 32) && p->precision != MRTFD_FP32)
+            return fail(MRTFD_ERR_ARG, "grids above 4 GiB per copy run in FP32 only");
+    }
     if (!(p->dx > 0) || !(p->dy > 0) || !(p->dt > 0) || !std::isfinite(p->dx) ||
         !std::isfinite(p->dy) || !std::isfinite(p->dt))
         return fail(MRTFD_ERR_ARG, "dx, dy, dt must be positive and finite");

@@ -110,6 +110,17 @@ def test_validation_rejects_bad_params(abi):
     for k in range(4, 16):
         p.s[k] = 4e4
     assert check_params(p)[0] == abi.MRTFD_OK
+    # one copy of f above 4 GiB (9000 x 8000 nodes): only the simple kernel
+    # addresses it; the row kernels' 32-bit buffer offsets cannot
+    p = _params(prob)
+    p.nx, p.ny = 9000, 8000
+    st, msg = check_params(p)
+    assert st == abi.MRTFD_ERR_ARG and "4 GiB" in msg, msg
+    p.kernel = abi.MRTFD_KERNEL_SIMPLE
+    assert check_params(p)[0] == abi.MRTFD_OK
+    p.nx, p.ny = 8192, 8000  # 4.2e9 B per copy: just below
+    p.kernel = abi.MRTFD_KERNEL_AUTO
+    assert check_params(p)[0] == abi.MRTFD_OK
 
 
 def test_create_rejects_bad_workspace_without_gpu(abi):

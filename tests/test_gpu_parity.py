@@ -349,16 +349,16 @@ def transform_scale(prob, f):
     return float(np.max(af + np.max(np.abs(f), axis=0, keepdims=True)))
 
 
-@pytest.mark.parametrize("config", ["mach3", "bubble"])
+@pytest.mark.parametrize("config", ["mach3", "bubble", "couette"])
 def test_full_size_steps_match_oracle(gpu, config):
     """At the benchmark's full sizes (2048x512 Mach reflection, 4096x1024
-    shock-bubble) and in its launch configuration (autotuned kernel, graph
+    shock-bubble, 8192x2048 Couette) and in its launch configuration (graph
     of 64 steps): a few steps from the oracle's initial state (rounded to
     FP32) agree with the whole-grid FP64 oracle node by node, within
     4 n u S after n steps, S = transform_scale (each step's rounding is a few
     u of the magnitudes the collision cancels)."""
-    prob = synth.mach_reflection() if config == "mach3" else synth.shock_bubble()
-    n = 4 if config == "mach3" else 2
+    prob = {"mach3": synth.mach_reflection, "bubble": synth.shock_bubble, "couette": synth.couette}[config]()
+    n = {"mach3": 4, "bubble": 2, "couette": 2}[config]
     o = core.Grid(prob, nthreads=THREADS)
     o.init_problem()
     f0 = o.get_f().astype(np.float32)
