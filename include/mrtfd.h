@@ -213,11 +213,12 @@ int32_t mrtfd_set_step(mrtfd_ctx *ctx, int64_t step);
  * the order in which tiles go to the chip's eight L2 domains: 0 = each takes
  * a band of whole tile rows, 1 = a band of tile columns (host outputs, each
  * may be NULL).  With MRTFD_KERNEL_AUTO, or _ROWS and
- * rows = 0, the choice is made by timing the candidates on the first steps
- * of the first mrtfd_step call long enough for a fair trial (a few dozen
- * steps; results are bit-identical whichever runs) and is cached per grid
- * size for later contexts; before that the rows kernel with one row per wave
- * and plain stores runs. */
+ * rows = 0, the choice is made by timing the candidates (rows per wave,
+ * store kind, tile order, and the simple kernel) on the first steps of the
+ * first mrtfd_step call long enough for a fair trial (up to about 300 steps;
+ * results are bit-identical whichever runs) and is cached per grid size for
+ * later contexts; before that the rows kernel with one row per wave and
+ * plain stores runs. */
 int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_t *streaming,
                           int32_t *tile_order);
 
