@@ -112,6 +112,53 @@ def test_one_step_grid_widths(gpu, nx, sides):
             assert np.array_equal(got, ref), (nx, ny, kern, seg, np.max(np.abs(got - ref)))
 
 
+@pytest.mark.parametrize("shape", [(3, 3), (3, 70), (70, 3), (65, 4)])
+@pytest.mark.parametrize("sides", sorted(SIDE_SETS))
+def test_smallest_grids(gpu, shape, sides):
+    """Degenerate shapes (3 x 3 is the smallest grid; one-wave and one-row-
+    group grids; a width with a lone last column): five steps of every
+    variant agree bit for bit and with the oracle."""
+    nx, ny = shape
+    f0 = synth.random_populations(nx, ny, seed=nx * 100 + ny)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS[sides], None)
+    want, _ = run_oracle(prob, f0, 5)
+    outs = [run_gpu(gpu, prob, f0, 5, kernel=k, rows=r)[0] for k, r in VARIANTS]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert np.max(np.abs(outs[0] - want)) <= 5 * 2e-6 * np.max(np.abs(want))
+
+
+def test_largest_grid_sampled(gpu):
+    """Largest grid whose copy of f stays below 4 GiB (8192 x 7990 nodes,
+    32-bit buffer offsets up to 4.26e9 B), periodic, one step of the row
+    kernel with one and two rows per wave: sampled nodes -- random ones, the
+    last grid row and column, the corners -- agree with the oracle's node
+    update computed from the same FP32 state."""
+    nx, ny = 8192, 7990
+    ic = synth.smooth_macro(nx, ny, seed=31, du=0.2, dr=0.1)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"], ic)
+    rng = np.random.default_rng(5)
+    pts = [(int(i), int(j)) for i, j in zip(rng.integers(0, nx, 200), rng.integers(0, ny, 200))]
+    pts += [(i, ny - 1) for i in (0, 1, 63, 64, nx - 65, nx - 2, nx - 1)]
+    pts += [(nx - 1, j) for j in (0, 1, ny // 2, ny - 2)] + [(0, 0), (0, ny - 1)]
+    for rows in (1, 2):
+        g = gpu.from_problem(prob, kernel="rows", rows=rows)
+        g.init_problem(prob)
+        f0 = g.get_f_numpy()
+        g.step(1)
+        f1 = g.get_f_numpy()
+        g.close()
+        scale = float(np.max(np.abs(f0)))
+        err = 0.0
+        for i, j in pts:
+            col = lambda a, b: f0[:, b % ny, a % nx]
+            want = core.cell_update(prob, col(i, j), col(i + 1, j), col(i - 1, j), col(i, j + 1), col(i, j - 1))
+            err = max(err, float(np.max(np.abs(f1[:, j, i] - want))))
+        del f0, f1
+        print(f"largest grid, rows {rows}: max err over {len(pts)} sampled nodes {err:.3e}")
+        assert err <= 2e-6 * scale
+
+
 @pytest.mark.parametrize("sides", ["periodic", "reflect_extrapolate", "wall_split"])
 def test_smooth_flow_many_steps(gpu, sides):
     nx, ny = 130, 70
