@@ -197,7 +197,7 @@ def main():
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
-    ap.add_argument("--layout", default="rows", choices=["rows", "planes"])
+    ap.add_argument("--layout", default="rows", choices=["rows", "planes", "tiles"])
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="oracle steps on the crop (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")

@@ -86,6 +86,8 @@ extern "C" {
 #define MRTFD_LAYOUT_ROWS 0   /* per grid row, the 16 population rows side by
                                  side                                          */
 #define MRTFD_LAYOUT_PLANES 1 /* 16 whole-grid population planes             */
+#define MRTFD_LAYOUT_TILES 2  /* per grid row and 64-column piece, the 16
+                                 population pieces side by side (4 KiB)        */
 
 /* ---- kernel choice for the step ---------------------------------------- */
 #define MRTFD_KERNEL_AUTO 0   /* autotuned among the variants below            */

@@ -32,6 +32,7 @@ MRTFD_BF16X3 = 1
 
 MRTFD_LAYOUT_ROWS = 0
 MRTFD_LAYOUT_PLANES = 1
+MRTFD_LAYOUT_TILES = 2
 
 MRTFD_COLLISION_MRT = 0
 MRTFD_COLLISION_SRT = 1

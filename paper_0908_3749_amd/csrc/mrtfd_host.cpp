@@ -358,7 +358,8 @@ int check(const mrtfd_params *p, char *msg, size_t len)
             if (p->s[k] != p->s[4])
                 return fail(MRTFD_ERR_ARG, "single relaxation time needs s_6..s_16 equal to s_5");
     }
-    if (p->layout != MRTFD_LAYOUT_ROWS && p->layout != MRTFD_LAYOUT_PLANES)
+    if (p->layout != MRTFD_LAYOUT_ROWS && p->layout != MRTFD_LAYOUT_PLANES &&
+        p->layout != MRTFD_LAYOUT_TILES)
         return fail(MRTFD_ERR_ARG, "unknown layout %d", p->layout);
     if (p->kernel != MRTFD_KERNEL_AUTO && p->kernel != MRTFD_KERNEL_SIMPLE &&
         p->kernel != MRTFD_KERNEL_ROWS)
@@ -404,9 +405,14 @@ Field make_field(const mrtfd_params &p)
     F.xoff = 64;
     F.pitch = ((F.xoff + p.nx + 1 + 63) / 64) * 64;
     F.total = (long long)NQ * F.pitch * (p.ny + 2);
+    F.tstride = 64;
     if (p.layout == MRTFD_LAYOUT_PLANES) {
         F.qstride = (long long)F.pitch * (p.ny + 2);
         F.jstride = F.pitch;
+    } else if (p.layout == MRTFD_LAYOUT_TILES) {
+        F.qstride = 64;
+        F.jstride = (long long)NQ * F.pitch;
+        F.tstride = 64LL * NQ;
     } else {
         F.qstride = F.pitch;
         F.jstride = (long long)NQ * F.pitch;

@@ -47,21 +47,27 @@ struct Consts {
     float lw[NQ][4];  // cE, cW, cN, cS
 };
 
-// Device layout of one copy of f.  Rows j = -1 .. ny of `pitch` floats;
-// interior node (i, j) of population q at
-//   q * qstride + (j + 1) * jstride + xoff + i.
-// Two orders: population planes (qstride = (ny + 2) pitch, jstride = pitch)
-// or rows of interleaved populations (qstride = pitch, jstride = 16 pitch:
-// the 16 populations of a row lie next to each other).  xoff = 64 keeps every
-// interior row start 256-byte aligned; the ring around the interior is
-// padding that no kernel reads.
+// Device layout of one copy of f.  Rows j = -1 .. ny of 16 x `pitch` floats;
+// column i sits at c = xoff + i (xoff = 64 keeps every interior row start
+// 256-byte aligned; the ring around the interior is padding that no kernel
+// reads), and node (i, j) of population q at
+//   q * qstride + (j + 1) * jstride + (c / 64) * tstride + c % 64.
+// Three orders: population planes (qstride = (ny + 2) pitch, jstride =
+// pitch, tstride = 64), rows of interleaved populations (qstride = pitch,
+// jstride = 16 pitch, tstride = 64: the 16 populations of a row lie next to
+// each other), and tiles (qstride = 64, jstride = 16 pitch, tstride = 1024:
+// each 64-column piece of a row holds its 16 populations in 4 KiB).
 struct Field {
     int nx, ny;
     int pitch, xoff;
-    long long qstride, jstride;
+    long long qstride, jstride, tstride;
     long long total;  // floats in one copy
+    __host__ __device__ long long col(int i) const {
+        const int c = xoff + i;
+        return (long long)(c >> 6) * tstride + (c & 63);
+    }
     __host__ __device__ long long at(int q, int i, int j) const {
-        return (long long)q * qstride + (long long)(j + 1) * jstride + xoff + i;
+        return (long long)q * qstride + (long long)(j + 1) * jstride + col(i);
     }
 };
 

@@ -466,8 +466,8 @@ __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const
     int xh = lane < 32 ? x0 - 1 : x0 + 64;
     if (G.per_x && west && lane < 32) xh = nx - 1;
     if (G.per_x && east && e == 63 && lane >= 32) xh = 0;
-    const unsigned vo = 4u * (unsigned)(F.xoff + xl);
-    const unsigned vh = 4u * (unsigned)(F.xoff + xh);
+    const unsigned vo = 4u * (unsigned)F.col(xl);
+    const unsigned vh = 4u * (unsigned)F.col(xh);
     const unsigned qB = 4u * (unsigned)F.qstride, jB = 4u * (unsigned)F.jstride;
     const auto rin = buffer_of(fin, bytes);
     const auto rout = buffer_of(fout, bytes);
@@ -602,8 +602,8 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
         }
         return;
     }
-    const unsigned vo = 4u * (unsigned)(F.xoff + x);
-    const unsigned vh = 4u * (unsigned)(F.xoff + (lane < 32 ? x0 - 1 : x0 + 64));
+    const unsigned vo = 4u * (unsigned)F.col(x);
+    const unsigned vh = 4u * (unsigned)F.col(lane < 32 ? x0 - 1 : x0 + 64);
     const unsigned qB = 4u * (unsigned)F.qstride, jB = 4u * (unsigned)F.jstride;
     const auto rin = buffer_of(fin, bytes);
     const auto rout = buffer_of(fout, bytes);
@@ -700,8 +700,8 @@ __global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
         if (x < F.nx && y < F.ny) node_update(F, K, G, fin, fout, x, y, step_time(G, d_step, k));
         return;
     }
-    const unsigned vo = 4u * (unsigned)(F.xoff + x);
-    const unsigned vh = 4u * (unsigned)(F.xoff + (lane < 32 ? x0 - 1 : x0 + 64));
+    const unsigned vo = 4u * (unsigned)F.col(x);
+    const unsigned vh = 4u * (unsigned)F.col(lane < 32 ? x0 - 1 : x0 + 64);
     const unsigned qB = 4u * (unsigned)F.qstride, jB = 4u * (unsigned)F.jstride;
     const auto rin = buffer_of(fin, bytes);
     const auto rout = buffer_of(fout, bytes);

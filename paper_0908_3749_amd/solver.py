@@ -19,7 +19,8 @@ PRECISIONS = {"fp32": _abi.MRTFD_FP32, "bf16x3": _abi.MRTFD_BF16X3}
 COLLISIONS = {"mrt": _abi.MRTFD_COLLISION_MRT, "srt": _abi.MRTFD_COLLISION_SRT}
 
 
-LAYOUTS = {"rows": _abi.MRTFD_LAYOUT_ROWS, "planes": _abi.MRTFD_LAYOUT_PLANES}
+LAYOUTS = {"rows": _abi.MRTFD_LAYOUT_ROWS, "planes": _abi.MRTFD_LAYOUT_PLANES,
+           "tiles": _abi.MRTFD_LAYOUT_TILES}
 
 
 def make_params(nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto", rows=0,

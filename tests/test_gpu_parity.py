@@ -112,6 +112,25 @@ def test_one_step_grid_widths(gpu, nx, sides):
             assert np.array_equal(got, ref), (nx, ny, kern, seg, np.max(np.abs(got - ref)))
 
 
+@pytest.mark.parametrize("sides", ["reflect_extrapolate", "wall_split"])
+def test_layouts_agree(gpu, sides):
+    """The three device orders of f (population planes, interleaved rows,
+    64-column tiles) give the same bits for every kernel variant over 20
+    steps, and match the oracle."""
+    nx, ny = 150, 37
+    f0 = synth.random_populations(nx, ny, seed=17)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS[sides], None)
+    want, _ = run_oracle(prob, f0, 20)
+    outs = []
+    for layout in ("rows", "planes", "tiles"):
+        for kern, seg in VARIANTS:
+            outs.append(run_gpu(gpu, prob, f0, 20, kernel=kern, rows=seg, layout=layout)[0])
+        outs.append(run_gpu(gpu, prob, f0, 20, layout=layout, graph_steps=4)[0])
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert np.max(np.abs(outs[0] - want)) <= 20 * 2e-6 * np.max(np.abs(want))
+
+
 @pytest.mark.parametrize("shape", [(3, 3), (3, 70), (70, 3), (65, 4)])
 @pytest.mark.parametrize("sides", sorted(SIDE_SETS))
 def test_smallest_grids(gpu, shape, sides):
