@@ -1004,7 +1004,7 @@ int32_t mrtfd_kernel_info(mrtfd_ctx *c, int32_t *kernel, int32_t *rows, int32_t 
 namespace {
 
 struct BatchLayout {
-    size_t fA, fB, tubes, states, items, total;
+    size_t fA, fB, tubes, states, items, kcopy, total;
     long long ncols;
     size_t max_items;
 };
@@ -1063,7 +1063,8 @@ BatchLayout batch_layout(const mrtfd_batch_params *p, const int32_t *n)
     L.tubes = 2 * fbytes;
     L.states = L.tubes + align256((size_t)p->ntubes * sizeof(TubeInfo));
     L.items = L.states + align256((size_t)p->ntubes * 8 * sizeof(float));
-    L.total = L.items + align256(L.max_items * sizeof(TubeItem));
+    L.kcopy = L.items + align256(L.max_items * sizeof(TubeItem));
+    L.total = L.kcopy + align256(sizeof(Consts));
     return L;
 }
 
@@ -1086,6 +1087,7 @@ struct mrtfd_batch {
     TubeInfo *d_tubes = nullptr;
     float *d_states = nullptr;
     TubeItem *d_items = nullptr;
+    const Consts *d_k = nullptr;  // device copy of K, read by the tube kernel
     hipStream_t stream = nullptr, cap = nullptr;
     hipGraphExec_t graph = nullptr;
     int seg = 0, ks = 0, max_n = 0;
@@ -1141,7 +1143,7 @@ hipError_t enqueue_rounds(mrtfd_batch *b, hipStream_t s)
 {
     const int R = (int)b->round_items.size();
     for (int r = 0; r < R; ++r) {
-        hipError_t e = launch_tubes(b->TG, b->K, b->d_tubes, b->d_items, b->round_items[r], r,
+        hipError_t e = launch_tubes(b->TG, b->d_k, b->d_tubes, b->d_items, b->round_items[r], r,
                                     b->seg, b->ks, b->f[r & 1], b->f[(r + 1) & 1], s);
         if (e != hipSuccess) return e;
     }
@@ -1188,11 +1190,11 @@ int batch_autotune(mrtfd_batch *b)
                                           hipMemcpyHostToDevice, b->stream);
             // trial round 0: reads copy 0, writes copy 1 (overwritten by the real run)
             if (e == hipSuccess)
-                e = launch_tubes(b->TG, b->K, b->d_tubes, b->d_items, ri[0], 0, seg, ks, b->f[0], b->f[1],
+                e = launch_tubes(b->TG, b->d_k, b->d_tubes, b->d_items, ri[0], 0, seg, ks, b->f[0], b->f[1],
                                  b->stream);
             if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
             for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
-                e = launch_tubes(b->TG, b->K, b->d_tubes, b->d_items, ri[0], 0, seg, ks, b->f[0],
+                e = launch_tubes(b->TG, b->d_k, b->d_tubes, b->d_items, ri[0], 0, seg, ks, b->f[0],
                                  b->f[1], b->stream);
             if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1267,6 +1269,7 @@ int32_t mrtfd_batch_create(const mrtfd_batch_params *p, const int32_t *n, const 
         b->d_tubes = reinterpret_cast<TubeInfo *>(b->ws + L.tubes);
         b->d_states = reinterpret_cast<float *>(b->ws + L.states);
         b->d_items = reinterpret_cast<TubeItem *>(b->ws + L.items);
+        b->d_k = reinterpret_cast<const Consts *>(b->ws + L.kcopy);
         b->stream = static_cast<hipStream_t>(stream);
         b->TG.ncols = (int)L.ncols;
         b->TG.plane = (long long)TUBE_ROWS * L.ncols;
@@ -1322,6 +1325,9 @@ int32_t mrtfd_batch_create(const mrtfd_batch_params *p, const int32_t *n, const 
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_states, b->states.data(), b->states.size() * sizeof(float),
                            hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + L.kcopy, &b->K, sizeof(Consts), hipMemcpyHostToDevice,
+                           b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         delete b;

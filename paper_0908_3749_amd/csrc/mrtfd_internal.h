@@ -173,8 +173,9 @@ struct TubeGrid {
 };
 
 // One round: every listed item advances min(round_steps, steps - round *
-// round_steps) steps.  seg/round_steps must be one of the built pairs.
-hipError_t launch_tubes(const TubeGrid &T, const Consts &K, const TubeInfo *tubes,
+// round_steps) steps.  seg/round_steps must be one of the built pairs; K is a
+// device copy of the constants.
+hipError_t launch_tubes(const TubeGrid &T, const Consts *K, const TubeInfo *tubes,
                         const TubeItem *items, int nitems, int round, int seg, int round_steps,
                         const float *fin, float *fout, hipStream_t s);
 bool tubes_config_built(int seg, int round_steps);

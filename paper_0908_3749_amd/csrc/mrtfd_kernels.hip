@@ -792,7 +792,7 @@ __global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
 __host__ __device__ constexpr int yslot(int q) { return q < 8 ? q >> 1 : q - 4; }  // has_y(q)
 
 template <int S, int KS>
-__global__ __launch_bounds__(256) void k_tubes(TubeGrid TG, Consts K,
+__global__ __launch_bounds__(256) void k_tubes(TubeGrid TG, const Consts *__restrict__ Kd,
                                                const TubeInfo *__restrict__ tubes,
                                                const TubeItem *__restrict__ items, int round,
                                                const float *__restrict__ fin,
@@ -835,6 +835,12 @@ __global__ __launch_bounds__(256) void k_tubes(TubeGrid TG, Consts K,
         for (int q = 0; q < NQ; ++q)
             if (has_y(q)) yb[yslot(q)][y][c] = f[q];
         __syncthreads();
+        // The constants are read from memory in every step: held across the
+        // loop they exceed the scalar registers and spill to vector lanes.
+        unsigned long long ka = reinterpret_cast<unsigned long long>(Kd);
+        asm volatile("" : "+s"(ka));
+        typedef const __attribute__((address_space(4))) Consts ConstConsts;
+        const Consts &K = *(const Consts *)(ConstConsts *)ka;
         float dC[NQ], g[NQ];
         collide(K, f, dC);
         Unroll<NQ>::run([&](auto qc) {
@@ -1266,7 +1272,7 @@ bool tubes_config_built(int seg, int round_steps)
     return false;
 }
 
-hipError_t launch_tubes(const TubeGrid &T, const Consts &K, const TubeInfo *tubes,
+hipError_t launch_tubes(const TubeGrid &T, const Consts *K, const TubeInfo *tubes,
                         const TubeItem *items, int nitems, int round, int seg, int round_steps,
                         const float *fin, float *fout, hipStream_t s)
 {
