@@ -24,9 +24,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS and % of HBM roofline (FP32 vs mixed vs batched) at stated L1 error"
 HBM_PEAK_GBS = 8000.0
-# VALU ceiling of the node update: 256 CUs x 64 FP32 lanes x 2.4 GHz over
-# about 330 operations per node update (factored transform, no packed math)
-ALU_NODE_RATE = 256 * 64 * 2.4e9 / 330
+# VALU ceiling of the node update: the published FP32 vector rate, 157.3
+# TFLOP/s = 256 CUs x 128 FP32 lanes x 2 (fused multiply-add) x 2.4 GHz,
+# taken as 128 lane-operations per CU and clock (each add, multiply or fused
+# multiply-add one operation), over about 330 operations per node update
+# (factored transform)
+ALU_NODE_RATE = 256 * 128 * 2.4e9 / 330
 BYTES_PER_UPDATE = 128  # 16 FP32 populations read + 16 written
 KERNEL_SRC = os.path.join(ROOT, "paper_0908_3749_amd", "csrc", "mrtfd_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")

@@ -15,10 +15,15 @@ benchmark configurations name:
 
 * ``sod``            -- Sod tube, 400x4, dt = 2e-5 (Sect. V.A(a) states)
 * ``lax``            -- Lax tube (Sect. V.A(b) states and rates)
+* ``colella``, ``two_shock``, ``high_mach``
+                     -- the other tubes of Sect. V.A (c)-(e)
+* ``regular_reflection`` -- Mach-5 regular reflection, Sect. V.B(a)
+* ``paper_mach_reflection`` -- the Mach-1.5 reflection of Sect. V.B(b)
 * ``mach_reflection``-- Mach-3 shock on a 30 degree wedge, the Sect. V.B(b)
                         geometry (2048x512, or a crop at the same spacing)
 * ``shock_bubble``   -- Mach-1.22 shock on a light bubble, Sect. V.C
-                        (4096x1024, or a scaled run at the same spacing)
+                        (4096x1024, or a scaled run at the same spacing);
+                        ``heavy_bubble`` is the second case of Sect. V.C
 * ``couette``        -- Couette flow with a resting and a moving wall,
                         Sect. V.D (8192x2048, or a strip)
 * ``shear_wave``     -- periodic decaying shear wave (transport check)
@@ -150,7 +155,92 @@ def lax(nx=400, ny=4, length=1.6, dt=2e-5, t_end=0.2):
                              right=(0.5, 0.0, 0.5 * 1.142)))
 
 
-def mach_reflection(nx=2048, ny=512, dx=0.003, dt=1e-5, mach=3.0, nsteps=20000, x0_cells=None):
+def riemann_tube(name, left, right, dx, dt, t_end, s, x_left, x_right, ny=4):
+    """A 1D Riemann problem as an nx x ny grid, periodic in y, f = f^eq of the
+    initial states on the x ends (Sect. V.A).  left/right = (rho, u1, u2, T);
+    the interface sits x_left from the west end, the domain reaches x_right
+    beyond it (chosen so that no wave reaches an end by t_end)."""
+    nx = int(round((x_left + x_right) / dx))
+    x0 = int(round(x_left / dx)) * dx
+    x = (np.arange(nx) + 0.5) * dx
+    ic = {k: np.empty((ny, nx)) for k in ("rho", "ux", "uy", "T")}
+    for q, key in enumerate(("rho", "ux", "uy", "T")):
+        ic[key][:] = np.where(x < x0, left[q], right[q])[None, :]
+    sides = {"west": side("dirichlet", left), "east": side("dirichlet", right),
+             "south": side("periodic"), "north": side("periodic")}
+    nsteps = int(round(t_end / dt))
+    return Problem(name, nx, ny, dx, dx, dt, s, sides, ic, nsteps,
+                   meta=dict(x0=x0, left=(left[0], left[1], left[0] * left[3]),
+                             right=(right[0], right[1], right[0] * right[3])))
+
+
+def colella(dx=0.002, dt=2e-6, t_end=0.1, margins=(5.0, 3.0)):
+    """Colella's explosion wave, Sect. V.A(c): (1,0,0,1000) | (1,0,0,0.01),
+    case 1 spacing (dx = 0.002, dt = 2e-6), rates s7 = s8 = 5e4, s11 = s13 =
+    5e5, others 1e5, to t = 0.1.  With gamma = 2 the rarefaction head runs at
+    -44.7 and the shock at +25.4, so the tube reaches 5 to the west and 3 to
+    the east of the interface (4000 cells); shorter runs may pass smaller
+    margins."""
+    s = rates(dt, s7=5e4, s8=5e4, s11=5e5, s13=5e5)
+    return riemann_tube("colella", (1.0, 0.0, 0.0, 1000.0), (1.0, 0.0, 0.0, 0.01),
+                        dx, dt, t_end, s, margins[0], margins[1])
+
+
+def two_shock(dx=0.003, dt=1e-5, t_end=0.1, srt=False):
+    """Collision of two strong shocks, Sect. V.A(d): (5.99924, 19.5975, 0,
+    76.8254) | (5.99242, -6.19633, 0, 7.69222), dx = 0.003, dt = 1e-5, to
+    t = 0.1; rates s5 = s6 = 5e3, s7 = s8 = 3e4, others 1e5, or with srt the
+    single relaxation time tau = 1e-5 (every rate 1e5).  The shocks reach
+    -0.37 and +1.64 from the interface: the tube spans [-0.6, 2.0] (867
+    cells)."""
+    s = rates(dt) if srt else rates(dt, s5=5e3, s6=5e3, s7=3e4, s8=3e4)
+    return riemann_tube("two_shock_srt" if srt else "two_shock",
+                        (5.99924, 19.5975, 0.0, 76.8254), (5.99242, -6.19633, 0.0, 7.69222),
+                        dx, dt, t_end, s, 0.6, 2.0)
+
+
+def high_mach(dx=0.003, dt=1e-5, t_end=0.018):
+    """High-Mach shock tube, Sect. V.A(e): (5, 45, 0, 10) | (6, -20, 0, 5)
+    (Mach 10.1 and 6.3 at gamma = 2), dx = 0.003, dt = 1e-5, to t = 0.018;
+    rates s5 = s6 = 1.5e4, s10 = 5e4, others 1e5.  The shocks reach -0.11
+    and +0.48: the tube spans [-0.3, 0.7] (333 cells)."""
+    s = rates(dt, s5=1.5e4, s6=1.5e4, s10=5e4)
+    return riemann_tube("high_mach", (5.0, 45.0, 0.0, 10.0), (6.0, -20.0, 0.0, 5.0),
+                        dx, dt, t_end, s, 0.3, 0.7)
+
+
+def regular_reflection(nx=300, ny=100, dx=0.002, dt=1e-5, nsteps=30000):
+    """Regular reflection of a Mach-5 flow, 30 degrees, Sect. V.B(a): a 0.6 x
+    0.2 box (300 x 100 cells), inflow (1, 5, 0, 0.5) on the west side, the
+    post-shock state (2.27273, 4.3, -1.21244, 1.76) on the north side,
+    reflecting bottom, extrapolation on the east; the interior starts at the
+    inflow state.  Rates s5 = 1e4, s6 = 2e3, s7 = s8 = 1e4, others 1e5; the
+    paper shows t = 0.3 (30 000 steps)."""
+    inflow = (1.0, 5.0, 0.0, 0.5)
+    post = (2.27273, 4.3, -1.21244, 1.76)
+    ic = uniform_ic(nx, ny, *inflow)
+    s = rates(dt, s5=1e4, s6=2e3, s7=1e4, s8=1e4)
+    sides = {"west": side("dirichlet", inflow), "east": side("extrapolate"),
+             "south": side("reflect"), "north": side("dirichlet", post)}
+    return Problem("regular_reflection", nx, ny, dx, dx, dt, s, sides, ic, nsteps,
+                   meta=dict(inflow=inflow, post=post))
+
+
+def paper_mach_reflection(nx=600, ny=300, nsteps=25000):
+    """The Mach reflection of Sect. V.B(b): Mach-1.5 shock into (rho, p) =
+    (2, 1), i.e. (2, 0, 0, 0.5), post-shock (3.17647, 0.555556 cos30,
+    -0.555556 sin30, 0.839506), wedge from cell 150 of 600 x 300, dx = 0.003,
+    dt = 1e-5, rates s5 = 1e3, s6 = 5e2, s7 = s8 = 1e3, others 1e5; the paper
+    shows t = 0.25 (25 000 steps)."""
+    dt = 1e-5
+    return mach_reflection(nx=nx, ny=ny, dx=0.003, dt=dt, mach=1.5, nsteps=nsteps,
+                           x0_cells=150 * nx // 600, pre=(2.0, 1.0),
+                           s=rates(dt, s5=1e3, s6=5e2, s7=1e3, s8=1e3),
+                           name="paper_mach_reflection")
+
+
+def mach_reflection(nx=2048, ny=512, dx=0.003, dt=1e-5, mach=3.0, nsteps=20000, x0_cells=None,
+                    pre=(1.0, 1.0), s=None, name="mach_reflection"):
     """Planar shock of Mach number `mach` into gas at rest (rho, p) = (1, 1)
     meeting a wedge at 30 degrees: the Sect. V.B(b) geometry.  The shock line
     is y = tan60 (x - x0) - W t / sin30; post-shock gas lies above it and
@@ -161,10 +251,10 @@ def mach_reflection(nx=2048, ny=512, dx=0.003, dt=1e-5, mach=3.0, nsteps=20000, 
     V.B(a): s5 = 1e4, s6 = 2e3, s7 = s8 = 1e4, others 1e5."""
     if x0_cells is None:
         x0_cells = nx // 4
-    rho2, u2, p2, W = normal_shock(1.0, 1.0, mach)
+    rho2, u2, p2, W = normal_shock(pre[0], pre[1], mach)
     c30, s30, t30, t60 = math.cos(math.pi / 6), 0.5, math.tan(math.pi / 6), math.tan(math.pi / 3)
     post = (rho2, u2 * c30, -u2 * s30, p2 / rho2)
-    pre = (1.0, 0.0, 0.0, 1.0)
+    pre = (pre[0], 0.0, 0.0, pre[1] / pre[0])
     x0 = x0_cells * dx
     H = ny * dx
     x = (np.arange(nx) + 0.5) * dx
@@ -174,7 +264,8 @@ def mach_reflection(nx=2048, ny=512, dx=0.003, dt=1e-5, mach=3.0, nsteps=20000, 
     ic = {}
     for q, key in enumerate(("rho", "ux", "uy", "T")):
         ic[key] = np.where(behind, post[q], pre[q]).astype(np.float64)
-    s = rates(dt, s5=1e4, s6=2e3, s7=1e4, s8=1e4)
+    if s is None:
+        s = rates(dt, s5=1e4, s6=2e3, s7=1e4, s8=1e4)
     sides = {
         "west": side("dirichlet", post),
         "east": side("extrapolate"),
@@ -182,12 +273,12 @@ def mach_reflection(nx=2048, ny=512, dx=0.003, dt=1e-5, mach=3.0, nsteps=20000, 
         "north": split_side("dirichlet", post, "extrapolate", pre,
                             x0 + t30 * H, t30 * W / s30),
     }
-    return Problem("mach_reflection", nx, ny, dx, dx, dt, s, sides, ic, nsteps,
+    return Problem(name, nx, ny, dx, dx, dt, s, sides, ic, nsteps,
                    meta=dict(mach=mach, post=post, pre=pre, W=W, x0=x0))
 
 
 def shock_bubble(nx=4096, ny=1024, dx=0.003, dt=1e-5, nsteps=10000, seed=2024,
-                 bubble_density=0.138, mach=1.22, noise=0.01):
+                 bubble_density=0.138, mach=1.22, noise=0.01, s=None, name="shock_bubble"):
     """Mach-1.22 planar shock moving in -x onto a light circular bubble of
     radius 0.1*ny cells in ambient gas (rho, p) = (1, 1), pressure-matched
     (Sect. V.C, first case).  The centre is jittered by up to 0.05*ny cells
@@ -217,11 +308,19 @@ def shock_bubble(nx=4096, ny=1024, dx=0.003, dt=1e-5, nsteps=10000, seed=2024,
     xi = np.clip(rng.standard_normal((ny, nx)), -3.0, 3.0)
     rho = rho * (1.0 + noise * xi)
     ic = {"rho": rho, "ux": ux, "uy": np.zeros((ny, nx)), "T": p / rho}
-    s = rates(dt, s5=1e4, s6=1e4, s7=1e4, s8=1e4)
+    if s is None:
+        s = rates(dt, s5=1e4, s6=1e4, s7=1e4, s8=1e4)
     sides = {"west": side("extrapolate"), "east": side("dirichlet", post),
              "south": side("reflect"), "north": side("reflect")}
-    return Problem("shock_bubble", nx, ny, dx, dx, dt, s, sides, ic, nsteps,
+    return Problem(name, nx, ny, dx, dx, dt, s, sides, ic, nsteps,
                    meta=dict(centre=(cx, cy), radius=R, shock_x=xs, post=post))
+
+
+def heavy_bubble(nx=4096, ny=1024, dt=1e-5, nsteps=10000, seed=2024, noise=0.01):
+    """The second case of Sect. V.C: the same Mach-1.22 shock on a heavy
+    bubble (rho = 3.1538, p = 1); rates s5 = 1e3, others 1e5."""
+    return shock_bubble(nx=nx, ny=ny, dt=dt, nsteps=nsteps, seed=seed, bubble_density=3.1538,
+                        noise=noise, s=rates(dt, s5=1e3), name="heavy_bubble")
 
 
 def couette(nx=8192, ny=2048, dt=1e-5, U=0.1, nsteps=50000, seed=7, noise=1e-3,

@@ -101,3 +101,61 @@ def test_default_tube_batch_is_linearly_stable(S):
             worst = max(worst, t["steps"] * math.log(max(w, 1.0)))
     print("largest growth over a run", math.exp(worst))
     assert math.exp(worst) <= 4.0
+
+
+HIGH_MACH = dict(dx=0.003, s=dict(s5=1.5e4, s6=1.5e4, s10=5e4), grows=1.015)
+REGULAR = dict(dx=0.002, s=dict(s5=1e4, s6=2e3, s7=1e4, s8=1e4), grows=1.001)
+
+
+@pytest.mark.parametrize("state,theta,case", [
+    ((5.0, 45.0, 0.0, 10.0), (5, 21, 0, 3), HIGH_MACH),   # high-Mach tube, west state: a 1D mode grows
+    ((5.0, 45.0, 0.0, 10.0), (5, 21, 2, 7), HIGH_MACH),   # and an oblique one
+    ((1.0, 0.0, 0.0, 1.0), (3, 21, 1, 7), HIGH_MACH),     # Sod, west state: decays
+    ((1.0, 5.0, 0.0, 0.5), (0, 3, 13, 48), REGULAR),      # Mach-5 inflow: a transverse mode grows
+])
+def test_oracle_follows_the_screens_eigenvalue(S, state, theta, case):
+    """Seed the most unstable (or any) eigenvector of the screen's G at the
+    phases (2 pi kx / nx, 2 pi ky / ny) on a periodic grid around a uniform
+    state, step the FP64 oracle and read the mode's Fourier coefficient: it
+    is multiplied by the eigenvalue omega each step.  The screen (Jacobian of
+    Eq. 14 written out, closed-form Lax-Wendroff factor) and the oracle (the
+    whole nonlinear step) share no code."""
+    kx, nx, ky, ny = theta
+    tx, ty = 2 * math.pi * kx / nx, 2 * math.pi * ky / ny
+    dx, dt = case["dx"], 1e-5
+    s = synth.rates(dt, **case["s"])
+    G = S.amplification(state, s, dx, dx, dt, tx, ty)
+    w, V = np.linalg.eig(G)
+    k = int(np.argmax(np.abs(w)))
+    omega, v = w[k], V[:, k]
+    wl, U = np.linalg.eig(G.conj().T)  # left eigenvector: u^H G = omega u^H
+    u = U[:, int(np.argmin(np.abs(wl - np.conj(omega))))]
+    feq = core.feq_velocity(*state)
+    I = np.arange(nx)[None, :]
+    J = np.arange(ny)[:, None]
+    phase = np.exp(1j * (tx * I + ty * J))
+    eps = 1e-7 * np.max(np.abs(feq)) / np.max(np.abs(v))
+    f0 = feq[:, None, None] + eps * np.real(v[:, None, None] * phase[None])
+    prob = synth.generic(nx, ny, dx, dt, s, {k_: synth.side("periodic") for k_ in synth.SIDES},
+                         synth.uniform_ic(nx, ny, *state))
+    g = core.Grid(prob, nthreads=1)
+    g.set_f(f0)
+
+    def coef():
+        d = g.get_f() - feq[:, None, None]
+        return np.einsum("qyx,yx->q", d, np.conj(phase)) / (nx * ny) * 2
+
+    c0 = coef()
+    np.testing.assert_allclose(c0, eps * v, rtol=0, atol=1e-7 * eps * np.max(np.abs(v)))
+    n = 40
+    g.run(n)
+    ratio = np.vdot(u, coef()) / np.vdot(u, c0)
+    # G is far from normal at the hot state (entries up to 1e5), so its
+    # eigenvalues move by ~1e-5 per step under entry changes of 1e-7; a
+    # dropped term or a sign moves them by orders more
+    assert abs(ratio / omega ** n - 1.0) < 1e-3, (ratio, omega ** n)
+    growth = abs(ratio) ** (1.0 / n)
+    if state[1] > 0:
+        assert growth > case["grows"]   # the oracle's own run grows: unstable configuration
+    else:
+        assert growth < 1.0
