@@ -45,3 +45,16 @@ def paper_states():
             lab, *vals = line.split(",")
             out[lab] = [float(v) for v in vals]
     return out
+
+
+def paper_tube_errors():
+    """{label: dict(dx, dt, rho, p, ux, T)} with E in percent."""
+    out = {}
+    with open(os.path.join(HERE, "paper_tube_errors.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            lab, dx, dt, r, p, u, T = line.split(",")
+            out[lab] = dict(dx=float(dx), dt=float(dt), rho=float(r), p=float(p), ux=float(u), T=float(T))
+    return out

@@ -283,3 +283,34 @@ def test_high_mach_tube_is_unstable_under_these_readings():
     assert np.min(g.macro()["T"]) < 0.0
     g.run(prob.nsteps - 30)
     assert not np.all(np.isfinite(g.get_f()))
+
+
+@pytest.mark.slow
+def test_sod_reproduces_paper_errors():
+    """Sect. V.A(a), case 1 (dx = 0.002, dt = 2e-6, t = 0.18): the paper
+    prints E = 0.234 / 0.182 / 3.32 / 0.327 % for rho, p, u, T but not its
+    tube length.  E of u counts only the disturbed region (u = 0 elsewhere),
+    so it does not depend on the length: here 3.18 %.  The other three are
+    divided by sums over the whole tube; fitting the undisturbed length on
+    each side from E(rho) alone (the tube comes out ~7.8 long) predicts
+    E(p) and E(T) within 3 % of the printed ones (0.180 % and 0.330 %)."""
+    want = parse.paper_tube_errors()["sod_case1"]
+    L, R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    prob = synth.sod(nx=int(round(1.0 / want["dx"])), dt=want["dt"], nsteps=int(round(0.18 / want["dt"])))
+    g = core.Grid(prob, nthreads=8)
+    g.init_problem()
+    g.run(prob.nsteps)
+    mac = g.macro()
+    r, u, p, T = riemann.profile(L, R, prob.x_centres(), prob.meta["x0"], g.t, 2.0)
+    J = prob.ny // 2
+    ex = {"rho": r, "p": p, "ux": u, "T": T}
+    far = {"rho": 1.0 + 0.125, "p": 1.0 + 0.1, "T": 1.0 + 0.8}
+    num = {k: float(np.sum(np.abs(mac[k][J] - ex[k]))) for k in ex}
+    den = {k: float(np.sum(np.abs(ex[k]))) for k in ex}
+    assert abs(100 * num["ux"] / den["ux"] / want["ux"] - 1.0) < 0.1
+    # extra undisturbed cells per side that give the printed E(rho)
+    a = (100 * num["rho"] / want["rho"] - den["rho"]) / far["rho"]
+    assert a > 0
+    for k in ("p", "T"):
+        e = 100 * num[k] / (den[k] + a * far[k])
+        assert abs(e / want[k] - 1.0) < 0.03, (k, e, want[k])
