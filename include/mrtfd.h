@@ -28,7 +28,7 @@
  *    released by mrtfd_destroy().
  *  - Every GPU operation is enqueued on the stream given at creation, in
  *    call order.  Only calls returning host data (mrtfd_sums) synchronise
- *    that stream.
+ *    that stream.  Memory is cleared by kernels, never by memset nodes.
  *  - Macroscopic fields are FP32, row-major [ny][nx] over the interior
  *    nodes, node (i, j) at x = (i + 1/2) dx, y = (j + 1/2) dy.
  *  - Populations are numbered as in Eq. (4): 0-3 = cyc(+-1,0) in the order

@@ -840,7 +840,7 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
+    if (e == hipSuccess) e = launch_zero(c->ws, L.total, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_mfma, &c->h_mfma, sizeof(MfmaOperands), hipMemcpyHostToDevice,
                            c->stream);
@@ -869,12 +869,12 @@ int32_t mrtfd_init_macro(mrtfd_ctx *c, const float *rho, const float *ux, const 
 {
     if (!c) return MRTFD_ERR_ARG;
     if (!rho || !ux || !uy || !T) return set_err(c, MRTFD_ERR_ARG, "init_macro: NULL field");
-    HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+    HIPCHK(c, launch_zero(c->d_flag, sizeof(int), c->stream));
     c->cur = 0;
     HIPCHK(c, launch_init(c->F, c->K, c->f[0], rho, ux, uy, T, c->d_flag, c->stream));
     HIPCHK(c, launch_counter_set(c->d_step, 0, c->stream));
     if (c->p.flux_budget)
-        HIPCHK(c, hipMemsetAsync(c->flux, 0, c->L.outflow - c->L.flux, c->stream));
+        HIPCHK(c, launch_zero(c->flux, c->L.outflow - c->L.flux, c->stream));
     c->step = 0;
     c->initialised = true;
     return MRTFD_OK;
@@ -886,7 +886,7 @@ int32_t mrtfd_set_f(mrtfd_ctx *c, const float *src)
     if (!src) return set_err(c, MRTFD_ERR_ARG, "set_f: NULL array");
     HIPCHK(c, launch_unpack(c->F, src, c->f[c->cur], c->stream));
     if (c->p.flux_budget)
-        HIPCHK(c, hipMemsetAsync(c->flux, 0, c->L.outflow - c->L.flux, c->stream));
+        HIPCHK(c, launch_zero(c->flux, c->L.outflow - c->L.flux, c->stream));
     c->initialised = true;
     return MRTFD_OK;
 }
@@ -1318,7 +1318,7 @@ int32_t mrtfd_batch_create(const mrtfd_batch_params *p, const int32_t *n, const 
         delete b;
         return MRTFD_ERR_ARG;
     }
-    hipError_t e = hipMemsetAsync(b->ws, 0, L.total, b->stream);
+    hipError_t e = launch_zero(b->ws, L.total, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_tubes, b->info.data(), b->info.size() * sizeof(TubeInfo),
                            hipMemcpyHostToDevice, b->stream);
