@@ -117,3 +117,29 @@ def test_batch_tubes_match_oracle_and_exact(gpu):
             assert abs(a - b) <= prob.dx, (k, side, a, b)
             assert abs(b - xs) <= 3 * prob.dx, (k, side, b, xs)
     B.close()
+
+
+def test_full_batch_sampled_tubes_bitwise(gpu):
+    """The 512-tube batch that bench.py times (seed 12345, autotuned work
+    items, all rounds replayed from one graph): sampled tubes -- the one that
+    runs longest (269 331 steps), the shortest run, the widest and narrowest
+    tubes, and two drawn at random -- end bit for bit where single-grid runs
+    of the same tubes end."""
+    batch = synth.tube_batch(star_fn=star_fn)
+    tubes = batch["tubes"]
+    steps = np.array([t["steps"] for t in tubes])
+    ns = np.array([t["n"] for t in tubes])
+    rng = np.random.default_rng(5)
+    sample = sorted({int(np.argmax(steps)), int(np.argmin(steps)), int(np.argmax(ns)), int(np.argmin(ns)),
+                     *rng.choice(len(tubes), size=2, replace=False).tolist()})
+    B = gpu.TubeBatch.from_description(batch, use_graph=True)
+    B.init()
+    B.run()
+    seg, ks, rounds = B.info()
+    print(f"full batch: seg {seg}, steps/round {ks}, rounds {rounds}; sample {sample}", flush=True)
+    for k in sample:
+        got = B.get_f_numpy(k)
+        want = single_grid(gpu, batch, k)
+        print(f"tube {k}: n {ns[k]}, steps {steps[k]}", flush=True)
+        assert np.array_equal(got, want), k
+    B.close()
