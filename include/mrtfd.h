@@ -29,6 +29,10 @@
  *  - Every GPU operation is enqueued on the stream given at creation, in
  *    call order.  Only calls returning host data (mrtfd_sums) synchronise
  *    that stream.  Memory is cleared by kernels, never by memset nodes.
+ *  - Debugging: with MRTFD_POISON_PADDING=1 in the environment when a
+ *    context is created, its two copies of f start filled with NaN instead
+ *    of zeros.  Only interior nodes are ever written or read as state, so
+ *    results are unchanged; a read outside the interior would show as NaN.
  *  - Macroscopic fields are FP32, row-major [ny][nx] over the interior
  *    nodes, node (i, j) at x = (i + 1/2) dx, y = (j + 1/2) dy.
  *  - Populations are numbered as in Eq. (4): 0-3 = cyc(+-1,0) in the order

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -562,6 +563,15 @@ void drop_graphs(mrtfd_ctx *c)
         }
 }
 
+// Debugging aid: with MRTFD_POISON_PADDING=1 in the environment at create,
+// the copies of f start as NaN instead of zero, so that any read of a node
+// outside the interior (the ring and the padding columns) shows in results.
+bool poison_padding()
+{
+    const char *v = std::getenv("MRTFD_POISON_PADDING");
+    return v && v[0] == '1' && v[1] == 0;
+}
+
 // Graphs, private streams and events, then the context itself.
 void release(mrtfd_ctx *c)
 {
@@ -841,6 +851,8 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
     }
     if (e == hipSuccess) e = launch_zero(c->ws, L.total, c->stream);
+    if (e == hipSuccess && poison_padding())  // both copies of f: a quiet NaN everywhere
+        e = launch_fill(c->ws + L.fA, L.partials - L.fA, 0x7FC00000u, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_mfma, &c->h_mfma, sizeof(MfmaOperands), hipMemcpyHostToDevice,
                            c->stream);

@@ -138,8 +138,9 @@ hipError_t launch_face_flux(const Field &F, const Consts &K, const Ghosts &G, co
                             hipStream_t s);
 hipError_t launch_flux_totals(int nx, int ny, const double *slots, double *out, hipStream_t s);
 
-// Zero `bytes` (a multiple of 4) at p (16-byte aligned) with a kernel, not a
-// memset node.
+// Fill `bytes` (a multiple of 4) at p (16-byte aligned) with a 32-bit pattern,
+// or with zeros, by a kernel, not a memset node.
+hipError_t launch_fill(void *p, size_t bytes, unsigned pattern, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_counter_add(long long *d_step, long long n, hipStream_t s);
 hipError_t launch_counter_set(long long *d_step, long long n, hipStream_t s);

@@ -938,15 +938,16 @@ __global__ __launch_bounds__(256) void k_init(Field F, Consts K, float *__restri
     for (int q = 0; q < NQ; ++q) f[F.at(q, i, j)] = fe[q];
 }
 
-// Zero n 16-byte words, then `tail` 4-byte words after them (grid-stride).
-// Used instead of memset nodes, so that a caller may capture the calls that
-// clear memory into a graph.
-__global__ __launch_bounds__(256) void k_zero(uint4 *p, size_t n, unsigned *tail, int ntail)
+// Fill n 16-byte words, then `tail` 4-byte words after them, with the 32-bit
+// pattern v (grid-stride).  Used instead of memset nodes, so that a caller may
+// capture the calls that clear memory into a graph.
+__global__ __launch_bounds__(256) void k_fill(uint4 *p, size_t n, unsigned *tail, int ntail,
+                                              unsigned v)
 {
     const size_t stride = (size_t)gridDim.x * 256;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
-        p[i] = make_uint4(0u, 0u, 0u, 0u);
-    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0u;
+        p[i] = make_uint4(v, v, v, v);
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = v;
 }
 
 __global__ void k_counter(long long *d_step, long long n, int set)
@@ -1205,17 +1206,19 @@ hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, co
     return hipGetLastError();
 }
 
-hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+hipError_t launch_fill(void *p, size_t bytes, unsigned pattern, hipStream_t s)
 {
     if (bytes == 0) return hipSuccess;
     if ((bytes & 3) || (reinterpret_cast<uintptr_t>(p) & 15)) return hipErrorInvalidValue;
     const size_t n = bytes / 16;
     const int ntail = (int)((bytes % 16) / 4);
     const unsigned blocks = (unsigned)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, static_cast<uint4 *>(p), n,
-                       reinterpret_cast<unsigned *>(static_cast<char *>(p) + n * 16), ntail);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, static_cast<uint4 *>(p), n,
+                       reinterpret_cast<unsigned *>(static_cast<char *>(p) + n * 16), ntail, pattern);
     return hipGetLastError();
 }
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) { return launch_fill(p, bytes, 0u, s); }
 
 hipError_t launch_counter_add(long long *d_step, long long n, hipStream_t s)
 {

@@ -693,3 +693,24 @@ def test_paper_2d_workloads(gpu, name):
             assert (a is None) == (b is None), (i, a, b)
             if a is not None:
                 assert abs(a - b) <= prob.dy, (i, a, b)
+
+
+@pytest.mark.parametrize("sides", sorted(SIDE_SETS))
+def test_padding_is_never_read(gpu, sides, monkeypatch):
+    """Both copies of f start as NaN outside the interior
+    (MRTFD_POISON_PADDING=1): after 20 steps on a ragged grid (the last tile
+    column is mostly padding) every kernel variant, the split-BF16x3 one
+    included, gives the same bits as with zeroed padding, all finite -- no
+    kernel reads a node outside the interior as state."""
+    nx, ny = 141, 43
+    ic = synth.smooth_macro(nx, ny, seed=11, du=0.2, dr=0.1)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS[sides], ic)
+    for kernel, rows, prec in [(k, r, "fp32") for k, r in VARIANTS] + [("auto", 0, "bf16x3")]:
+        kw = dict(kernel=kernel, rows=rows, precision=prec)
+        monkeypatch.delenv("MRTFD_POISON_PADDING", raising=False)
+        clean, _, _ = run_gpu(gpu, prob, None, 20, **kw)
+        monkeypatch.setenv("MRTFD_POISON_PADDING", "1")
+        poisoned, _, info = run_gpu(gpu, prob, None, 20, **kw)
+        monkeypatch.delenv("MRTFD_POISON_PADDING")
+        assert np.all(np.isfinite(poisoned)), (info, prec)
+        assert np.array_equal(poisoned, clean), (info, prec)
