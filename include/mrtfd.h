@@ -100,7 +100,8 @@ extern "C" {
 #define MRTFD_KERNEL_ROWS 2   /* each wave: `rows` rows of 64 columns loaded
                                  once, west/east neighbours by lane shifts     */
 #define MRTFD_KERNEL_MFMA 3   /* reported only: the matrix-core kernel that
-                                 MRTFD_BF16X3 always uses                      */
+                                 MRTFD_BF16X3 always uses (its store kind and
+                                 tile order are autotuned)                     */
 
 /* One side of the grid.  The rule is kind_lo at ghost nodes whose
  * along-side coordinate (x for the south/north sides, y for west/east) is
@@ -222,9 +223,10 @@ int32_t mrtfd_set_step(mrtfd_ctx *ctx, int64_t step);
  * rows = 0, the choice is made by timing the candidates (rows per wave,
  * store kind, tile order, and the simple kernel) on the first steps of the
  * first mrtfd_step call long enough for a fair trial (up to about 300 steps;
- * results are bit-identical whichever runs) and is cached per grid size for
- * later contexts; before that the rows kernel with one row per wave and
- * plain stores runs. */
+ * results are bit-identical whichever runs) and is cached per grid size and
+ * precision for later contexts; before that the rows kernel with one row per
+ * wave and plain stores runs.  With MRTFD_BF16X3 the same trial picks the
+ * matrix-core kernel's store kind and tile order. */
 int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_t *streaming,
                           int32_t *tile_order);
 

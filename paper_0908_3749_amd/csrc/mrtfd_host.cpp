@@ -450,14 +450,15 @@ Layout layout(const mrtfd_params &p)
 // ----------------------------------------------------------- autotune cache
 
 struct TuneKey {
-    int nx, ny, layout, kernel, rows;
+    int nx, ny, layout, kernel, rows, precision;
     bool operator<(const TuneKey &o) const
     {
         if (nx != o.nx) return nx < o.nx;
         if (ny != o.ny) return ny < o.ny;
         if (layout != o.layout) return layout < o.layout;
         if (kernel != o.kernel) return kernel < o.kernel;
-        return rows < o.rows;
+        if (rows != o.rows) return rows < o.rows;
+        return precision < o.precision;
     }
 };
 std::mutex g_tune_mu;
@@ -526,7 +527,8 @@ hipError_t launch_step(mrtfd_ctx *c, const float *fin, float *fout, int k, hipSt
     if (c->kernel == MRTFD_KERNEL_ROWS)
         return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg & 15, (c->seg >> 4) & 1,
                                 (c->seg >> 5) & 1, c->d_step, k, s);
-    return launch_step_mfma(c->F, c->K, c->G, c->d_mfma, fin, fout, c->d_step, k, s);
+    return launch_step_mfma(c->F, c->K, c->G, c->d_mfma, fin, fout, (c->seg >> 4) & 1,
+                            (c->seg >> 5) & 1, c->d_step, k, s);
 }
 
 // Enqueue n steps starting from copy `start`, then advance the device clock.
@@ -629,7 +631,7 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
 {
     *taken = 0;
     if (c->tuned) return MRTFD_OK;
-    const TuneKey key{c->p.nx, c->p.ny, c->p.layout, c->p.kernel, c->p.rows};
+    const TuneKey key{c->p.nx, c->p.ny, c->p.layout, c->p.kernel, c->p.rows, c->p.precision};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
@@ -643,7 +645,13 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
     std::vector<std::pair<int, int>> cands;
     // second: rows per wave, (bit 4) streaming stores, (bit 5) tile order by
     // column bands
-    if (c->p.kernel == MRTFD_KERNEL_SIMPLE) {
+    if (c->p.precision == MRTFD_BF16X3) {
+        const bool bands = ((c->p.nx + 63) / 64) % 8 == 0;
+        for (int o = 0; o <= (bands ? 1 : 0); ++o) {
+            cands.push_back({MRTFD_KERNEL_MFMA, 1 | (o << 5)});
+            cands.push_back({MRTFD_KERNEL_MFMA, 1 | 16 | (o << 5)});
+        }
+    } else if (c->p.kernel == MRTFD_KERNEL_SIMPLE) {
         cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     } else {
         const bool bands = ((c->p.nx + 63) / 64) % 8 == 0;
@@ -839,10 +847,10 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         c->seg = p->rows;
         c->tuned = true;
     }
-    if (p->precision == MRTFD_BF16X3) {
+    if (p->precision == MRTFD_BF16X3) {  // stores and tile order autotuned
         c->kernel = MRTFD_KERNEL_MFMA;
         c->seg = 1;
-        c->tuned = true;
+        c->tuned = false;
     }
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess && p->flux_budget) {

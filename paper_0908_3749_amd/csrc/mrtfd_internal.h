@@ -103,9 +103,11 @@ struct Ghosts {
     const Ghosts *gd;
 };
 
+// Split-BF16x3 step; stream_stores and order as for launch_step_rows.
 hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
                             const MfmaOperands *mo, const float *fin, float *fout,
-                            const long long *d_step, int k, hipStream_t s);
+                            int stream_stores, int order, const long long *d_step, int k,
+                            hipStream_t s);
 
 // Launchers (mrtfd_kernels.hip).  All enqueue on `s` and return the HIP
 // status of the launch.

@@ -651,15 +651,26 @@ __device__ __forceinline__ unsigned short bf16_bits(float x)
 }
 __device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
-// x = hi + lo with both parts BF16 (|x - hi - lo| <= 2^-18 |x|).
+// x = hi + lo with both parts BF16 (|x - hi - lo| <= 2^-18 |x|).  The
+// conversions round to nearest even, as bf16_bits does (the hardware
+// conversion instruction on this target).
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef int i32x2v __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ void split4(const float (&x)[4], bf16x4 &hi, bf16x4 &lo)
 {
+    i32x2v h, l;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const unsigned short h = bf16_bits(x[c]);
-        hi[c] = (short)h;
-        lo[c] = (short)bf16_bits(x[c] - bf16_float(h));
+    for (int p = 0; p < 2; ++p) {  // one packed conversion per pair
+        const f32x2v v = {x[2 * p], x[2 * p + 1]};
+        const bf16x2v hv = __builtin_convertvector(v, bf16x2v);
+        const bf16x2v lv = __builtin_convertvector(v - __builtin_convertvector(hv, f32x2v), bf16x2v);
+        h[p] = __builtin_bit_cast(int, hv);
+        l[p] = __builtin_bit_cast(int, lv);
     }
+    hi = __builtin_bit_cast(bf16x4, h);
+    lo = __builtin_bit_cast(bf16x4, l);
 }
 
 // A . B with A, B split into BF16 parts: A_hi B_hi + A_hi B_lo + A_lo B_hi,
@@ -673,28 +684,53 @@ __device__ __forceinline__ f32x4 mfma3(bf16x4 ahi, bf16x4 alo, bf16x4 bhi, bf16x
     return c;
 }
 
+// Order this wave's LDS stores before its later LDS loads by other lanes (a
+// wave runs in lockstep; this keeps the compiler from moving accesses across
+// and waits for the stores).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Step kernel with the two 16x16 transforms of the collision on the matrix
 // cores (split-BF16, three products, FP32 accumulation); the equilibria, the
 // relaxation and the Lax-Wendroff update stay FP32.  Block = 64 columns x 4
 // rows, wave = one row (lane = node, west/east neighbours by DPP as in the
-// row kernel).  Per 16-node group the wave stages its populations in LDS
-// ([node][population]) so that lane l reads populations 4 (l/16) .. +3 of node
+// row kernel).  The wave stages its populations in LDS ([node][population])
+// so that, per 16-node group, lane l reads populations 4 (l/16) .. +3 of node
 // l % 16 -- the B-operand layout; the product M F comes back with lane l
 // holding moments 4 (l/16) .. +3 of node l % 16, which is again the B layout
-// for the back-map.  Blocks touching a side of the grid use the FP32 node path.
+// for the back-map.  The conserved moments and the equilibria are computed
+// once per node in FP32 and staged the same way.  Blocks touching a side of
+// the grid use the FP32 node path.
+template <int AUX>
 __global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
                                                    const MfmaOperands *__restrict__ mo,
                                                    const float *__restrict__ fin,
                                                    float *__restrict__ fout, unsigned bytes,
                                                    int ncol, int nrb, int nblocks,
-                                                   const long long *__restrict__ d_step, int k)
+                                                   const long long *__restrict__ d_step, int k,
+                                                   int order)
 {
     __shared__ float stage[4][64][NQ + 4];
+    __shared__ float eqst[4][64][13];  // equilibria of moments 5..16 per node
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // tiles to XCDs in bands of tile rows (order 0) or tile columns (order 1),
+    // as in the row kernel
     int b = blockIdx.x;
     if ((nblocks & 7) == 0) b = (b & 7) * (nblocks >> 3) + (b >> 3);
-    const int col = b % ncol, rb = b / ncol;
+    int col, rb;
+    if (order == 1) {
+        const int cw = ncol >> 3;
+        col = (b / (nrb * cw)) * cw + b % cw;
+        rb = (b / cw) % nrb;
+    } else {
+        col = b % ncol;
+        rb = b / ncol;
+    }
     const int x0 = col * 64, yb = rb * 4, x = x0 + lane, y = yb + wv;
     if (col == 0 || x0 + 64 >= F.nx || yb == 0 || yb + 4 >= F.ny) {  // uniform over the block
         if (x < F.nx && y < F.ny) node_update(F, K, G, fin, fout, x, y, step_time(G, d_step, k));
@@ -724,10 +760,29 @@ __global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
         il[c] = (short)mo->inv_lo[lane][c];
     }
     const int grp = lane >> 4, nd = lane & 15;
+    float sv[4];  // rates of the moments this lane holds in the product layout
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sv[c] = mo->s[4 * grp + c];
+    // Conserved moments and equilibria once per node, in FP32 as the scalar
+    // path computes them, staged beside the populations; the LDS regions are
+    // private to the wave.
+    float rho, jx, jy, e;
+    conserved(K, cur, rho, jx, jy, e);
+    const Eq eq = equilibria(rho, jx, jy, e);
     float (*st)[NQ + 4] = stage[wv];
+    float (*qs)[13] = eqst[wv];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) st[lane][q] = cur[q];
-    __syncthreads();
+    {
+        const float ev[12] = {eq.e5, eq.e6, eq.e7, eq.e8, eq.e9, eq.e10,
+                              eq.e11, 0.f, eq.e13, eq.e14, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 12; ++k) qs[lane][k] = ev[k];
+    }
+    wave_sync();
+    // Lane l reads populations 4 (l/16) .. +3 of node 16 nb + l%16 (the B
+    // operand) and gets back the same entries of dt C (the product layout),
+    // so it overwrites exactly what it read: no other lane touches them.
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
         const int node = nb * 16 + nd;
@@ -737,29 +792,17 @@ __global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
         bf16x4 fh, fl;
         split4(fv, fh, fl);
         const f32x4 m = mfma3(mh, ml, fh, fl);  // moments 4 grp .. +3 of `node`
-        // conserved moments of the node live in lanes 0..15 (grp 0)
-        const float rho = __shfl(m[0], nd), jx = __shfl(m[1], nd), jy = __shfl(m[2], nd),
-                    e = __shfl(m[3], nd);
-        const Eq q = equilibria(rho, jx, jy, e);
-        const float eqv[NQ] = {rho, jx, jy, e, q.e5, q.e6, q.e7, q.e8,
-                               q.e9, q.e10, q.e11, 0.f, q.e13, q.e14, 0.f, 0.f};
         float d[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int mk = 4 * grp + c;
-            float eqk = eqv[0];
-#pragma unroll
-            for (int t = 1; t < NQ; ++t) eqk = mk == t ? eqv[t] : eqk;
-            d[c] = mo->s[mk] * (m[c] - eqk);
-        }
+        for (int c = 0; c < 4; ++c)  // conserved moments (grp 0) have rate 0
+            d[c] = sv[c] * (m[c] - qs[node][max(4 * grp + c - 4, 0)]);
         bf16x4 dh, dl;
         split4(d, dh, dl);
         const f32x4 dc = mfma3(ih, il, dh, dl);  // dt C, populations 4 grp .. +3 of `node`
-        __syncthreads();
 #pragma unroll
         for (int c = 0; c < 4; ++c) st[node][4 * grp + c] = dc[c];
-        __syncthreads();
     }
+    wave_sync();
     float dC[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) dC[q] = st[lane][q];
@@ -770,7 +813,7 @@ __global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
             fE = shl1(cur[q], hc[q]);
             fW = shr1(cur[q], hc[q]);
         }
-        bstore(rout, lw_update<q>(K, cur[q], dC[q], fE, fW, nxt[q], prv[q]), vo, row(q, y));
+        bstore<AUX>(rout, lw_update<q>(K, cur[q], dC[q], fE, fW, nxt[q], prv[q]), vo, row(q, y));
     });
 }
 
@@ -1341,15 +1384,21 @@ hipError_t launch_tube_pack(const TubeGrid &T, const TubeInfo *tubes, int tube, 
 
 hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
                             const MfmaOperands *mo, const float *fin, float *fout,
-                            const long long *d_step, int k, hipStream_t s)
+                            int stream_stores, int order, const long long *d_step, int k,
+                            hipStream_t s)
 {
     const int ncol = (F.nx + 63) / 64;
     const int nrb = (F.ny + 3) / 4;
     const int nb = ncol * nrb;
     const long long total = 4LL * F.total;
     if (total >= (1LL << 32)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step_mfma, dim3(nb), dim3(256), 0, s, F, K, G, mo, fin, fout,
-                       (unsigned)total, ncol, nrb, nb, d_step, k);
+    const int ord = (order == 1 && (ncol & 7) == 0) ? 1 : 0;
+    if (stream_stores)
+        hipLaunchKernelGGL(k_step_mfma<2>, dim3(nb), dim3(256), 0, s, F, K, G, mo, fin, fout,
+                           (unsigned)total, ncol, nrb, nb, d_step, k, ord);
+    else
+        hipLaunchKernelGGL(k_step_mfma<0>, dim3(nb), dim3(256), 0, s, F, K, G, mo, fin, fout,
+                           (unsigned)total, ncol, nrb, nb, d_step, k, ord);
     return hipGetLastError();
 }
 

@@ -285,6 +285,43 @@ def test_autotune_trial_steps_are_ordinary_steps(gpu, nx, ny):
     h.close()
 
 
+def test_bf16x3_autotune_variants_agree(gpu):
+    """The split-BF16x3 step autotunes its store kind and tile order on steps
+    of the run (a grid of 8 tile columns, so both orders run): the tuned run
+    equals a run that never tunes (each call too short) bit for bit, and a
+    second context takes the cached choice, which an FP32 context of the
+    same size does not share."""
+    nx, ny = 504, 36
+    f0 = synth.random_populations(nx, ny, seed=8)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["reflect_extrapolate"], None)
+    g = gpu.from_problem(prob, precision="bf16x3", graph_steps=0)
+    g.set_f(f0)
+    for _ in range(200):
+        g.step(1)                  # each call too short to tune
+    assert g.kernel_details() == ("mfma", 1, False)
+    ref = g.get_f_numpy()
+    g.close()
+    t = gpu.from_problem(prob, precision="bf16x3", graph_steps=16)
+    t.set_f(f0)
+    t.step(200)                    # tunes on its first 4 x 34 steps
+    tuned = t.kernel_details()
+    got = t.get_f_numpy()
+    t.close()
+    print("bf16x3 tuned variant", tuned)
+    assert tuned[0] == "mfma"
+    assert np.array_equal(got, ref)
+    h = gpu.from_problem(prob, precision="bf16x3")
+    h.set_f(f0)
+    h.step(1)
+    assert h.kernel_details() == tuned
+    h.close()
+    k = gpu.from_problem(prob)
+    k.set_f(f0)
+    k.step(1)
+    assert k.kernel_details()[0] == "rows"
+    k.close()
+
+
 @pytest.mark.parametrize("sides", ["wall_split", "reflect_extrapolate", "periodic"])
 def test_outflow_budget(gpu, sides):
     """Outflow budget (flux_budget): the GPU's FP64 outflow through each side
