@@ -169,11 +169,12 @@ def test_shear_wave_decays_with_corrected_viscosity():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("case,dx,ny,dt,E_paper", [(1, 0.004, 32, 1e-4, 0.0702), (2, 0.002, 64, 5e-5, 0.0386)])
+@pytest.mark.parametrize("case,dx,ny,dt,E_paper", [(1, 0.004, 32, 1e-4, 0.0702), (2, 0.002, 64, 5e-5, 0.0386),
+                                                   (3, 0.001, 128, 2.5e-5, 0.0206)])
 def test_couette_reproduces_paper_errors(case, dx, ny, dt, E_paper):
     """Sect. V.D: plates at -+D/2 moving at -+U = 0.1, rho = T = 1, periodic
-    in x; the paper reports E(u) = 7.02 % and 3.86 % for its first two cases
-    (dx = 0.004 and 0.002, s dt = 1 and 0.5, t = 57.5).  Here the rates are
+    in x; the paper reports E(u) = 7.02 %, 3.86 % and 2.06 % for its three
+    cases (dx = 0.004, 0.002 and 0.001, s dt = 1, 0.5 and 0.25, t = 57.5).  Here the rates are
     divided and dt and t multiplied by ten, which keeps s dt, the lattice
     Courant number and nu t / D^2.  Walls sit on the ghost rows, so
     D = (ny + 1) dy.  Measured against the series with nu = T / s, the
