@@ -215,11 +215,17 @@ def test_uniform_flow_stays_bitwise_uniform(gpu):
     np.testing.assert_allclose(mac["ux"], 0.4, rtol=1e-5)
 
 
-def test_periodic_conservation_fp64_sums(gpu):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_periodic_conservation_fp64_sums(gpu, precision):
+    """On a periodic grid the FP64 totals of rho, j, e drift by FP32
+    round-off only -- in the split-BF16x3 mode too, whose back-map is not
+    exactly blind to the conserved moments (observed: 1e-8 .. 1e-7 of the
+    totals after 5000 steps in both modes, so no projection of the collision
+    increment is needed)."""
     nx, ny = 200, 120
     ic = synth.smooth_macro(nx, ny, seed=9, du=0.3, dr=0.2)
     prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"], ic)
-    g = gpu.from_problem(prob)
+    g = gpu.from_problem(prob, precision=precision)
     g.init_problem(prob)
     a = g.sums()
     g.step(1000)
