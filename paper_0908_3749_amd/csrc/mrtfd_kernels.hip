@@ -643,17 +643,9 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Round-to-nearest-even FP32 -> BF16 bits, and back.
-__device__ __forceinline__ unsigned short bf16_bits(float x)
-{
-    const unsigned u = __float_as_uint(x);
-    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-__device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
-
 // x = hi + lo with both parts BF16 (|x - hi - lo| <= 2^-18 |x|).  The
-// conversions round to nearest even, as bf16_bits does (the hardware
-// conversion instruction on this target).
+// conversions round to nearest even (the packed hardware conversion of this
+// target), as the host does for the constant operands.
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 typedef float f32x2v __attribute__((ext_vector_type(2)));
 typedef int i32x2v __attribute__((ext_vector_type(2)));
