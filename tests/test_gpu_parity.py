@@ -260,6 +260,32 @@ def test_graph_replay_equals_direct_launches(gpu):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("budget", [0, 1])
+def test_every_graph_replay_matches_direct_launches(gpu, budget):
+    """Each call replays the captured step graphs (8 steps per graph, the
+    outflow budget's side-stream fork and join captured with them when on);
+    between calls the program does its own eager work (FP64 sums, reading f,
+    synchronisation).  After every call the state, the sums and the outflow
+    totals equal those of a context that launches the same steps directly."""
+    nx, ny = 150, 37
+    f0 = synth.random_populations(nx, ny, seed=12)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["wall_split"], None)
+    kw = dict(kernel="rows", rows=1, flux_budget=budget)
+    g = gpu.from_problem(prob, graph_steps=8, **kw)
+    d = gpu.from_problem(prob, graph_steps=0, **kw)
+    g.set_f(f0)
+    d.set_f(f0)
+    for n in (8, 16, 3, 8, 24, 8):
+        g.step(n)
+        d.step(n)
+        assert np.array_equal(g.get_f_numpy(), d.get_f_numpy()), n
+        assert np.array_equal(np.array(g.sums()), np.array(d.sums())), n
+        if budget:
+            assert np.array_equal(np.array(g.outflow()), np.array(d.outflow())), n
+    g.close()
+    d.close()
+
+
 @pytest.mark.parametrize("nx,ny", [(141, 43), (500, 40)])
 def test_autotune_trial_steps_are_ordinary_steps(gpu, nx, ny):
     """The autotuner times the candidate kernels on steps of the run itself:
