@@ -54,15 +54,17 @@ def single_grid(P, batch, k):
                                  dict(seg_cols=48, round_steps=8, use_graph=True),
                                  dict(seg_cols=32, round_steps=16, use_graph=True)])
 def test_batch_equals_single_grid_bitwise(gpu, small_batch, cfg):
+    """With graph replay the batch runs twice (the second run replays the
+    same captured graph after eager reads of every tube), each run checked."""
     B = gpu.TubeBatch.from_description(small_batch, **cfg)
-    B.init()
-    B.run()
-    seg, ks, rounds = B.info()
-    print(f"batch cfg {cfg}: seg {seg}, steps/round {ks}, rounds {rounds}")
-    for k in range(len(small_batch["tubes"])):
-        got = B.get_f_numpy(k)
-        want = single_grid(gpu, small_batch, k)
-        assert np.array_equal(got, want), k
+    want = [single_grid(gpu, small_batch, k) for k in range(len(small_batch["tubes"]))]
+    for rep in range(2 if cfg.get("use_graph") else 1):
+        B.init()
+        B.run()
+        seg, ks, rounds = B.info()
+        print(f"batch cfg {cfg}, run {rep}: seg {seg}, steps/round {ks}, rounds {rounds}")
+        for k in range(len(small_batch["tubes"])):
+            assert np.array_equal(B.get_f_numpy(k), want[k]), (rep, k)
     B.close()
 
 
