@@ -636,9 +636,16 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
         if (it != g_tune.end()) {
+            const bool changed = c->kernel != it->second.first || c->seg != it->second.second;
             c->kernel = it->second.first;
             c->seg = it->second.second;
             c->tuned = true;
+            // graphs captured before (a call too short to tune) hold the old
+            // variant; they are rebuilt on the next replay
+            if (changed) {
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+                drop_graphs(c);
+            }
             return MRTFD_OK;
         }
     }
@@ -704,6 +711,12 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
     (void)hipEventDestroy(e1);
     c->kernel = pick.first;
     c->seg = pick.second;
+    // graphs captured by earlier, shorter calls hold the default variant:
+    // wait until none is in flight (an error may have cut the trials short
+    // of their own synchronisation), then drop them; they are rebuilt on the
+    // next replay
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
     if (rc == MRTFD_OK) {
         c->tuned = true;
         std::lock_guard<std::mutex> lk(g_tune_mu);

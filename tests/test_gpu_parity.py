@@ -317,6 +317,26 @@ def test_autotune_trial_steps_are_ordinary_steps(gpu, nx, ny):
     h.close()
 
 
+def test_graphs_captured_before_tuning_are_rebuilt(gpu):
+    """A first call long enough to capture a step graph but too short to
+    tune replays the default variant; the next, longer call tunes, and its
+    replays (graphs rebuilt for the chosen variant) continue the same bits
+    as a run that never uses graphs."""
+    nx, ny = 331, 29
+    f0 = synth.random_populations(nx, ny, seed=13)
+    prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["dirichlet"], None)
+    ref, _, _ = run_gpu(gpu, prob, f0, 16 + 600, kernel="simple")
+    g = gpu.from_problem(prob, graph_steps=16)
+    g.set_f(f0)
+    g.step(16)                     # one graph captured and replayed, no tuning
+    assert g.kernel_details() == ("rows", 1, False)
+    g.step(600)                    # tunes, then replays rebuilt graphs
+    got = g.get_f_numpy()
+    print("tuned", g.kernel_variant())
+    g.close()
+    assert np.array_equal(got, ref)
+
+
 def test_bf16x3_autotune_variants_agree(gpu):
     """The split-BF16x3 step autotunes its store kind and tile order on steps
     of the run (a grid of 8 tile columns, so both orders run): the tuned run
