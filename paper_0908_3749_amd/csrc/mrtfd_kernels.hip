@@ -698,7 +698,8 @@ __device__ __forceinline__ void wave_sync()
 // once per node in FP32 and staged the same way.  Blocks touching a side of
 // the grid use the FP32 node path.
 template <int AUX>
-__global__ __launch_bounds__(256) void k_step_mfma(Field F, Consts K, Ghosts G,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_step_mfma(Field F, Consts K, Ghosts G,
                                                    const MfmaOperands *__restrict__ mo,
                                                    const float *__restrict__ fin,
                                                    float *__restrict__ fout, unsigned bytes,
