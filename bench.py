@@ -192,9 +192,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's run length)")
-    ap.add_argument("--warmup", type=int, default=256,
-                    help="untimed steps; they hold the kernel autotune (up to 5 x 34 steps) "
-                         "and the graph capture")
+    ap.add_argument("--warmup", type=int, default=512,
+                    help="untimed steps; they hold the kernel autotune (two passes over up to 9 "
+                         "candidates, 360 steps at 2048x512) and the graph capture")
     ap.add_argument("--config", default="mach3", choices=sorted(workloads()))
     ap.add_argument("--kernel", default="auto", choices=["auto", "simple", "rows"])
     ap.add_argument("--rows", type=int, default=0)
@@ -275,7 +275,9 @@ def main():
             out = g.outflow()
             resid = sums - sums0 + out.sum(axis=0)
             scale = abs(sums0) + abs(sums) + abs(out).sum(axis=0)
-            budget = {"outflow_total": [float(v) for v in out.sum(axis=0)],
+            kern, rows, nt, order = g.kernel_variant()
+            budget = {"kernel": kern, "rows": rows, "streaming_stores": nt, "tile_order": order,
+                      "outflow_total": [float(v) for v in out.sum(axis=0)],
                       "residual_over_scale": [float(f"{v:.3e}") for v in resid / scale]}
         return g, e0.elapsed_time(e1), budget
 
@@ -292,8 +294,9 @@ def main():
         gb.close()
         budget = {"value": round(cells * nb_steps / (ms_b * 1e-3) / 1e6, 1), "unit": "MLUPS",
                   "ms_per_step": round(ms_b / nb_steps, 6), "steps": nb_steps, **summary,
-                  "note": "same workload with the FP64 outflow budget on (its kernel on a second "
-                          "stream beside each step); residual = sums(end) - sums(start) + outflow, "
+                  "note": "same workload with the FP64 outflow budget on (in leading blocks of "
+                          "the step kernel's grid at one row per wave, else its own kernel on a "
+                          "second stream beside each step); residual = sums(end) - sums(start) + outflow, "
                           "over warm-up and timed steps"}
     # One step = one launch of the step kernel (plus one single-thread clock
     # kernel per captured graph), so the kernel's average launch duration over

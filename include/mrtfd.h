@@ -135,8 +135,10 @@ typedef struct mrtfd_params {
     int32_t layout;     /* MRTFD_LAYOUT_ROWS or _PLANES (device order of f)   */
     int32_t flux_budget;/* 1: every step also adds the FP64 outflow through
                            each side to a running total (mrtfd_outflow):
-                           a small kernel on a library-owned stream that
-                           runs beside the step kernel. 0: off           */
+                           in extra blocks of the step kernel's own grid
+                           (rows kernel, one row per wave), else a small
+                           kernel on a library-owned stream that runs
+                           beside the step kernel. 0: off                */
 } mrtfd_params;
 
 typedef struct mrtfd_ctx mrtfd_ctx;
@@ -222,10 +224,11 @@ int32_t mrtfd_set_step(mrtfd_ctx *ctx, int64_t step);
  * may be NULL).  With MRTFD_KERNEL_AUTO, or _ROWS and
  * rows = 0, the choice is made by timing the candidates (rows per wave,
  * store kind, tile order, and the simple kernel) on the first steps of the
- * first mrtfd_step call long enough for a fair trial (up to about 300 steps;
- * results are bit-identical whichever runs) and is cached per grid size and
- * precision for later contexts; before that the rows kernel with one row per
- * wave and plain stores runs.  With MRTFD_BF16X3 the same trial picks the
+ * first mrtfd_step call long enough for a fair trial (two passes over the
+ * candidates, up to about 600 steps; results are bit-identical whichever
+ * runs) and is cached per grid size, precision and flux_budget for later
+ * contexts; before that the rows kernel with one row per wave and plain
+ * stores runs.  With MRTFD_BF16X3 the same trial picks the
  * matrix-core kernel's store kind and tile order. */
 int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_t *streaming,
                           int32_t *tile_order);

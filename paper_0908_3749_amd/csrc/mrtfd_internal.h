@@ -92,6 +92,8 @@ struct GhostSide {
     double h;                        // node spacing along the side
 };
 
+struct FluxCoef;
+
 struct Ghosts {
     GhostSide side[4];  // west, east, south, north
     double dt;
@@ -101,6 +103,7 @@ struct Ghosts {
     // the kernel arguments to itself
     const Consts *kd;
     const Ghosts *gd;
+    const FluxCoef *fd;  // device copy of the outflow-budget coefficients
 };
 
 // Split-BF16x3 step; stream_stores and order as for launch_step_rows.
@@ -120,10 +123,13 @@ hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, 
                               float *fout, const long long *d_step, int k, hipStream_t s);
 // rows per wave (1 or 2); stream_stores: non-temporal stores; order: tiles
 // to XCDs in bands of tile rows (0) or of tile columns (1, when the number of
-// tile columns divides by 8; else 0).
+// tile columns divides by 8; else 0).  slots != nullptr: the launch also
+// adds the step's outflow budget (as launch_face_flux) in leading blocks of
+// its own grid (constants from the device copies G.kd, G.gd, G.fd).
 hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
                             float *fout, int rows, int stream_stores, int order,
-                            const long long *d_step, int k, hipStream_t s);
+                            const long long *d_step, int k, hipStream_t s,
+                            double *slots = nullptr);
 // Outflow budget (FP64).  cx[q] = {(dt/dx) v_qx / 2, (dt/dx) v_qx^2 dt / (2 dx)}
 // and likewise cy along y: the face value of the A.1b difference between a
 // node at the lower coordinate (lo) and the next one (hi) is

@@ -559,12 +559,32 @@ __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const
     }
 }
 
-template <int R, int AUX>
+__device__ __forceinline__ void face_flux_node(const Field &F, const Consts &K, const Ghosts &G,
+                                               const FluxCoef &C, const float *__restrict__ fin,
+                                               double *__restrict__ slots,
+                                               const long long *__restrict__ d_step, int k, int t);
+
+// BUD: the first fblocks blocks (a multiple of 8, so that the XCD of every
+// step block is unchanged) add the step's outflow budget from the input copy,
+// one thread per side node, with the constants read from the device copies;
+// dispatched first, they run beside the step blocks, which only write the
+// other copy.
+template <int R, int AUX, bool BUD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 1 ? 5 : 4, 8)))
 void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
                  float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
-                 const long long *__restrict__ d_step, int k, int order)
+                 const long long *__restrict__ d_step, int k, int order,
+                 double *__restrict__ slots, int fblocks)
 {
+    int b = blockIdx.x;
+    if (BUD) {
+        if (b < fblocks) {
+            face_flux_node(F, *G.kd, *G.gd, *G.fd, fin, slots, d_step, k,
+                           b * 256 + (int)threadIdx.x);
+            return;
+        }
+        b -= fblocks;
+    }
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // Consecutive blocks land on different XCDs (round robin over 8); give
@@ -572,7 +592,6 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
     // share halo rows and columns, share an L2: a band of whole tile rows
     // (order 0), or of ncol/8 tile columns (order 1, taken when the tile
     // columns and blocks divide by 8).
-    int b = blockIdx.x;
     if ((nblocks & 7) == 0) b = (b & 7) * (nblocks >> 3) + (b >> 3);
     int col, rb;
     if (order == 1) {
@@ -1079,13 +1098,12 @@ __global__ __launch_bounds__(256) void k_sums_final(const double *__restrict__ p
 // the FP32 populations and added to the thread's own slot, so the totals do
 // not depend on scheduling.  Periodic faces are counted on both sides with
 // equal and opposite values.
-__global__ __launch_bounds__(256) void k_face_flux(Field F, Consts K, Ghosts G, FluxCoef C,
-                                                   const float *__restrict__ fin,
-                                                   double *__restrict__ slots,
-                                                   const long long *__restrict__ d_step, int k)
+__device__ __forceinline__ void face_flux_node(const Field &F, const Consts &K, const Ghosts &G,
+                                               const FluxCoef &C, const float *__restrict__ fin,
+                                               double *__restrict__ slots,
+                                               const long long *__restrict__ d_step, int k, int t)
 {
     const int nx = F.nx, ny = F.ny;
-    const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= 2 * (nx + ny)) return;
     int sd, a;
     if (t < ny) {
@@ -1139,6 +1157,14 @@ __global__ __launch_bounds__(256) void k_face_flux(Field F, Consts K, Ghosts G, 
     double *sl = slots + 4 * (long long)t;
 #pragma unroll
     for (int m = 0; m < 4; ++m) sl[m] += acc[m];
+}
+
+__global__ __launch_bounds__(256) void k_face_flux(Field F, Consts K, Ghosts G, FluxCoef C,
+                                                   const float *__restrict__ fin,
+                                                   double *__restrict__ slots,
+                                                   const long long *__restrict__ d_step, int k)
+{
+    face_flux_node(F, K, G, C, fin, slots, d_step, k, blockIdx.x * 256 + threadIdx.x);
 }
 
 // Per-side totals of the slots, one block per side, fixed summation order.
@@ -1214,7 +1240,7 @@ hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, 
 
 hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
                             float *fout, int rows, int stream_stores, int order,
-                            const long long *d_step, int k, hipStream_t s)
+                            const long long *d_step, int k, hipStream_t s, double *slots)
 {
     const int ncol = (F.nx + 63) / 64;
     const int nrg = (F.ny + rows - 1) / rows;
@@ -1223,20 +1249,29 @@ hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, co
     const long long total = 4LL * F.total;
     if (total >= (1LL << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
     const unsigned bytes = (unsigned)total;
+    // budget blocks: one thread per side node, rounded up to a multiple of 8
+    const int fb = slots ? (int)((blocks_for(2LL * (F.nx + F.ny), 256) + 7) / 8 * 8) : 0;
+    const dim3 grid(nb + fb);
     switch (rows) {
     // store cache policy: 0 default, 2 non-temporal (streaming)
+#define MRTFD_ROWS_B(Rr, Aa)                                                                       \
+    if (slots)                                                                                     \
+        hipLaunchKernelGGL((k_step_rows<Rr, Aa, true>), grid, dim3(256), 0, s, F, K, G, fin, fout, \
+                           bytes, ncol, nrg, nb, d_step, k, ord, slots, fb);                       \
+    else                                                                                           \
+        hipLaunchKernelGGL((k_step_rows<Rr, Aa, false>), grid, dim3(256), 0, s, F, K, G, fin,      \
+                           fout, bytes, ncol, nrg, nb, d_step, k, ord, slots, 0)
 #define MRTFD_ROWS(Rr)                                                                             \
     case Rr:                                                                                       \
         if (stream_stores)                                                                         \
-            hipLaunchKernelGGL((k_step_rows<Rr, 2>), dim3(nb), dim3(256), 0, s, F, K, G, fin,      \
-                               fout, bytes, ncol, nrg, nb, d_step, k, ord);                        \
+            MRTFD_ROWS_B(Rr, 2);                                                                   \
         else                                                                                       \
-            hipLaunchKernelGGL((k_step_rows<Rr, 0>), dim3(nb), dim3(256), 0, s, F, K, G, fin,      \
-                               fout, bytes, ncol, nrg, nb, d_step, k, ord);                        \
+            MRTFD_ROWS_B(Rr, 0);                                                                   \
         break;
         MRTFD_ROWS(1)
         MRTFD_ROWS(2)
 #undef MRTFD_ROWS
+#undef MRTFD_ROWS_B
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
