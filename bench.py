@@ -215,7 +215,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)}); "
+        print(f"bench.py: the library runs on one GPU only (asked for {max(args.gpus, world)}); "
               "the multi-GPU slab decomposition is a design, not an implementation.", file=sys.stderr)
         return 2
 

@@ -56,7 +56,7 @@ extern "C" {
 #define MRTFD_ERR_UNSTABLE (-3)    /* dt*s > 1 or Courant number > 1        */
 #define MRTFD_ERR_NONFINITE (-4)   /* NaN/Inf met in the state              */
 #define MRTFD_ERR_STATE (-5)       /* call out of order (e.g. step before init) */
-#define MRTFD_ERR_UNSUPPORTED (-6) /* a mode this build does not provide    */
+#define MRTFD_ERR_UNSUPPORTED (-6) /* a mode the library does not provide  */
 
 /* ---- boundary rules (Sect. V) ------------------------------------------ */
 #define MRTFD_BC_PERIODIC 0    /* copy of the opposite interior edge (V.A)      */
