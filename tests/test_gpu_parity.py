@@ -517,6 +517,17 @@ def test_error_paths(gpu):
     assert e.value.status == _abi.MRTFD_ERR_ARG
     g.init_problem(prob)
     g.sums()
+    # zero steps change nothing; a negative count is rejected and leaves the
+    # context usable
+    f0 = g.get_f_numpy()
+    clock = g.time()
+    g.step(0)
+    assert np.array_equal(g.get_f_numpy(), f0) and g.time() == clock
+    with pytest.raises(MrtfdError) as e:
+        g.step(-1)
+    assert e.value.status == _abi.MRTFD_ERR_ARG
+    g.step(2)
+    assert g.time()[0] == clock[0] + 2
     f = g.get_f_numpy()
     f[2, 5, 5] = np.nan
     g.set_f(f)
