@@ -183,7 +183,11 @@ class Grid:
         self.f = np.zeros((self.ny + 2, self.nx + 2, NQ))
         self.work = np.zeros_like(self.f)
         self.step_index = 0
-        self.nthreads = int(nthreads)
+        # ORACLE_MAX_THREADS caps the thread count where parallel test
+        # workers share the host's cores; the results do not depend on it
+        # (one static parallel loop over nodes per step)
+        cap = os.environ.get("ORACLE_MAX_THREADS")
+        self.nthreads = max(1, min(int(nthreads), int(cap))) if cap else int(nthreads)
         # outflow of (rho, j1, j2, e) node sums through west, east, south,
         # north since the last init_macro / set_f
         self.outflow = np.zeros((4, 4))
