@@ -188,6 +188,61 @@ def traffic_entry(workload, kernel, seg, streaming, tile_order, per_launch_cells
     return None
 
 
+def comparison():
+    """The metric's three forms side by side in one run: Couette 8192x2048
+    in plain FP32 and with the split-BF16x3 matrix-core transforms (1000
+    timed steps each after 512 warm-up steps that hold the autotune and the
+    graph capture), and the 512-tube batch (one whole run after a warm-up
+    run).  Their accuracy against the oracle: bench.py --config couette
+    [--precision bf16x3] and --config tubes."""
+    import torch
+
+    import synth
+    from paper_0908_3749_amd import MRT2D, TubeBatch
+
+    out = {}
+    prob = synth.couette()
+    cells = prob.nx * prob.ny
+    for prec in ("fp32", "bf16x3"):
+        g = MRT2D.from_problem(prob, graph_steps=64, precision=prec)
+        g.init_problem(prob)
+        g.step(512)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        n = 1000
+        e0.record(g.stream)
+        g.step(n)
+        e1.record(g.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        kernel, seg, streaming, order = g.kernel_variant()
+        g.close()
+        gbs = BYTES_PER_UPDATE * cells / (ms * 1e-3) / 1e9
+        out[prec] = {"workload": "couette_8192x2048", "value": round(cells / (ms * 1e-3) / 1e6, 1),
+                     "unit": "MLUPS", "ms_per_step": round(ms, 6),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "kernel": f"{kernel}/{seg}{'/nt' if streaming else ''}{'/colbands' if order else ''}"}
+    batch = synth.tube_batch(star_fn=tube_star)
+    work = sum(4 * t["n"] * t["steps"] for t in batch["tubes"])
+    B = TubeBatch.from_description(batch, use_graph=True)
+    B.init()
+    B.run()  # autotune, capture
+    B.init()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(B.stream)
+    B.run()
+    e1.record(B.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    out["batched"] = {"workload": "tube_batch_512", "value": round(work / (ms * 1e-3) / 1e6, 1),
+                      "unit": "MLUPS", "wall_ms": round(ms, 2),
+                      "alu_frac": round(work / (ms * 1e-3) / ALU_NODE_RATE, 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,7 +258,8 @@ def main():
     ap.add_argument("--layout", default="rows", choices=["rows", "planes", "tiles"])
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="oracle steps on the crop (default: the workload's)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle leg and the FP32 / mixed / batched comparison (profiling runs)")
     ap.add_argument("--flux-budget", type=int, default=1, choices=[0, 1],
                     help="1: after the headline run, time the same workload with the FP64 "
                          "outflow budget on (up to 2000 steps) and report it beside")
@@ -367,6 +423,8 @@ def main():
         }
         if not np.all(np.isfinite(got["rho"])):
             out["accuracy"]["note"] = "non-finite values in the GPU crop run"
+        if args.config == "mach3" and args.precision == "fp32":
+            out["comparison"] = comparison()
     print(json.dumps(out), flush=True)
     return 0
 
