@@ -717,7 +717,7 @@ __device__ __forceinline__ void wave_sync()
 // once per node in FP32 and staged the same way.  Blocks touching a side of
 // the grid use the FP32 node path.
 template <int AUX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
 void k_step_mfma(Field F, Consts K, Ghosts G,
                                                    const MfmaOperands *__restrict__ mo,
                                                    const float *__restrict__ fin,
@@ -726,7 +726,8 @@ void k_step_mfma(Field F, Consts K, Ghosts G,
                                                    const long long *__restrict__ d_step, int k,
                                                    int order)
 {
-    __shared__ float stage[4][64][NQ + 4];
+    // staging rows of 18 floats: five blocks' LDS (31 KiB each) fit a CU
+    __shared__ float stage[4][64][NQ + 2];
     __shared__ float eqst[4][64][13];  // equilibria of moments 5..16 per node
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -781,7 +782,7 @@ void k_step_mfma(Field F, Consts K, Ghosts G,
     float rho, jx, jy, e;
     conserved(K, cur, rho, jx, jy, e);
     const Eq eq = equilibria(rho, jx, jy, e);
-    float (*st)[NQ + 4] = stage[wv];
+    float (*st)[NQ + 2] = stage[wv];
     float (*qs)[13] = eqst[wv];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) st[lane][q] = cur[q];
