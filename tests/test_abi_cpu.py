@@ -118,9 +118,12 @@ def test_validation_rejects_bad_params(abi):
     assert st == abi.MRTFD_ERR_ARG and "4 GiB" in msg, msg
     p.kernel = abi.MRTFD_KERNEL_SIMPLE
     assert check_params(p)[0] == abi.MRTFD_OK
-    p.nx, p.ny = 8192, 8000  # 4.2e9 B per copy: just below
+    p.nx, p.ny = 8192, 8063  # 64 x 8320 x 8065 B per copy: just below 2^32
     p.kernel = abi.MRTFD_KERNEL_AUTO
     assert check_params(p)[0] == abi.MRTFD_OK
+    p.ny = 8064  # one more row crosses it
+    st, msg = check_params(p)
+    assert st == abi.MRTFD_ERR_ARG and "4 GiB" in msg, msg
 
 
 def test_create_rejects_bad_workspace_without_gpu(abi):

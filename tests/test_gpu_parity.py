@@ -148,11 +148,12 @@ def test_smallest_grids(gpu, shape, sides):
 
 
 def test_largest_grid_sampled(gpu):
-    """Largest grid whose copy of f stays below 4 GiB (8192 x 7990 nodes,
-    32-bit buffer offsets up to 4.26e9 B), periodic, one step of the row
-    kernel with one and two rows per wave: sampled nodes -- random ones, the
-    last grid row and column, the corners -- agree with the oracle's node
-    update computed from the same FP32 state."""
+    """A grid near the 4 GiB limit of one copy of f (8192 x 7990 nodes,
+    32-bit buffer offsets up to 4.26e9 B), periodic on all four sides, one
+    step of the row kernel with one and two rows per wave: sampled nodes --
+    random ones, the last grid row and column, the corners -- agree with the
+    oracle's node update computed from the same FP32 state.  The limit itself
+    with wall sides: test_largest_grid_for_32bit_offsets."""
     nx, ny = 8192, 7990
     ic = synth.smooth_macro(nx, ny, seed=31, du=0.2, dr=0.1)
     prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"], ic)
@@ -615,6 +616,39 @@ def test_full_size_steps_match_oracle(gpu, config):
     bound = 4 * n * U32 * scale
     print(f"full size {config}, {n} steps, variant {variant}: max err {err:.3e}, bound {bound:.3e}")
     assert err <= bound
+
+
+def test_largest_grid_for_32bit_offsets(gpu):
+    """Maximum size: 8192 x 8063 is the largest grid of that width whose copy
+    of f (rows of 16 x 8320 floats and the padding ring) stays below 4 GiB,
+    the range of the row kernels' 32-bit buffer offsets; one more row is
+    refused at create.  The Couette set-up (periodic in x, walls south and
+    north, so the last rows build wall ghosts at the largest offsets), two
+    steps with one and with two rows per wave against the whole-grid FP64
+    oracle, node by node within 4 n u S (S over a window of columns: the
+    flow is uniform in x up to the 1e-3 velocity noise)."""
+    nx, ny, n = 8192, 8063, 2
+    prob = synth.couette(nx=nx, ny=ny)
+    o = core.Grid(prob, nthreads=THREADS)
+    o.init_problem()
+    f0 = o.get_f().astype(np.float32)
+    o.set_f(f0.astype(np.float64))
+    scale = transform_scale(prob, f0[:, :, :256].astype(np.float64))
+    o.run(n)
+    want = o.get_f()
+    del o
+    bound = 4 * n * U32 * scale
+    for rows in (1, 2):
+        g = gpu.from_problem(prob, kernel="rows", rows=rows, graph_steps=0)
+        g.set_f(f0)
+        g.step(n)
+        got = g.get_f_numpy()
+        variant = g.kernel_variant()
+        g.close()
+        err = max(float(np.max(np.abs(got[q] - want[q]))) for q in range(16))
+        del got
+        print(f"largest grid {nx}x{ny}, variant {variant}: max err {err:.3e}, bound {bound:.3e}")
+        assert err <= bound
 
 
 def _shock_x(prob, rho, row, lo, hi):
