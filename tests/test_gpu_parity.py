@@ -618,6 +618,40 @@ def test_full_size_steps_match_oracle(gpu, config):
     assert err <= bound
 
 
+def test_full_size_bf16x3_couette_matches_oracle(gpu):
+    """The mixed-precision workload at its full size (Couette 8192 x 2048,
+    split-BF16x3 transforms on the matrix cores) in bench.py's launch
+    configuration (graph of 64 steps, store kind and tile order autotuned on
+    the run's first steps): after the autotune's two passes it agrees with
+    the whole-grid FP64 oracle node by node within n (16 2^-18 + 4 u) S per
+    step bound of the split products on top of the FP32 one, S =
+    transform_scale."""
+    prob = synth.couette()
+    cells = prob.nx * prob.ny
+    reps = 2 * int(max(4.0, min(16.0, 1e7 / cells)))
+    ncand = 4 if ((prob.nx + 63) // 64) % 8 == 0 else 2  # store kind x tile order
+    n = 2 * ncand * (reps + 2) + 4
+    o = core.Grid(prob, nthreads=THREADS)
+    o.init_problem()
+    f0 = o.get_f().astype(np.float32)
+    o.set_f(f0.astype(np.float64))
+    scale = transform_scale(prob, o.get_f())
+    o.run(n)
+    want = o.get_f()
+    del o
+    g = gpu.from_problem(prob, graph_steps=64, precision="bf16x3")
+    g.set_f(f0)
+    g.step(n)
+    got = g.get_f_numpy()
+    variant = g.kernel_variant()
+    g.close()
+    assert variant[0] == "mfma"
+    err = max(float(np.max(np.abs(got[q] - want[q]))) for q in range(16))
+    bound = n * (16 * 2.0 ** -18 + 4 * U32) * scale
+    print(f"full size couette bf16x3, {n} steps, variant {variant}: max err {err:.3e}, bound {bound:.3e}")
+    assert err <= bound
+
+
 def test_largest_grid_for_32bit_offsets(gpu):
     """Maximum size: 8192 x 8063 is the largest grid of that width whose copy
     of f (rows of 16 x 8320 floats and the padding ring) stays below 4 GiB,
