@@ -139,6 +139,22 @@ typedef struct mrtfd_params {
                            (rows kernel, one row per wave), else a small
                            kernel on a library-owned stream that runs
                            beside the step kernel. 0: off                */
+    double ref_rho, ref_T;
+                        /* reference state at rest, both > 0, or both 0 for
+                           none.  With a reference the copies of f hold
+                           g = f - f_ref, f_ref = f^eq(ref_rho, 0, 0, ref_T)
+                           (Eq. 14 mapped back by M^-1; the reference values
+                           are rounded to FP32 first): the difference
+                           scheme (Eq. A.1b) is linear and f_ref uniform, so
+                           it acts on g alone, and the collision (Eq. 3)
+                           adds back the reference's conserved moments and
+                           takes out its one nonzero nonconserved
+                           equilibrium.  The FP32 rounding of every step
+                           then scales with |f - f_ref| rather than |f|:
+                           near the reference state (smooth, slow flow) the
+                           error against exact arithmetic falls by the
+                           ratio.  mrtfd_get_f / mrtfd_set_f exchange g;
+                           mrtfd_ref_populations gives f_ref.           */
 } mrtfd_params;
 
 typedef struct mrtfd_ctx mrtfd_ctx;
@@ -191,9 +207,18 @@ int32_t mrtfd_read_macro(mrtfd_ctx *ctx, float *d_rho, float *d_ux, float *d_uy,
 int32_t mrtfd_sums(mrtfd_ctx *ctx, double out[4]);
 
 /* Copy the interior populations out of / into the context as a packed
- * device FP32 array [16][ny][nx] (checkpoint / restart, seeded states). */
+ * device FP32 array [16][ny][nx] (checkpoint / restart, seeded states).
+ * These are the populations as stored: f itself, or g = f - f_ref when the
+ * parameters set a reference state (ref_rho, ref_T), so that a checkpoint
+ * taken with mrtfd_get_f restarts bit for bit. */
 int32_t mrtfd_get_f(mrtfd_ctx *ctx, float *d_f);
 int32_t mrtfd_set_f(mrtfd_ctx *ctx, const float *d_f);
+
+/* f_ref = M^-1 f-hat^eq(ref_rho, 0, 0, ref_rho ref_T) (Eq. 14, FP64, from
+ * the FP32 roundings of ref_rho and ref_T) of these parameters into the host
+ * array out[16]; zeros when no reference state is set.  f = g + f_ref for the
+ * arrays of mrtfd_get_f / mrtfd_set_f.  Needs no GPU. */
+int32_t mrtfd_ref_populations(const mrtfd_params *p, double out[16]);
 
 /* Current step index and time t = step * dt (host outputs, may be NULL). */
 int32_t mrtfd_time(mrtfd_ctx *ctx, int64_t *step, double *t);

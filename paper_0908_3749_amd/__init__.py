@@ -7,4 +7,4 @@ not need a GPU; using a grid does.
 """
 from . import _abi  # noqa: F401
 from ._abi import MrtfdError, lib  # noqa: F401
-from .solver import MRT2D, TubeBatch, check_params, make_params  # noqa: F401
+from .solver import MRT2D, TubeBatch, check_params, make_params, ref_populations  # noqa: F401

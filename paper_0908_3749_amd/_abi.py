@@ -70,6 +70,7 @@ class mrtfd_params(C.Structure):
         ("rows", C.c_int32), ("graph_steps", C.c_int32),
         ("collision", C.c_int32), ("layout", C.c_int32),
         ("flux_budget", C.c_int32),
+        ("ref_rho", C.c_double), ("ref_T", C.c_double),
     ]
 
 
@@ -87,6 +88,7 @@ _PROTOS = {
     "mrtfd_sums": (C.c_int32, [_vp, C.POINTER(C.c_double)]),
     "mrtfd_get_f": (C.c_int32, [_vp, _fp]),
     "mrtfd_set_f": (C.c_int32, [_vp, _fp]),
+    "mrtfd_ref_populations": (C.c_int32, [C.POINTER(mrtfd_params), C.POINTER(C.c_double)]),
     "mrtfd_time": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "mrtfd_set_step": (C.c_int32, [_vp, C.c_int64]),
     "mrtfd_kernel_info": (C.c_int32, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),

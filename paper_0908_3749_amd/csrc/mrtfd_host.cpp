@@ -231,6 +231,25 @@ void feq_host(const Model &m, double rho, double ux, double uy, double T, double
     }
 }
 
+// The reference state at rest (rho0, T0), rounded to FP32 as the kernels
+// hold it; (0, 0) when none is set.
+void ref_state(const mrtfd_params &p, double &rho0, double &T0)
+{
+    rho0 = p.ref_rho > 0 ? (double)(float)p.ref_rho : 0.0;
+    T0 = p.ref_rho > 0 ? (double)(float)p.ref_T : 0.0;
+}
+
+// f_ref = M^-1 f-hat^eq(rho0, 0, 0, rho0 T0) in FP64; zeros without a reference.
+void ref_populations(const Model &m, const mrtfd_params &p, double out[NQ])
+{
+    double rho0, T0;
+    ref_state(p, rho0, T0);
+    if (rho0 > 0)
+        feq_host(m, rho0, 0.0, 0.0, T0, out);
+    else
+        for (int q = 0; q < NQ; ++q) out[q] = 0.0;
+}
+
 void fill_consts(const Model &m, const mrtfd_params &p, Consts &K)
 {
     std::memset(&K, 0, sizeof K);
@@ -275,6 +294,12 @@ void fill_consts(const Model &m, const mrtfd_params &p, Consts &K)
         K.lw[q][2] = (float)(0.5 * (b * b - b));
         K.lw[q][3] = (float)(0.5 * (b * b + b));
     }
+    double rho0, T0;
+    ref_state(p, rho0, T0);
+    K.rho0 = (float)rho0;
+    K.T0 = (float)T0;
+    K.e0 = (float)(rho0 * T0);
+    K.Te0 = (float)(T0 * rho0 * T0);
 }
 
 // BF16 bits of an FP32 value, round to nearest even (as the kernels do).
@@ -371,6 +396,11 @@ int check(const mrtfd_params *p, char *msg, size_t len)
         return fail(MRTFD_ERR_ARG, "flux_budget must be 0 or 1");
     if (p->graph_steps < 0 || (p->graph_steps % 2) != 0 || p->graph_steps > 4096)
         return fail(MRTFD_ERR_ARG, "graph_steps must be even, in [0, 4096]");
+    if (!std::isfinite(p->ref_rho) || !std::isfinite(p->ref_T) || p->ref_rho < 0 || p->ref_T < 0 ||
+        ((p->ref_rho > 0) != (p->ref_T > 0)) ||
+        (p->ref_rho > 0 && (!((float)p->ref_rho > 0.f) || !((float)p->ref_T > 0.f) ||
+                            !std::isfinite((float)p->ref_rho) || !std::isfinite((float)p->ref_T))))
+        return fail(MRTFD_ERR_ARG, "reference state: ref_rho and ref_T both > 0 (FP32 range), or both 0");
     for (int s = 0; s < 4; ++s) {
         const mrtfd_side &S = p->side[s];
         for (int part = 0; part < 2; ++part) {
@@ -495,6 +525,9 @@ struct mrtfd_ctx {
     int device = 0;
     int cur = 0;                 // which copy holds the state
     long long step = 0;
+    double fref[NQ] = {0};       // f_ref (FP64) of the reference state, zeros if none
+    double ref_out[4][4] = {{0}};// outflow of f_ref per side node and step
+    long long budget_steps = 0;  // steps added to the outflow budget since its reset
     bool initialised = false;
     int kernel = 0, seg = 0;     // step kernel in use and its rows per wave
     bool tuned = false;          // kernel/seg final (explicit, cached or timed)
@@ -784,6 +817,16 @@ int32_t mrtfd_model(double *v, double *M, double *Minv)
     return MRTFD_OK;
 }
 
+int32_t mrtfd_ref_populations(const mrtfd_params *p, double out[16])
+{
+    if (!p || !out) return MRTFD_ERR_ARG;
+    if (check(p, nullptr, 0) != MRTFD_OK) return MRTFD_ERR_ARG;
+    const Model &m = model();
+    if (!m.ok) return MRTFD_ERR_ARG;
+    ref_populations(m, *p, out);
+    return MRTFD_OK;
+}
+
 int32_t mrtfd_struct_sizes(size_t *params_size, size_t *side_size)
 {
     if (params_size) *params_size = sizeof(mrtfd_params);
@@ -848,6 +891,20 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     }
     c->stream = static_cast<hipStream_t>(stream);
     fill_consts(m, *p, c->K);
+    double rho0, T0;
+    ref_state(*p, rho0, T0);
+    ref_populations(m, *p, c->fref);
+    // outflow of the uniform f_ref through one node of each side per step
+    // (its face value is v f_ref), added to the budget's totals on readout
+    for (int s = 0; s < 4; ++s)
+        for (int k = 0; k < 4; ++k) {
+            double a = 0.0;
+            for (int q = 0; q < NQ; ++q) {
+                const double c0 = s < 2 ? c->FC.cx[q][0] : c->FC.cy[q][0];
+                a += c->FC.w[k][q] * 2.0 * c0 * c->fref[q];
+            }
+            c->ref_out[s][k] = (s == 0 || s == 2) ? -a : a;
+        }
     for (int k = 0; k < 4; ++k)
         for (int q = 0; q < NQ; ++q) c->W.w[k][q] = m.M[k][q];
     c->G.dt = p->dt;
@@ -865,20 +922,23 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         g.split_rate = S.split_rate;
         g.h = s < 2 ? p->dy : p->dx;
         double fe[NQ];
+        // states as deviations from the reference (rho - rho0, u1, u2, T - T0)
+        // and Dirichlet equilibria as f^eq - f_ref, both in FP64, then rounded
+        const double off[4] = {rho0, 0.0, 0.0, T0};
         for (int k = 0; k < 4; ++k) {
-            g.st_lo[k] = (float)S.state_lo[k];
-            g.st_hi[k] = (float)S.state_hi[k];
+            g.st_lo[k] = (float)(S.state_lo[k] - off[k]);
+            g.st_hi[k] = (float)(S.state_hi[k] - off[k]);
         }
         const bool dlo = S.kind_lo == MRTFD_BC_DIRICHLET, dhi = S.kind_hi == MRTFD_BC_DIRICHLET;
         std::memset(g.feq_lo, 0, sizeof g.feq_lo);
         std::memset(g.feq_hi, 0, sizeof g.feq_hi);
         if (dlo) {
             feq_host(m, S.state_lo[0], S.state_lo[1], S.state_lo[2], S.state_lo[3], fe);
-            for (int q = 0; q < NQ; ++q) g.feq_lo[q] = (float)fe[q];
+            for (int q = 0; q < NQ; ++q) g.feq_lo[q] = (float)(fe[q] - c->fref[q]);
         }
         if (dhi) {
             feq_host(m, S.state_hi[0], S.state_hi[1], S.state_hi[2], S.state_hi[3], fe);
-            for (int q = 0; q < NQ; ++q) g.feq_hi[q] = (float)fe[q];
+            for (int q = 0; q < NQ; ++q) g.feq_hi[q] = (float)(fe[q] - c->fref[q]);
         }
     }
     // default until tuned: rows kernel, one row per wave, plain stores
@@ -938,6 +998,7 @@ int32_t mrtfd_init_macro(mrtfd_ctx *c, const float *rho, const float *ux, const 
     HIPCHK(c, launch_counter_set(c->d_step, 0, c->stream));
     if (c->p.flux_budget)
         HIPCHK(c, launch_zero(c->flux, c->L.outflow - c->L.flux, c->stream));
+    c->budget_steps = 0;
     c->step = 0;
     c->initialised = true;
     return MRTFD_OK;
@@ -950,6 +1011,7 @@ int32_t mrtfd_set_f(mrtfd_ctx *c, const float *src)
     HIPCHK(c, launch_unpack(c->F, src, c->f[c->cur], c->stream));
     if (c->p.flux_budget)
         HIPCHK(c, launch_zero(c->flux, c->L.outflow - c->L.flux, c->stream));
+    c->budget_steps = 0;
     c->initialised = true;
     return MRTFD_OK;
 }
@@ -969,6 +1031,7 @@ int32_t mrtfd_step(mrtfd_ctx *c, int64_t nsteps)
     if (nsteps < 0) return set_err(c, MRTFD_ERR_ARG, "nsteps must be >= 0");
     if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "step before init");
     if (nsteps == 0) return MRTFD_OK;
+    c->budget_steps += nsteps;
     long long left = nsteps;
     if (!c->tuned) {
         long long taken = 0;
@@ -1010,6 +1073,12 @@ int32_t mrtfd_sums(mrtfd_ctx *c, double out[4])
     HIPCHK(c, hipMemcpyAsync(h, c->sums, sizeof h, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&flag, c->d_flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    // the reference state's share: its moments (rho0, 0, 0, e0) at every node
+    const double nodes = (double)c->p.nx * (double)c->p.ny;
+    double rho0, T0;
+    ref_state(c->p, rho0, T0);
+    h[0] += nodes * rho0;
+    h[3] += nodes * (rho0 * T0);
     for (int k = 0; k < 4; ++k) out[k] = h[k];
     if (flag) return set_err(c, MRTFD_ERR_ARG, "initial state had rho <= 0, T <= 0 or non-finite values");
     for (int k = 0; k < 4; ++k)
@@ -1026,6 +1095,12 @@ int32_t mrtfd_outflow(mrtfd_ctx *c, double out[16])
     double h[16];
     HIPCHK(c, hipMemcpyAsync(h, c->outflow, sizeof h, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    // the kernels take face values of the stored g = f - f_ref; the uniform
+    // f_ref adds the same outflow through every side node in every step
+    for (int sd = 0; sd < 4; ++sd) {
+        const double len = sd < 2 ? (double)c->p.ny : (double)c->p.nx;
+        for (int k = 0; k < 4; ++k) h[4 * sd + k] += (double)c->budget_steps * len * c->ref_out[sd][k];
+    }
     for (int k = 0; k < 16; ++k) out[k] = h[k];
     for (int k = 0; k < 16; ++k)
         if (!std::isfinite(h[k])) return set_err(c, MRTFD_ERR_NONFINITE, "outflow %d is not finite", k);

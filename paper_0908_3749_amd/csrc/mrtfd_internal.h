@@ -45,6 +45,10 @@ struct Consts {
     // + cN (fN - f) + cS (fS - f), cE = (a^2 - a)/2, cW = (a^2 + a)/2 with
     // a = v_x dt / dx (likewise N/S with b = v_y dt / dy).
     float lw[NQ][4];  // cE, cW, cN, cS
+    // Reference state at rest: the copies of f hold g = f - f^eq(rho0, 0, 0,
+    // T0); e0 = rho0 T0 is its energy and Te0 = T0 e0.  All zero when no
+    // reference is set (g = f).
+    float rho0, T0, e0, Te0;
 };
 
 // Device layout of one copy of f.  Rows j = -1 .. ny of 16 x `pitch` floats;
@@ -86,8 +90,8 @@ enum Kind { K_PERIODIC = 0, K_DIRICHLET = 1, K_REFLECT = 2, K_EXTRAPOLATE = 3, K
 
 struct GhostSide {
     int kind_lo, kind_hi;
-    float st_lo[4], st_hi[4];        // rho, u1, u2, T
-    float feq_lo[NQ], feq_hi[NQ];    // f^eq of the states (host FP64, rounded)
+    float st_lo[4], st_hi[4];        // rho - rho0, u1, u2, T - T0 (host FP64, rounded)
+    float feq_lo[NQ], feq_hi[NQ];    // f^eq - f_ref of the states (host FP64, rounded)
     double split0, split_rate;       // rule switch point along the side
     double h;                        // node spacing along the side
 };

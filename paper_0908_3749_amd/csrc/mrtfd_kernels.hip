@@ -6,7 +6,12 @@
 //   f_new = f - dt [Lax-Wendroff difference of v.grad f] - dt*C (Eq. A.1a-b),
 // collision and stencil both on the old state.  FP32 throughout; FP64 only in
 // the conservation sums and in the time comparison that picks a boundary
-// rule.  All code is compiled with FMA contraction off: every fused
+// rule.  The state is stored as g = f - f_ref, f_ref the equilibrium of a
+// reference state at rest (zero when none is set): the difference stencil
+// is linear and f_ref uniform, so it acts on g unchanged, and the collision
+// needs only the reference's conserved moments added back and its one
+// nonzero nonconserved equilibrium (f-hat_11) taken out, so that FP32
+// rounding scales with |f - f_ref| instead of |f|.  All code is compiled with FMA contraction off: every fused
 // multiply-add below is written out, so every kernel variant rounds a node's
 // update identically and their results agree bit for bit.
 #include <type_traits>
@@ -94,27 +99,36 @@ __device__ __forceinline__ void moments(const Consts &K, const float (&f)[NQ], f
     m[13] = fma_(K.fqd[1][1], Q[3], K.fqd[1][0] * Q[2]);
 }
 
-// Conserved moments only: rho, j_x, j_y, e.
-__device__ __forceinline__ void conserved(const Consts &K, const float (&f)[NQ], float &rho,
-                                          float &jx, float &jy, float &e)
+// Conserved moments of the stored populations.  The library stores g = f -
+// f_ref, f_ref = f^eq of a reference state at rest (rho0, 0, 0, T0) (all
+// zero when no reference is set, so that g = f): the moments of g are rho -
+// rho0, j_x, j_y, e - e0 with e0 = rho0 T0.
+__device__ __forceinline__ void conserved(const Consts &K, const float (&f)[NQ], float &dr,
+                                          float &jx, float &jy, float &de)
 {
     float A[4], X[4], Y[4], Q[4];
     butterflies(f, A, X, Y, Q);
-    rho = dot4(K.f0[0], A);
-    e = dot4(K.f0[1], A);
+    dr = dot4(K.f0[0], A);
+    de = dot4(K.f0[1], A);
     jx = dot4(K.fx[0], X);
     jy = dot4(K.fy[0], Y);
 }
 
 // Equilibria of the nonconserved moments, Eq. (14a)-(14i), written with
 // u = j / rho; moments 12, 15, 16 have zero equilibrium.  P = e - |j|^2/(2 rho).
+// Inputs are deviations from the reference state (dr = rho - rho0, de = e -
+// e0) and the outputs are the equilibria less the reference's: at rest only
+// f-hat_11^eq = 2 e^2 / rho - |j|^4 / (4 rho^3) is nonzero, 2 rho0 T0^2, and
+// 2 e^2/rho - 2 e0^2/rho0 = (2/rho) (de (2 e0 + de) - T0 e0 dr) is formed from
+// the deviations so that its rounding scales with them.
 struct Eq {
     float e5, e6, e7, e8, e9, e10, e11, e13, e14;
 };
 
-__device__ __forceinline__ Eq equilibria(float rho, float jx, float jy, float e)
+__device__ __forceinline__ Eq equilibria(const Consts &K, float dr, float jx, float jy, float de)
 {
     Eq q;
+    const float rho = K.rho0 + dr, e = K.e0 + de;
     const float r = 1.0f / rho;  // IEEE division
     const float ux = jx * r, uy = jy * r;
     const float jux = jx * ux, juy = jy * uy;
@@ -128,8 +142,9 @@ __device__ __forceinline__ Eq equilibria(float rho, float jx, float jy, float e)
     q.e8 = h * uy;                                    // (e + P) jy / rho
     q.e9 = fma_(-3.0f, uyy, uxx) * jx;                // (jx^2 - 3 jy^2) jx / rho^2
     q.e10 = fma_(3.0f, uxx, -uyy) * jy;               // (3 jx^2 - jy^2) jy / rho^2
+    const float dd = fma_(de, 2.0f * K.e0 + de, -(K.Te0 * dr));
+    q.e11 = fma_(2.0f * dd, r, (-0.25f * rho) * (u2 * u2));  // 2 e^2/rho - |j|^4/(4 rho^3) - 2 e0^2/rho0
     const float er = e * r;
-    q.e11 = fma_(2.0f * e, er, (-0.25f * rho) * (u2 * u2));  // 2 e^2/rho - |j|^4/(4 rho^3)
     const float kap = fma_(6.0f, er, -2.0f * u2);    // (6 rho e - 2 |j|^2) / rho^2
     q.e13 = kap * q.e5;
     q.e14 = kap * q.e6;
@@ -143,7 +158,7 @@ __device__ __forceinline__ void collide(const Consts &K, const float (&f)[NQ], f
 {
     float m[NQ];
     moments(K, f, m);
-    const Eq q = equilibria(m[0], m[1], m[2], m[3]);
+    const Eq q = equilibria(K, m[0], m[1], m[2], m[3]);
     const float d5 = m[4] - q.e5, d6 = m[5] - q.e6, d7 = m[6] - q.e7, d8 = m[7] - q.e8;
     const float d9 = m[8] - q.e9, d10 = m[9] - q.e10, d11 = m[10] - q.e11, d12 = m[11];
     const float d13 = m[12] - q.e13, d14 = m[13] - q.e14, d15 = m[14], d16 = m[15];
@@ -164,13 +179,13 @@ __device__ __forceinline__ void collide(const Consts &K, const float (&f)[NQ], f
     group_inv<false>(A[3], X[3], Y[3], Q[3], dC[12], dC[13], dC[14], dC[15]);
 }
 
-// f^eq = M^-1 f-hat^eq of a macroscopic state (initial and boundary nodes).
-// f^eq = M^-1 f-hat^eq of the conserved moments (rho, j, e).
-__device__ __forceinline__ void feq_of_moments(const Consts &K, float rho, float jx, float jy,
-                                               float e, float (&f)[NQ])
+// g^eq = M^-1 (f-hat^eq - f-hat_ref) from the conserved moments as
+// deviations (dr = rho - rho0, j, de = e - e0): initial and boundary nodes.
+__device__ __forceinline__ void feq_of_moments(const Consts &K, float dr, float jx, float jy,
+                                               float de, float (&f)[NQ])
 {
-    const Eq q = equilibria(rho, jx, jy, e);
-    const float h0[4] = {rho, e, q.e11, 0.0f};
+    const Eq q = equilibria(K, dr, jx, jy, de);
+    const float h0[4] = {dr, de, q.e11, 0.0f};
     const float hx[4] = {jx, q.e7, q.e9, 0.0f};
     const float hy[4] = {jy, q.e8, q.e10, 0.0f};
     float A[4], X[4], Y[4], Q[4];
@@ -190,27 +205,31 @@ __device__ __forceinline__ void feq_of_moments(const Consts &K, float rho, float
     group_inv<false>(A[3], X[3], Y[3], Q[3], f[12], f[13], f[14], f[15]);
 }
 
-// f^eq of a macroscopic state (rho, u1, u2, T): initial and boundary nodes.
-__device__ __forceinline__ void feq_velocity(const Consts &K, float rho, float ux, float uy,
-                                             float T, float (&f)[NQ])
+// g^eq of a macroscopic state given as (rho - rho0, u1, u2, T - T0): initial
+// and boundary nodes.  e - e0 = rho T - rho0 T0 + rho |u|^2 / 2 = rho0 (T - T0)
+// + (rho - rho0) T + rho |u|^2 / 2.
+__device__ __forceinline__ void feq_velocity(const Consts &K, float dr, float ux, float uy,
+                                             float dT, float (&f)[NQ])
 {
+    const float rho = K.rho0 + dr, T = K.T0 + dT;
     const float jx = rho * ux, jy = rho * uy;
-    const float e = rho * fma_(0.5f, fma_(ux, ux, uy * uy), T);
-    feq_of_moments(K, rho, jx, jy, e, f);
+    const float de = fma_(0.5f * rho, fma_(ux, ux, uy * uy), fma_(dr, T, K.rho0 * dT));
+    feq_of_moments(K, dr, jx, jy, de, f);
 }
 
-// (rho, u1, u2, T) of one node.
+// (rho - rho0, u1, u2, T - T0) of one node's stored populations:
+// T - T0 = (P - T0 rho) / rho = (de - T0 dr - |j|^2 / (2 rho)) / rho.
 __device__ __forceinline__ void macro_of(const Consts &K, const float (&f)[NQ], float (&q)[4])
 {
-    float rho, jx, jy, e;
-    conserved(K, f, rho, jx, jy, e);
-    const float r = 1.0f / rho;
+    float dr, jx, jy, de;
+    conserved(K, f, dr, jx, jy, de);
+    const float r = 1.0f / (K.rho0 + dr);
     const float ux = jx * r, uy = jy * r;
-    const float P = fma_(-0.5f, jx * ux + jy * uy, e);
-    q[0] = rho;
+    const float dP = fma_(-0.5f, jx * ux + jy * uy, fma_(-K.T0, dr, de));
+    q[0] = dr;
     q[1] = ux;
     q[2] = uy;
-    q[3] = P * r;
+    q[3] = dP * r;
 }
 
 // Which populations move along x / along y.
@@ -257,7 +276,8 @@ struct Unroll<0> {
 // Boundary nodes are never stored: a node next to a non-periodic side builds
 // the value of its missing neighbour when it needs it ("virtual ghost"), and a
 // periodic side is an index wrap.  The ghost node of side SD (0 west, 1 east,
-// 2 south, 3 north) at along-side index a carries f^eq of a macroscopic state
+// 2 south, 3 north) at along-side index a carries f^eq (stored as f^eq -
+// f_ref) of a macroscopic state
 // found by the side's rule (Sect. V) from n1, the boundary node itself, and n2,
 // the next node inward, at time t.  The rule switches from kind_lo to kind_hi
 // where the ghost's along-side coordinate passes split0 + split_rate t; that
@@ -288,11 +308,11 @@ __device__ __forceinline__ void ghost_of(const Consts &K, const Ghosts &G, doubl
         macro_of(K, n2, q2);
 #pragma unroll
         for (int c = 0; c < 4; ++c) st[c] = fma_(2.0f, q1[c], -q2[c]);
-        if (!(st[0] > 0.f) || !(st[3] > 0.f)) {
+        if (!(K.rho0 + st[0] > 0.f) || !(K.T0 + st[3] > 0.f)) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) st[c] = q1[c];
         }
-    } else {  // wall: density of the fluid, speed and temperature of the wall
+    } else {  // wall: density of the fluid, speed and temperature of the wall (T - T0)
         st[0] = q1[0];
         st[1] = lo ? S.st_lo[1] : S.st_hi[1];
         st[2] = lo ? S.st_lo[2] : S.st_hi[2];
@@ -779,9 +799,9 @@ void k_step_mfma(Field F, Consts K, Ghosts G,
     // Conserved moments and equilibria once per node, in FP32 as the scalar
     // path computes them, staged beside the populations; the LDS regions are
     // private to the wave.
-    float rho, jx, jy, e;
-    conserved(K, cur, rho, jx, jy, e);
-    const Eq eq = equilibria(rho, jx, jy, e);
+    float dr, jx, jy, de;
+    conserved(K, cur, dr, jx, jy, de);
+    const Eq eq = equilibria(K, dr, jx, jy, de);
     float (*st)[NQ + 2] = stage[wv];
     float (*qs)[13] = eqst[wv];
 #pragma unroll
@@ -932,7 +952,7 @@ __global__ __launch_bounds__(256) void k_tubes_init(TubeGrid TG, Consts K,
     if (x >= n) return;
     const float *st = states + (long long)k * 8 + (x < n / 2 ? 0 : 4);
     float fe[NQ];
-    feq_velocity(K, st[0], st[1], st[2], st[3], fe);
+    feq_velocity(K, st[0] - K.rho0, st[1], st[2], st[3] - K.T0, fe);
     const int start = tubes[k].start;
     for (int y = 0; y < TUBE_ROWS; ++y)
 #pragma unroll
@@ -953,11 +973,12 @@ __global__ __launch_bounds__(256) void k_tube_macro(TubeGrid TG, Consts K,
 #pragma unroll
     for (int c = 0; c < NQ; ++c) fc[c] = f[(long long)c * TG.plane + (long long)y * TG.ncols + start + x];
     macro_of(K, fc, q);
-    if (rho) rho[idx] = q[0];
+    const float rh = K.rho0 + q[0], tt = K.T0 + q[3];
+    if (rho) rho[idx] = rh;
     if (ux) ux[idx] = q[1];
     if (uy) uy[idx] = q[2];
-    if (Tt) Tt[idx] = q[3];
-    if (p) p[idx] = q[0] * q[3];
+    if (Tt) Tt[idx] = tt;
+    if (p) p[idx] = rh * tt;
 }
 
 __global__ __launch_bounds__(256) void k_tube_pack(TubeGrid TG, const TubeInfo *__restrict__ tubes,
@@ -989,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_init(Field F, Consts K, float *__restri
         !isfinite(t))
         atomicOr(flag, 1);
     float fe[NQ];
-    feq_velocity(K, r, ux[c], uy[c], t, fe);
+    feq_velocity(K, r - K.rho0, ux[c], uy[c], t - K.T0, fe);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) f[F.at(q, i, j)] = fe[q];
 }
@@ -1028,11 +1049,12 @@ __global__ __launch_bounds__(256) void k_read_macro(Field F, Consts K, const flo
 #pragma unroll
     for (int k = 0; k < NQ; ++k) fc[k] = f[F.at(k, i, j)];
     macro_of(K, fc, q);
-    if (rho) rho[c] = q[0];
+    const float rh = K.rho0 + q[0], tt = K.T0 + q[3];
+    if (rho) rho[c] = rh;
     if (ux) ux[c] = q[1];
     if (uy) uy[c] = q[2];
-    if (T) T[c] = q[3];
-    if (p) p[c] = q[0] * q[3];
+    if (T) T[c] = tt;
+    if (p) p[c] = rh * tt;
 }
 
 constexpr int SUM_BLOCKS_MAX = 1024;

@@ -24,10 +24,12 @@ LAYOUTS = {"rows": _abi.MRTFD_LAYOUT_ROWS, "planes": _abi.MRTFD_LAYOUT_PLANES,
 
 
 def make_params(nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto", rows=0,
-                graph_steps=0, collision="mrt", layout="rows", flux_budget=False):
+                graph_steps=0, collision="mrt", layout="rows", flux_budget=False, ref=None):
     """Fill the C parameter struct.  sides: dict west/east/south/north of
     dicts with kind_lo, kind_hi (rule names), state_lo, state_hi
-    (rho, u1, u2, T), split0, split_rate."""
+    (rho, u1, u2, T), split0, split_rate.  ref: (rho0, T0) of the reference
+    state at rest whose equilibrium the library subtracts from the stored
+    populations, or None."""
     p = _abi.mrtfd_params()
     p.nx, p.ny = int(nx), int(ny)
     p.dx, p.dy, p.dt = float(dx), float(dy), float(dt)
@@ -51,7 +53,19 @@ def make_params(nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto", r
     p.collision = COLLISIONS[collision]
     p.layout = LAYOUTS[layout]
     p.flux_budget = 1 if flux_budget else 0
+    if ref is not None:
+        p.ref_rho, p.ref_T = float(ref[0]), float(ref[1])
     return p
+
+
+def ref_populations(p):
+    """f_ref (FP64, 16 values) of a parameter struct; zeros without a
+    reference state."""
+    out = (C.c_double * 16)()
+    st = lib().mrtfd_ref_populations(C.byref(p), out)
+    if st != _abi.MRTFD_OK:
+        raise _abi.MrtfdError(st, "ref_populations")
+    return np.array(out[:])
 
 
 def check_params(p):
@@ -66,12 +80,12 @@ class MRT2D:
 
     def __init__(self, nx, ny, dx, dy, dt, s, sides, precision="fp32", kernel="auto",
                  rows=0, graph_steps=0, collision="mrt", layout="rows", flux_budget=False,
-                 device=None, stream=None):
+                 ref=None, device=None, stream=None):
         import torch
 
         self.torch = torch
         self.p = make_params(nx, ny, dx, dy, dt, s, sides, precision, kernel, rows, graph_steps,
-                             collision, layout, flux_budget)
+                             collision, layout, flux_budget, ref)
         st, msg = check_params(self.p)
         if st != _abi.MRTFD_OK:
             raise _abi.MrtfdError(st, msg)
@@ -149,9 +163,17 @@ class MRT2D:
         return f
 
     def get_f_numpy(self):
+        """The stored populations (g = f - f_ref with a reference state)."""
         f = self.get_f()
         self.stream.synchronize()
         return f.cpu().numpy()
+
+    def ref_populations(self):
+        return ref_populations(self.p)
+
+    def populations_numpy(self):
+        """f = g + f_ref in FP64, [16][ny][nx]."""
+        return self.get_f_numpy().astype(np.float64) + self.ref_populations()[:, None, None]
 
     def set_f(self, f):
         a = self._dev(f).reshape(16, self.ny, self.nx)

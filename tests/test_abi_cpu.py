@@ -144,3 +144,26 @@ def test_product_has_no_oracle_dependency():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "oracle" not in text.replace("the oracle", ""), fn
                 assert "liboracle" not in text, fn
+
+
+def test_reference_populations(abi):
+    """f_ref of a reference state at rest is the equilibrium of Eq. (14)
+    mapped back by M^-1 (the oracle's, independently built); no reference
+    gives zeros; half a reference is rejected."""
+    from oracle import core
+    from paper_0908_3749_amd import check_params, ref_populations
+    prob = synth.couette(nx=16, ny=64)
+    p = _params(prob)
+    assert list(ref_populations(p)) == [0.0] * 16
+    for rho0, T0 in ((1.0, 1.0), (2.5, 0.75), (0.125, 4.0)):
+        p = _params(prob, ref=(rho0, T0))
+        assert check_params(p) == (0, "")
+        got = ref_populations(p)
+        want = core.feq_velocity(rho0, 0.0, 0.0, T0)
+        assert abs(got - want).max() <= 1e-14 * abs(want).max(), (rho0, T0)
+        # the conserved moments of f_ref are (rho0, 0, 0, rho0 T0)
+        m = core.model()
+        assert abs(m.M[:4] @ got - [rho0, 0.0, 0.0, rho0 * T0]).max() <= 1e-13
+    for bad in ((1.0, 0.0), (0.0, 1.0), (-1.0, 1.0), (1.0, math.inf), (1e300, 1.0)):
+        p = _params(prob, ref=bad)
+        assert check_params(p)[0] == abi.MRTFD_ERR_ARG, bad
