@@ -206,6 +206,21 @@ int32_t mrtfd_read_macro(mrtfd_ctx *ctx, float *d_rho, float *d_ux, float *d_uy,
  * MRTFD_ERR_NONFINITE if any sum is not finite. */
 int32_t mrtfd_sums(mrtfd_ctx *ctx, double out[4]);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the FP64 sums of
+ * mrtfd_sums written to the caller's device array d_out[4] (rho, j_x, j_y,
+ * e), enqueued on the context's stream with no synchronisation, no host
+ * copy and no allocation of any kind.  The reduction's partial sums go to a
+ * library-held device array of 4096 doubles (32 KiB, one per GPU, held until
+ * the process ends; a reduction uses at most 1024 x 4 of them, so every grid
+ * fits and larger needs would be refused with MRTFD_ERR_ARG).  Same kernels
+ * and summation order as mrtfd_sums: the same bits.  The caller checks the
+ * values for finiteness.  All contexts on one GPU share that array: calls
+ * whose kernels can overlap (different streams on the same GPU without
+ * ordering between them) race and give wrong sums; calls on one stream, or
+ * ordered by events, are safe. */
+int32_t mrtfd_sums_noalloc(mrtfd_ctx *ctx, double *d_out);
+
 /* Copy the interior populations out of / into the context as a packed
  * device FP32 array [16][ny][nx] (checkpoint / restart, seeded states).
  * These are the populations as stored: f itself, or g = f - f_ref when the

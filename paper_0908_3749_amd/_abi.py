@@ -86,6 +86,7 @@ _PROTOS = {
     "mrtfd_outflow": (C.c_int32, [_vp, C.POINTER(C.c_double)]),
     "mrtfd_read_macro": (C.c_int32, [_vp, _fp, _fp, _fp, _fp, _fp]),
     "mrtfd_sums": (C.c_int32, [_vp, C.POINTER(C.c_double)]),
+    "mrtfd_sums_noalloc": (C.c_int32, [_vp, _vp]),
     "mrtfd_get_f": (C.c_int32, [_vp, _fp]),
     "mrtfd_set_f": (C.c_int32, [_vp, _fp]),
     "mrtfd_ref_populations": (C.c_int32, [C.POINTER(mrtfd_params), C.POINTER(C.c_double)]),

@@ -515,6 +515,7 @@ struct mrtfd_ctx {
     MfmaOperands *d_mfma = nullptr;
     MfmaOperands h_mfma;
     double *flux = nullptr, *outflow = nullptr;  // outflow budget slots and totals
+    double *scratch = nullptr;   // this device's library scratch (mrtfd_sums_noalloc)
     FluxCoef FC;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;  // private stream used only to capture graphs
@@ -907,6 +908,16 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         }
     for (int k = 0; k < 4; ++k)
         for (int q = 0; q < NQ; ++q) c->W.w[k][q] = m.M[k][q];
+    {
+        // the reference state's share of the sums: its moments (rho0, 0, 0,
+        // e0) at every node
+        double rho0, T0;
+        ref_state(*p, rho0, T0);
+        const double nodes = (double)p->nx * (double)p->ny;
+        c->W.add[0] = nodes * rho0;
+        c->W.add[1] = c->W.add[2] = 0.0;
+        c->W.add[3] = nodes * (rho0 * T0);
+    }
     c->G.dt = p->dt;
     c->G.kd = reinterpret_cast<const Consts *>(c->ws + L.kcopy);
     c->G.gd = reinterpret_cast<const Ghosts *>(c->ws + L.gcopy);
@@ -954,6 +965,8 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         c->tuned = false;
     }
     hipError_t e = hipGetDevice(&c->device);
+    // this device's copy of the library scratch (mrtfd_sums_noalloc)
+    if (e == hipSuccess) e = scratch_address(c->device, &c->scratch);
     if (e == hipSuccess && p->flux_budget) {
         e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
@@ -1073,16 +1086,24 @@ int32_t mrtfd_sums(mrtfd_ctx *c, double out[4])
     HIPCHK(c, hipMemcpyAsync(h, c->sums, sizeof h, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&flag, c->d_flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    // the reference state's share: its moments (rho0, 0, 0, e0) at every node
-    const double nodes = (double)c->p.nx * (double)c->p.ny;
-    double rho0, T0;
-    ref_state(c->p, rho0, T0);
-    h[0] += nodes * rho0;
-    h[3] += nodes * (rho0 * T0);
     for (int k = 0; k < 4; ++k) out[k] = h[k];
     if (flag) return set_err(c, MRTFD_ERR_ARG, "initial state had rho <= 0, T <= 0 or non-finite values");
     for (int k = 0; k < 4; ++k)
         if (!std::isfinite(h[k])) return set_err(c, MRTFD_ERR_NONFINITE, "sum %d is not finite", k);
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_sums_noalloc(mrtfd_ctx *c, double *d_out)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    if (!d_out) return set_err(c, MRTFD_ERR_ARG, "sums_noalloc: NULL output");
+    if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "sums_noalloc before init");
+    if (!c->scratch) return set_err(c, MRTFD_ERR_STATE, "sums_noalloc: no library scratch");
+    const int nb = sums_blocks(c->F);
+    if (4 * nb > SCRATCH_DOUBLES)
+        return set_err(c, MRTFD_ERR_ARG, "sums_noalloc: %d partial sums exceed the scratch of %d",
+                       4 * nb, SCRATCH_DOUBLES);
+    HIPCHK(c, launch_sums(c->F, c->W, c->f[c->cur], c->scratch, d_out, c->stream));
     return MRTFD_OK;
 }
 

@@ -158,13 +158,24 @@ hipError_t launch_counter_add(long long *d_step, long long n, hipStream_t s);
 hipError_t launch_counter_set(long long *d_step, long long n, hipStream_t s);
 hipError_t launch_read_macro(const Field &F, const Consts &K, const float *f, float *rho,
                              float *ux, float *uy, float *T, float *p, hipStream_t s);
-// FP64 weights of the conserved rows m1..m4 at the 16 velocities.
+// FP64 weights of the conserved rows m1..m4 at the 16 velocities, and the
+// reference state's share of the totals (its moments times the node count),
+// added once at the end.
 struct SumW {
     double w[4][NQ];
+    double add[4];
 };
+// At most SUM_BLOCKS_MAX blocks of 4 partial sums each.
+constexpr int SUM_BLOCKS_MAX = 1024;
+constexpr int SCRATCH_DOUBLES = 4 * SUM_BLOCKS_MAX;
 int sums_blocks(const Field &F);
+// partials: 4 * sums_blocks(F) doubles; out: 4 doubles (device).
 hipError_t launch_sums(const Field &F, const SumW &W, const float *f, double *partials,
                        double *out, hipStream_t s);
+// Device address of the library's file-scope scratch array (SCRATCH_DOUBLES
+// doubles) on `device`, which must be the current device: looked up with
+// hipGetSymbolAddress on the first call per device and kept.
+hipError_t scratch_address(int device, double **out);
 hipError_t launch_pack(const Field &F, const float *f, float *dst, hipStream_t s);
 
 // ------------------------------------------------------------------ tubes

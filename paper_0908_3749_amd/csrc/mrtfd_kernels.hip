@@ -14,6 +14,8 @@
 // rounding scales with |f - f_ref| instead of |f|.  All code is compiled with FMA contraction off: every fused
 // multiply-add below is written out, so every kernel variant rounds a node's
 // update identically and their results agree bit for bit.
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "mrtfd_internal.h"
@@ -1057,7 +1059,6 @@ __global__ __launch_bounds__(256) void k_read_macro(Field F, Consts K, const flo
     if (p) p[c] = rh * tt;
 }
 
-constexpr int SUM_BLOCKS_MAX = 1024;
 
 // FP64 sums of rho, j_x, j_y, e.  Each thread walks a fixed set of nodes,
 // then a fixed-order tree reduction per block; a second kernel adds the block
@@ -1092,7 +1093,7 @@ __global__ __launch_bounds__(256) void k_sums_partial(Field F, SumW W, const flo
 }
 
 __global__ __launch_bounds__(256) void k_sums_final(const double *__restrict__ partials, int nblk,
-                                                    double *out)
+                                                    SumW W, double *out)
 {
     __shared__ double sh[4][256];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1110,7 +1111,7 @@ __global__ __launch_bounds__(256) void k_sums_final(const double *__restrict__ p
         }
         __syncthreads();
     }
-    if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0] + W.add[threadIdx.x];
 }
 
 // Outflow budget.  One thread per node next to a side (west rows, east
@@ -1346,8 +1347,40 @@ hipError_t launch_sums(const Field &F, const SumW &W, const float *f, double *pa
 {
     const int nb = sums_blocks(F);
     hipLaunchKernelGGL(k_sums_partial, dim3(nb), dim3(256), 0, s, F, W, f, partials);
-    hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s, partials, nb, out);
+    hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s, partials, nb, W, out);
     return hipGetLastError();
+}
+
+// Library-held scratch for the reduction partials of the allocation-free
+// sums (4 doubles per block of k_sums_partial).  Each GPU holds its own copy
+// at its own address for the life of the process; host code must use the
+// address that hipGetSymbolAddress reports for the current device, never
+// the symbol itself.
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch;  // device -> address of its copy of `scratch`
+}  // namespace
+
+hipError_t scratch_address(int device, double **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(device);
+    if (it != g_scratch.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+    double *p = nullptr;
+    e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = p;
+    *out = p;
+    return hipSuccess;
 }
 
 hipError_t launch_face_flux(const Field &F, const Consts &K, const Ghosts &G, const FluxCoef &C,
