@@ -1309,6 +1309,13 @@ hipError_t enqueue_rounds(mrtfd_batch *b, hipStream_t s)
     return hipSuccess;
 }
 
+// Pick the work-item width and steps per round (all give the same bits) by
+// timing each candidate on two rounds of the batch itself: round 0, where
+// every tube runs, and the round a quarter of the way through the longest
+// run, where the short tubes are done.  Each trial launch reads copy 0 and
+// writes copy 1, which the real run overwrites.  Two passes over the
+// candidates, each keeping its faster pass (the first launches of a new
+// shape run slower).
 int batch_autotune(mrtfd_batch *b)
 {
     if (b->seg && b->ks) return MRTFD_OK;
@@ -1316,6 +1323,8 @@ int batch_autotune(mrtfd_batch *b)
     static std::map<std::vector<int>, std::pair<int, int>> cache;
     std::vector<int> key(b->n);
     for (long long v : b->steps) key.push_back((int)std::min<long long>(v, 1 << 30));
+    key.push_back(b->p.seg_cols);
+    key.push_back(b->p.round_steps);
     {
         std::lock_guard<std::mutex> lk(mu);
         auto it = cache.find(key);
@@ -1325,59 +1334,86 @@ int batch_autotune(mrtfd_batch *b)
             return MRTFD_OK;
         }
     }
-    hipEvent_t e0, e1;
-    BHIPCHK(b, hipEventCreate(&e0));
-    BHIPCHK(b, hipEventCreate(&e1));
-    double best = -1.0;
-    std::pair<int, int> pick{48, 8};
-    int rc = MRTFD_OK;
-    std::vector<std::vector<TubeItem>> keep;  // host sources of the async uploads
+    struct Cand {
+        int seg, ks;
+        std::vector<TubeItem> items;
+        std::vector<int> ri;
+        double work[2];
+        int round[2];
+    };
+    std::vector<Cand> cands;
     for (int seg : kTubeSegs) {
         if (b->p.seg_cols && seg != b->p.seg_cols) continue;
         for (int ks : {4, 8, 16}) {
             if (b->p.round_steps && ks != b->p.round_steps) continue;
             if (!tubes_config_built(seg, ks)) continue;
-            keep.emplace_back();
-            std::vector<TubeItem> &items = keep.back();
-            std::vector<int> ri;
-            build_items(b, seg, ks, items, ri);
-            if (ri.empty() || ri[0] == 0) continue;
-            double work = 0.0;  // node updates in round 0
-            for (int k = 0; k < b->p.ntubes; ++k)
-                work += (double)b->n[k] * TUBE_ROWS * (double)std::min<long long>(ks, b->steps[k]);
-            hipError_t e = hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(TubeItem),
+            Cand c;
+            c.seg = seg;
+            c.ks = ks;
+            build_items(b, seg, ks, c.items, c.ri);
+            if (c.ri.empty() || c.ri[0] == 0) continue;
+            const int R = (int)c.ri.size();
+            c.round[0] = 0;
+            c.round[1] = R / 4;
+            for (int t = 0; t < 2; ++t) {  // node updates of the trial round
+                double w = 0.0;
+                const long long r = c.round[t];
+                for (int k = 0; k < b->p.ntubes; ++k) {
+                    const long long left = b->steps[k] - r * ks;
+                    if (left > 0) w += (double)b->n[k] * TUBE_ROWS * (double)std::min<long long>(ks, left);
+                }
+                c.work[t] = w;
+            }
+            cands.push_back(std::move(c));
+        }
+    }
+    if (cands.empty()) return bset_err(b, MRTFD_ERR_ARG, "batch autotune: no candidate");
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    int rc = MRTFD_OK;
+    std::vector<double> rate(cands.size(), 0.0);
+    for (int pass = 0; pass < 2 && rc == MRTFD_OK; ++pass) {
+        for (size_t ci = 0; ci < cands.size() && rc == MRTFD_OK; ++ci) {
+            Cand &c = cands[ci];
+            hipError_t e = hipMemcpyAsync(b->d_items, c.items.data(), c.items.size() * sizeof(TubeItem),
                                           hipMemcpyHostToDevice, b->stream);
-            // trial round 0: reads copy 0, writes copy 1 (overwritten by the real run)
-            if (e == hipSuccess)
-                e = launch_tubes(b->TG, b->d_k, b->d_tubes, b->d_items, ri[0], 0, seg, ks, b->f[0], b->f[1],
-                                 b->stream);
-            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
-                e = launch_tubes(b->TG, b->d_k, b->d_tubes, b->d_items, ri[0], 0, seg, ks, b->f[0],
+            double work = 0.0;
+            float total = 0.f;
+            for (int t = 0; t < 2 && e == hipSuccess; ++t) {
+                const int r = c.round[t], ni = c.ri[(size_t)r];
+                if (ni == 0) continue;
+                // one launch to warm the shape, then two timed
+                e = launch_tubes(b->TG, b->d_k, b->d_tubes, b->d_items, ni, r, c.seg, c.ks, b->f[0],
                                  b->f[1], b->stream);
-            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+                for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
+                    e = launch_tubes(b->TG, b->d_k, b->d_tubes, b->d_items, ni, r, c.seg, c.ks, b->f[0],
+                                     b->f[1], b->stream);
+                if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                total += ms;
+                work += 2.0 * c.work[t];
+            }
             if (e != hipSuccess) {
                 rc = bset_err(b, MRTFD_ERR_HIP, "batch autotune: %s", hipGetErrorString(e));
                 break;
             }
-            const double rate = 2.0 * work / std::max(1e-6, (double)ms);
-            if (rate > best) {
-                best = rate;
-                pick = {seg, ks};
-            }
+            rate[ci] = std::max(rate[ci], work / std::max(1e-6, (double)total));
         }
-        if (rc != MRTFD_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    b->seg = pick.first;
-    b->ks = pick.second;
+    size_t pick = 0;
+    for (size_t ci = 1; ci < cands.size(); ++ci)
+        if (rate[ci] > rate[pick]) pick = ci;
+    b->seg = cands[pick].seg;
+    b->ks = cands[pick].ks;
     if (rc == MRTFD_OK) {
         std::lock_guard<std::mutex> lk(mu);
-        cache[key] = pick;
+        cache[key] = std::make_pair(b->seg, b->ks);
     }
     return rc;
 }

@@ -239,12 +239,15 @@ __host__ __device__ constexpr bool has_x(int q) { return q >= 8 || (q % 2) == 0;
 __host__ __device__ constexpr bool has_y(int q) { return q >= 8 || (q % 2) == 1; }
 
 // Lax-Wendroff + Euler update of population q (same operation order in every
-// kernel variant).
+// kernel variant).  The step's increment (the four neighbour terms and the
+// collision) is summed first and added to the node's value last, so that
+// only that final addition rounds at the scale of the stored value; the
+// others round at the scale of the increment.
 template <int Q>
 __device__ __forceinline__ float lw_update(const Consts &K, float fc, float dC, float fE, float fW,
                                            float fN, float fS)
 {
-    float r = fc - dC;
+    float r = -dC;
     if (has_x(Q)) {
         r = fma_(K.lw[Q][0], fE - fc, r);
         r = fma_(K.lw[Q][1], fW - fc, r);
@@ -253,7 +256,7 @@ __device__ __forceinline__ float lw_update(const Consts &K, float fc, float dC, 
         r = fma_(K.lw[Q][2], fN - fc, r);
         r = fma_(K.lw[Q][3], fS - fc, r);
     }
-    return r;
+    return fc + r;
 }
 
 template <int Q>
@@ -341,7 +344,7 @@ __device__ __forceinline__ void node_update(const Field &F, const Consts &K, con
         float dC[NQ];
         collide(K, fc, dC);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) out[q] = fc[q] - dC[q];
+        for (int q = 0; q < NQ; ++q) out[q] = -dC[q];  // the increment, as in lw_update
     }
     if (i == nx - 1 && !G.per_x) {
         float n2[NQ], g[NQ];
@@ -400,7 +403,7 @@ __device__ __forceinline__ void node_update(const Field &F, const Consts &K, con
             if (has_y(q)) out[q] = fma_(K.lw[q][3], fin[F.at(q, i, js)] - fc[q], out[q]);
     }
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) fout[F.at(q, i, j)] = out[q];
+    for (int q = 0; q < NQ; ++q) fout[F.at(q, i, j)] = fc[q] + out[q];
 }
 
 __device__ __forceinline__ double step_time(const Ghosts &G, const long long *d_step, int k)

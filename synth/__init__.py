@@ -115,6 +115,73 @@ def normal_shock(rho1, p1, mach, gamma=GAMMA):
     return rho2, u2, p2, W
 
 
+def riemann_waves(left, right, gamma=GAMMA):
+    """Exact solution of the Riemann problem of two ideal-gas states
+    (rho, u, p) as far as building tube workloads needs it: star pressure
+    and velocity, the two star densities and the speeds of the four wave
+    edges (a shock's two edges coincide).  Star pressure from Newton's method
+    on the sum of the two wave curves, started from the two-rarefaction
+    estimate and kept positive.  Raises ValueError if the states open a
+    vacuum."""
+    rl, ul, pl = (float(v) for v in left)
+    rr, ur, pr = (float(v) for v in right)
+    al, ar = math.sqrt(gamma * pl / rl), math.sqrt(gamma * pr / rr)
+    g1 = (gamma - 1.0) / (2.0 * gamma)
+    if 2.0 / (gamma - 1.0) * (al + ar) <= ur - ul:
+        raise ValueError("vacuum")
+
+    def curve(p, rk, pk, ak):
+        """Velocity change across the wave from state k to pressure p, and
+        its derivative in p."""
+        if p > pk:  # shock
+            A, B = 2.0 / ((gamma + 1.0) * rk), (gamma - 1.0) / (gamma + 1.0) * pk
+            q = math.sqrt(A / (p + B))
+            return (p - pk) * q, q * (1.0 - 0.5 * (p - pk) / (p + B))
+        r = (p / pk) ** g1  # rarefaction
+        return (2.0 * ak / (gamma - 1.0) * (r - 1.0),
+                ak / (gamma * pk) * (p / pk) ** (-(gamma + 1.0) / (2.0 * gamma)))
+
+    p = (((al + ar - 0.5 * (gamma - 1.0) * (ur - ul)) /
+          (al / pl ** g1 + ar / pr ** g1)) ** (1.0 / g1))
+    for _ in range(100):
+        fl, dl = curve(p, rl, pl, al)
+        fr, dr = curve(p, rr, pr, ar)
+        step = (fl + fr + ur - ul) / (dl + dr)
+        pn = max(p - step, 1e-6 * p)
+        if abs(pn - p) <= 1e-15 * (pn + p):
+            p = pn
+            break
+        p = pn
+    fl, _ = curve(p, rl, pl, al)
+    fr, _ = curve(p, rr, pr, ar)
+    u = 0.5 * (ul + ur) + 0.5 * (fr - fl)
+    out = {"pstar": p, "ustar": u}
+    for side, rk, uk, pk, ak, sgn in (("left", rl, ul, pl, al, -1.0), ("right", rr, ur, pr, ar, 1.0)):
+        if p > pk:  # shock: Rankine-Hugoniot density and speed
+            ratio = p / pk
+            g = (gamma - 1.0) / (gamma + 1.0)
+            out["rho_star_" + side] = rk * (ratio + g) / (g * ratio + 1.0)
+            speed = uk + sgn * ak * math.sqrt((gamma + 1.0) / (2.0 * gamma) * ratio + g1)
+            out[side + "_head"] = out[side + "_tail"] = speed
+            out[side + "_shock"] = True
+        else:  # rarefaction: isentropic density, head and tail
+            rs = rk * (p / pk) ** (1.0 / gamma)
+            out["rho_star_" + side] = rs
+            out[side + "_head"] = uk + sgn * ak
+            out[side + "_tail"] = u + sgn * math.sqrt(gamma * p / rs)
+            out[side + "_shock"] = False
+    return out
+
+
+def tube_star(left, right, gamma=GAMMA):
+    """(fastest wave speed, smaller star density, largest star temperature)
+    of a tube's Riemann problem: the star_fn that tube_batch takes."""
+    W = riemann_waves(left, right, gamma)
+    smax = max(abs(W[k]) for k in ("left_head", "left_tail", "right_head", "right_tail"))
+    rmin = min(W["rho_star_left"], W["rho_star_right"])
+    return smax, rmin, W["pstar"] / rmin
+
+
 # -------------------------------------------------------------- workloads
 
 def sod(nx=400, ny=4, dt=2e-5, nsteps=10000):
@@ -395,8 +462,19 @@ def generic(nx, ny, dx, dt, s, sides, ic, nsteps=0, name="generic"):
     return Problem(name, nx, ny, dx, dx, dt, list(s), sides, ic, nsteps)
 
 
+# Draws of the seeded tube batch that the method cannot run: their FP64
+# reference run goes non-physical (rho <= 0, T <= 0 or non-finite) at the
+# initial jump, found by tests/golden/screen_tubes.py.  Keyed by seed; the
+# numbers count the draws that pass the other rules, from 0.
+UNRUNNABLE_DRAWS = {
+    12345: (36, 52, 87, 90, 95, 103, 118, 131, 135, 146, 147, 153, 160, 171, 178, 186, 195, 203,
+            204, 210, 226, 239, 315, 329, 375, 389, 402, 403, 410, 432, 449, 460, 478, 499, 505),
+}
+
+
 def tube_batch(ntubes=512, nmin=200, nmax=8000, seed=12345, dx=0.002, dt=1e-5,
-               cfl_fraction=0.8, star_fn=None, min_star_density=0.05, max_temperature=200.0):
+               cfl_fraction=0.8, star_fn=None, min_star_density=0.05, max_temperature=200.0,
+               skip_draws=None):
     """Independent 1D Riemann problems, each n_k x 4 cells, periodic in y and
     f = f^eq of its initial states at both ends, interface at the middle.
     n_k ~ U{nmin..nmax}; per side rho ~ U[0.1,5], u ~ U[-2,2], p ~ U[0.1,100],
@@ -409,9 +487,14 @@ def tube_batch(ntubes=512, nmin=200, nmax=8000, seed=12345, dx=0.002, dt=1e-5,
     density below min_star_density, or a temperature T = p / rho above
     max_temperature in an end or star state are redrawn.  (With these rates
     and this grid the linear stability screen of Sect. IV finds growing
-    modes for the 16-velocity model above T of about 200.)"""
+    modes for the 16-velocity model above T of about 200.)  Draws listed in
+    skip_draws (default: UNRUNNABLE_DRAWS of the seed) are skipped as well:
+    numbered from 0 among the draws that pass the rules above, they are the
+    ones whose reference run fails at the initial jump."""
     rng = np.random.default_rng(seed)
+    skip = set(UNRUNNABLE_DRAWS.get(seed, ()) if skip_draws is None else skip_draws)
     tubes = []
+    ordinal = -1
     while len(tubes) < ntubes:
         n = int(rng.integers(nmin, nmax + 1))
         L = (rng.uniform(0.1, 5.0), rng.uniform(-2.0, 2.0), rng.uniform(0.1, 100.0))
@@ -426,11 +509,14 @@ def tube_batch(ntubes=512, nmin=200, nmax=8000, seed=12345, dx=0.002, dt=1e-5,
                 continue
             if rmin < min_star_density or tmax > max_temperature:
                 continue
+        ordinal += 1
+        if ordinal in skip:
+            continue
         steps = None
         if smax is not None:
             t_end = cfl_fraction * 0.5 * n * dx / smax
             steps = int(math.floor(t_end / dt))
-        tubes.append(dict(n=n, left=L, right=R, steps=steps))
+        tubes.append(dict(n=n, left=L, right=R, steps=steps, draw=ordinal))
     s = rates(dt, s5=5e3, s6=5e3, s7=3e4, s8=3e4)
     return dict(tubes=tubes, dx=dx, dt=dt, s=s, width=4)
 

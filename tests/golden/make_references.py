@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
-from oracle import core, riemann  # noqa: E402
+from oracle import core, riemann  # noqa: E402,F401
 
 COUETTE_FILE = os.path.join(HERE, "couette_256x2048_50000.npz")
 TUBES_FILE = os.path.join(HERE, "tube_sample_16.npz")

@@ -43,8 +43,61 @@ def test_workload_sizes_match_their_names(key, name, nx, ny):
 
 def test_roofline_constants():
     """128 B per node update (16 FP32 populations read and written once)
-    against 8 TB/s; the VALU ceiling is the published FP32 vector rate over
-    ~330 operations per node update."""
+    against 8 TB/s; the VALU ceiling is half the published FP32 vector rate
+    (157.3 TFLOP/s counts packed FP32, two lanes of work per instruction,
+    which the library's build leaves out), i.e. 64 lane-operations per CU
+    and clock, over ~330 operations per node update: 119 G node updates/s."""
     assert bench.BYTES_PER_UPDATE == 16 * 4 * 2
     assert bench.HBM_PEAK_GBS == 8000.0
-    assert abs(bench.ALU_NODE_RATE * 330 * 2 - 157.3e12) / 157.3e12 < 1e-3
+    assert abs(bench.ALU_NODE_RATE * 330 * 2 * 2 - 157.3e12) / 157.3e12 < 1e-3
+    assert abs(bench.ALU_NODE_RATE - 119.2e9) < 0.1e9
+
+
+def test_default_workload_is_the_hbm_resident_couette():
+    """With no flags, bench.py times the Couette flow on 8192 x 2048 nodes
+    (2 x 1 GiB of populations, beyond the 256 MB last-level cache), stored
+    as deviations from the equilibrium at rest of rho = T = 1."""
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    assert 'ap.add_argument("--config", default="couette"' in src
+    w = bench.workloads()["couette"]
+    assert w["ref"] == (1.0, 1.0) and w["steps"] == 50000
+    prob = w["make"]()
+    assert 2 * 16 * 4 * prob.nx * prob.ny >= 2 * 2 ** 30
+
+
+def test_host_threads():
+    threads, nproc, avail = bench.host_threads()
+    assert 1 <= threads <= avail <= nproc
+
+
+def test_input_riemann_solver_matches_the_oracles():
+    """The input generators' own exact Riemann solver (used to size the tube
+    runs without touching the oracle) agrees with the oracle's on random
+    states of the batch's ranges, both gammas, and reports vacuum alike; the
+    default batch is the same whichever builds it."""
+    import numpy as np
+
+    import synth
+    from oracle import riemann
+
+    rng = np.random.default_rng(3)
+    for gamma in (2.0, 1.4):
+        for _ in range(500):
+            L = (rng.uniform(0.1, 5), rng.uniform(-2, 2), rng.uniform(0.1, 100))
+            R = (rng.uniform(0.1, 5), rng.uniform(-2, 2), rng.uniform(0.1, 100))
+            if riemann.has_vacuum(L, R, gamma):
+                with pytest.raises(ValueError):
+                    synth.riemann_waves(L, R, gamma)
+                continue
+            a, b = synth.riemann_waves(L, R, gamma), riemann.wave_speeds(L, R, gamma)
+            for k in ("pstar", "ustar", "rho_star_left", "rho_star_right", "left_head", "left_tail",
+                      "right_head", "right_tail"):
+                assert abs(a[k] - b[k]) <= 1e-12 * max(1.0, abs(b[k])), (k, a[k], b[k])
+            assert (a["left_shock"], a["right_shock"]) == (b["left_shock"], b["right_shock"])
+
+    def oracle_star(L, R):
+        W = riemann.wave_speeds(L, R)
+        rmin = min(W["rho_star_left"], W["rho_star_right"])
+        return riemann.max_signal_speed(L, R), rmin, W["pstar"] / rmin
+
+    assert synth.tube_batch(star_fn=synth.tube_star) == synth.tube_batch(star_fn=oracle_star)

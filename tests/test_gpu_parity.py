@@ -18,6 +18,7 @@ import pytest
 
 import synth
 from oracle import core, metrics
+from tests.rounding import equilibrium_scale, transform_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -566,17 +567,6 @@ def test_init_matches_oracle(gpu, state):
     assert np.all(ratio <= 64), ratio
 
 
-def transform_scale(prob, f):
-    """max over nodes and populations of (|dt M^-1| |S| |M| |f|)_i + max_q |f_q|:
-    the magnitude that the FP32 collision of a node cancels down from (the
-    moments m_k = sum M_kq f_q and their equilibria, mapped back by dt M^-1 S),
-    plus the node's own populations."""
-    m = core.model()
-    A = np.abs(m.Minv) * prob.dt @ np.diag(np.abs(prob.s)) @ np.abs(m.M)
-    af = np.einsum("ik,kyx->iyx", A, np.abs(f))
-    return float(np.max(af + np.max(np.abs(f), axis=0, keepdims=True)))
-
-
 def _steps_to_autotune(nx, ny):
     """Steps the library's first long-enough mrtfd_step call spends timing
     its candidates (rows per wave x store kind x tile order, plus the simple
@@ -828,35 +818,6 @@ def _tube_shock_cells(prob, rho_o, rho_g):
             b = metrics.crossing(x, rho_g[J], lvl, lo=xs - 0.1, hi=xs + 0.1)
             assert a is not None and b is not None, (side, xs, a, b)
             out[side] = (a - b) / prob.dx
-    return out
-
-
-def equilibrium_scale(prob, f):
-    """max over nodes of (|dt M^-1| |S| |d f-hat^eq / d c| |M_c| |f|)_i, c =
-    (rho, j_x, j_y, e) and M_c their rows of M: the FP32 rounding of the
-    conserved moments (a few u of |M_c| |f|) carried through the equilibria
-    (Eq. 14) and the back-map.  Hot or fast states make it dominate
-    transform_scale: populations of 1e4-1e5 sum to rho ~ 1-6 there.  The
-    Jacobian is a central difference of the oracle's equilibria, once per
-    distinct node state."""
-    m = core.model()
-    A = np.abs(m.Minv) * prob.dt @ np.diag(np.abs(prob.s))
-    fl = f.reshape(16, -1)
-    c = m.M[:4] @ fl
-    cerr = np.abs(m.M[:4]) @ np.abs(fl)
-    keys = np.round(np.concatenate([c, cerr]).T, 10)
-    _, idx = np.unique(keys, axis=0, return_index=True)
-    out = 0.0
-    for i in idx:
-        x0 = c[:, i]
-        J = np.empty((16, 4))
-        for k in range(4):
-            h = 1e-6 * max(1.0, abs(x0[k]))
-            xp, xm = x0.copy(), x0.copy()
-            xp[k] += h
-            xm[k] -= h
-            J[:, k] = (core.feq_moments(*xp) - core.feq_moments(*xm)) / (2 * h)
-        out = max(out, float(np.max(A @ np.abs(J) @ cerr[:, i])))
     return out
 
 
