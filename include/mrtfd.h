@@ -72,10 +72,13 @@ extern "C" {
 
 /* ---- arithmetic of the moment transforms ------------------------------- */
 #define MRTFD_FP32 0  /* FP32 everywhere (FP64 only in mrtfd_sums)            */
-#define MRTFD_BF16X3 1 /* the two 16x16 transforms of the collision on the matrix
-                          cores, operands split into high and low BF16
-                          parts, three products, FP32 accumulation; the rest
-                          FP32 (nodes next to a side use the FP32 path)      */
+#define MRTFD_BF16X3 1 /* the collision's transforms (the 4x4 blocks of the
+                          factored M and M^-1) on the matrix cores, operands
+                          split into high and low BF16 parts, three products,
+                          FP32 accumulation; the butterflies, conserved
+                          moments, equilibria and stencil FP32 (a last grid
+                          column alone in its 64-column wave takes the FP32
+                          collision)                                        */
 
 /* ---- collision operator ------------------------------------------------ */
 #define MRTFD_COLLISION_MRT 0 /* Eq. (3): M^-1 S-hat (f-hat - f-hat^eq)            */
@@ -99,9 +102,10 @@ extern "C" {
                                  read from memory                              */
 #define MRTFD_KERNEL_ROWS 2   /* each wave: `rows` rows of 64 columns loaded
                                  once, west/east neighbours by lane shifts     */
-#define MRTFD_KERNEL_MFMA 3   /* reported only: the matrix-core kernel that
-                                 MRTFD_BF16X3 always uses (its store kind and
-                                 tile order are autotuned)                     */
+#define MRTFD_KERNEL_MFMA 3   /* reported only: the rows kernel with the
+                                 split-BF16 matrix-core collision, which
+                                 MRTFD_BF16X3 always uses (rows per wave, store
+                                 kind and tile order autotuned)                */
 
 /* One side of the grid.  The rule is kind_lo at ghost nodes whose
  * along-side coordinate (x for the south/north sides, y for west/east) is
@@ -268,8 +272,8 @@ int32_t mrtfd_set_step(mrtfd_ctx *ctx, int64_t step);
  * candidates, up to about 600 steps; results are bit-identical whichever
  * runs) and is cached per grid size, precision and flux_budget for later
  * contexts; before that the rows kernel with one row per wave and plain
- * stores runs.  With MRTFD_BF16X3 the same trial picks the
- * matrix-core kernel's store kind and tile order. */
+ * stores runs.  With MRTFD_BF16X3 the same trial picks the split-BF16 rows
+ * kernel's rows per wave, store kind and tile order. */
 int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_t *streaming,
                           int32_t *tile_order);
 

@@ -317,22 +317,46 @@ double bf16_value(unsigned short b)
     return f;
 }
 
-// Split-BF16 A operands of the two transforms (lane layout of the 16x16x16
-// matrix instruction: lane l holds row l % 16, columns 4 (l/16) .. +3).
-void fill_mfma(const Model &m, const mrtfd_params &p, MfmaOperands &mo)
+// Split-BF16 block table (Bf3Ops) from the FP32 constants: for each 4x4
+// block and row, the BF16 high parts (round to nearest even) and the BF16
+// roundings of the remainders, packed two per 32-bit word, element 0 low.
+void fill_bf3(const Consts &K, Bf3Ops &out)
 {
-    std::memset(&mo, 0, sizeof mo);
-    for (int l = 0; l < 64; ++l)
+    float W[8][4][4] = {};
+    for (int i = 0; i < 4; ++i)
         for (int c = 0; c < 4; ++c) {
-            const int r = l % 16, k = 4 * (l / 16) + c;
-            const double a = m.M[r][k], b = m.Minv[r][k] * p.dt;
-            const unsigned short ah = bf16_of((float)a), bh = bf16_of((float)b);
-            mo.m_hi[l][c] = ah;
-            mo.m_lo[l][c] = bf16_of((float)(a - bf16_value(ah)));
-            mo.inv_hi[l][c] = bh;
-            mo.inv_lo[l][c] = bf16_of((float)(b - bf16_value(bh)));
+            W[0][i][c] = K.f0[i][c];
+            W[1][i][c] = K.fx[i][c];
+            W[2][i][c] = K.fy[i][c];
         }
-    for (int k = 0; k < NQ; ++k) mo.s[k] = k < 4 ? 0.f : (float)p.s[k];
+    for (int i = 0; i < 2; ++i) {
+        W[3][i][0] = K.fqa[i][0];      // m5, m13 over Q0, Q1
+        W[3][i][1] = K.fqa[i][1];
+        W[3][2 + i][2] = K.fqd[i][0];  // m6, m14 over Q2, Q3
+        W[3][2 + i][3] = K.fqd[i][1];
+        W[7][i][0] = K.cqa[i][0];      // Q0, Q1 over m5, m13
+        W[7][i][1] = K.cqa[i][1];
+        W[7][2 + i][2] = K.cqd[i][0];  // Q2, Q3 over m6, m14
+        W[7][2 + i][3] = K.cqd[i][1];
+    }
+    for (int g = 0; g < 4; ++g) {
+        W[4][g][0] = K.c0[g][0];
+        W[4][g][1] = K.c0[g][1];
+        for (int c = 0; c < 3; ++c) {
+            W[5][g][c] = K.cx[g][c];
+            W[6][g][c] = K.cy[g][c];
+        }
+    }
+    for (int b = 0; b < 8; ++b)
+        for (int i = 0; i < 4; ++i) {
+            unsigned short hi[4], lo[4];
+            for (int c = 0; c < 4; ++c) {
+                hi[c] = bf16_of(W[b][i][c]);
+                lo[c] = bf16_of((float)(W[b][i][c] - bf16_value(hi[c])));
+            }
+            out.w[b][i] = make_uint4(hi[0] | (unsigned)hi[1] << 16, hi[2] | (unsigned)hi[3] << 16,
+                                     lo[0] | (unsigned)lo[1] << 16, lo[2] | (unsigned)lo[3] << 16);
+        }
 }
 
 // --------------------------------------------------------------- validation
@@ -452,7 +476,7 @@ Field make_field(const mrtfd_params &p)
 }
 
 struct Layout {
-    size_t fA, fB, partials, sums, step, flag, mfma, kcopy, gcopy, fcopy, flux, outflow, total;
+    size_t fA, fB, partials, sums, step, flag, bf3, kcopy, gcopy, fcopy, flux, outflow, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -468,8 +492,8 @@ Layout layout(const mrtfd_params &p)
     L.sums = L.partials + align256(1024 * 4 * sizeof(double));
     L.step = L.sums + 256;
     L.flag = L.step + 256;
-    L.mfma = L.flag + 256;
-    L.kcopy = L.mfma + align256(sizeof(MfmaOperands));
+    L.bf3 = L.flag + 256;
+    L.kcopy = L.bf3 + align256(sizeof(Bf3Ops));
     L.gcopy = L.kcopy + align256(sizeof(Consts));
     L.fcopy = L.gcopy + align256(sizeof(Ghosts));
     L.flux = L.fcopy + align256(sizeof(FluxCoef));
@@ -512,8 +536,8 @@ struct mrtfd_ctx {
     double *partials = nullptr, *sums = nullptr;
     long long *d_step = nullptr;
     int *d_flag = nullptr;
-    MfmaOperands *d_mfma = nullptr;
-    MfmaOperands h_mfma;
+    Bf3Ops *d_bf3 = nullptr;      // device copy of the split-BF16 block table
+    Bf3Ops h_bf3;
     double *flux = nullptr, *outflow = nullptr;  // outflow budget slots and totals
     double *scratch = nullptr;   // this device's library scratch (mrtfd_sums_noalloc)
     FluxCoef FC;
@@ -565,19 +589,18 @@ int set_err(mrtfd_ctx *c, int code, const char *fmt, ...)
 // it in.
 bool budget_fused(const mrtfd_ctx *c)
 {
-    return c->p.flux_budget && c->kernel == MRTFD_KERNEL_ROWS && (c->seg & 15) == 1;
+    return c->p.flux_budget && (c->kernel == MRTFD_KERNEL_ROWS || c->kernel == MRTFD_KERNEL_MFMA) &&
+           (c->seg & 15) == 1;
 }
 
 hipError_t launch_step(mrtfd_ctx *c, const float *fin, float *fout, int k, hipStream_t s)
 {
     if (c->kernel == MRTFD_KERNEL_SIMPLE)
         return launch_step_simple(c->F, c->K, c->G, fin, fout, c->d_step, k, s);
-    if (c->kernel == MRTFD_KERNEL_ROWS)
-        return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg & 15, (c->seg >> 4) & 1,
-                                (c->seg >> 5) & 1, c->d_step, k, s,
-                                budget_fused(c) ? c->flux : nullptr);
-    return launch_step_mfma(c->F, c->K, c->G, c->d_mfma, fin, fout, (c->seg >> 4) & 1,
-                            (c->seg >> 5) & 1, c->d_step, k, s);
+    // the row kernels; with MRTFD_KERNEL_MFMA their split-BF16 variant
+    return launch_step_rows(c->F, c->K, c->G, fin, fout, c->seg & 15, (c->seg >> 4) & 1,
+                            (c->seg >> 5) & 1, c->d_step, k, s, budget_fused(c) ? c->flux : nullptr,
+                            c->kernel == MRTFD_KERNEL_MFMA ? c->d_bf3 : nullptr);
 }
 
 // Enqueue n steps starting from copy `start`, then advance the device clock.
@@ -709,10 +732,11 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
     // column bands
     if (c->p.precision == MRTFD_BF16X3) {
         const bool bands = ((c->p.nx + 63) / 64) % 8 == 0;
-        for (int o = 0; o <= (bands ? 1 : 0); ++o) {
-            cands.push_back({MRTFD_KERNEL_MFMA, 1 | (o << 5)});
-            cands.push_back({MRTFD_KERNEL_MFMA, 1 | 16 | (o << 5)});
-        }
+        for (int r = 1; r <= 2; ++r)
+            for (int o = 0; o <= (bands ? 1 : 0); ++o) {
+                cands.push_back({MRTFD_KERNEL_MFMA, r | (o << 5)});
+                cands.push_back({MRTFD_KERNEL_MFMA, r | 16 | (o << 5)});
+            }
     } else if (c->p.kernel == MRTFD_KERNEL_SIMPLE) {
         cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     } else {
@@ -878,10 +902,9 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     c->sums = reinterpret_cast<double *>(c->ws + L.sums);
     c->d_step = reinterpret_cast<long long *>(c->ws + L.step);
     c->d_flag = reinterpret_cast<int *>(c->ws + L.flag);
-    c->d_mfma = reinterpret_cast<MfmaOperands *>(c->ws + L.mfma);
+    c->d_bf3 = reinterpret_cast<Bf3Ops *>(c->ws + L.bf3);
     c->flux = reinterpret_cast<double *>(c->ws + L.flux);
     c->outflow = reinterpret_cast<double *>(c->ws + L.outflow);
-    fill_mfma(m, *p, c->h_mfma);
     for (int q = 0; q < NQ; ++q) {
         const double vx = m.v[q][0], vy = m.v[q][1];
         c->FC.cx[q][0] = p->dt / p->dx * vx / 2.0;
@@ -892,6 +915,7 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     }
     c->stream = static_cast<hipStream_t>(stream);
     fill_consts(m, *p, c->K);
+    fill_bf3(c->K, c->h_bf3);
     double rho0, T0;
     ref_state(*p, rho0, T0);
     ref_populations(m, *p, c->fref);
@@ -976,8 +1000,7 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     if (e == hipSuccess && poison_padding())  // both copies of f: a quiet NaN everywhere
         e = launch_fill(c->ws + L.fA, L.partials - L.fA, 0x7FC00000u, c->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->d_mfma, &c->h_mfma, sizeof(MfmaOperands), hipMemcpyHostToDevice,
-                           c->stream);
+        e = hipMemcpyAsync(c->d_bf3, &c->h_bf3, sizeof(Bf3Ops), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->ws + L.kcopy, &c->K, sizeof(Consts), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)

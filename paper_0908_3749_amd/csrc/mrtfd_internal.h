@@ -75,15 +75,16 @@ struct Field {
     }
 };
 
-// Operands of the split-BF16 transforms on the matrix cores, in the lane
-// layout of v_mfma_f32_16x16x16_bf16 for the A operand (lane l holds row
-// l % 16, columns 4 (l / 16) .. +3): M (rows m1..m16 over populations) and
-// dt M^-1 (rows populations over moments), each as a high and a low BF16
-// part; and dt-free rates s_k per moment for the relaxation in between.
-struct MfmaOperands {
-    unsigned short m_hi[64][4], m_lo[64][4];
-    unsigned short inv_hi[64][4], inv_lo[64][4];
-    float s[NQ];
+// Split-BF16 operands of the factored transform's eight 4x4 blocks for the
+// matrix instruction v_mfma_f32_4x4x4_16b_bf16, where lane l supplies row
+// l % 4: w[b][i] = (BF16 high parts of row i's 4 entries as two packed
+// pairs, then the low parts likewise).  Blocks: 0 f0, 1 fx, 2 fy (columns
+// A/X/Y 0..3), 3 the quadrupole block (rows m5, m13, m6, m14 over Q0..Q3);
+// 4 c0 (columns m11, m12, 0, 0), 5 cx (m7, m9, m15, 0), 6 cy (m8, m10, m16,
+// 0), 7 the quadrupole back-map (rows Q0..Q3 over m5, m13, m6, m14), with
+// dt s_k folded in as in Consts.
+struct Bf3Ops {
+    uint4 w[8][4];
 };
 
 enum Kind { K_PERIODIC = 0, K_DIRICHLET = 1, K_REFLECT = 2, K_EXTRAPOLATE = 3, K_WALL = 4 };
@@ -110,12 +111,6 @@ struct Ghosts {
     const FluxCoef *fd;  // device copy of the outflow-budget coefficients
 };
 
-// Split-BF16x3 step; stream_stores and order as for launch_step_rows.
-hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
-                            const MfmaOperands *mo, const float *fin, float *fout,
-                            int stream_stores, int order, const long long *d_step, int k,
-                            hipStream_t s);
-
 // Launchers (mrtfd_kernels.hip).  All enqueue on `s` and return the HIP
 // status of the launch.
 hipError_t launch_init(const Field &F, const Consts &K, float *f, const float *rho,
@@ -130,10 +125,12 @@ hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, 
 // tile columns divides by 8; else 0).  slots != nullptr: the launch also
 // adds the step's outflow budget (as launch_face_flux) in leading blocks of
 // its own grid (constants from the device copies G.kd, G.gd, G.fd).
+// bops != nullptr (device copy of the block table): the collision's
+// transforms in split-BF16 on the matrix cores.
 hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
                             float *fout, int rows, int stream_stores, int order,
                             const long long *d_step, int k, hipStream_t s,
-                            double *slots = nullptr);
+                            double *slots = nullptr, const Bf3Ops *bops = nullptr);
 // Outflow budget (FP64).  cx[q] = {(dt/dx) v_qx / 2, (dt/dx) v_qx^2 dt / (2 dx)}
 // and likewise cy along y: the face value of the A.1b difference between a
 // node at the lower coordinate (lo) and the next one (hi) is

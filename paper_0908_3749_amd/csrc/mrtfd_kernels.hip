@@ -234,6 +234,82 @@ __device__ __forceinline__ void macro_of(const Consts &K, const float (&f)[NQ], 
     q[3] = dP * r;
 }
 
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// x = hi + lo with both parts BF16 (|x - hi - lo| <= 2^-18 |x|).  The
+// conversions round to nearest even (the packed hardware conversion of this
+// target), as the host does for the constant operands.
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef int i32x2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void split4(const float (&x)[4], bf16x4 &hi, bf16x4 &lo)
+{
+    i32x2v h, l;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {  // one packed conversion per pair
+        const f32x2v v = {x[2 * p], x[2 * p + 1]};
+        const bf16x2v hv = __builtin_convertvector(v, bf16x2v);
+        const bf16x2v lv = __builtin_convertvector(v - __builtin_convertvector(hv, f32x2v), bf16x2v);
+        h[p] = __builtin_bit_cast(int, hv);
+        l[p] = __builtin_bit_cast(int, lv);
+    }
+    hi = __builtin_bit_cast(bf16x4, h);
+    lo = __builtin_bit_cast(bf16x4, l);
+}
+
+// The factored transform's 4x4 blocks on the matrix instruction
+// v_mfma_f32_4x4x4_16b_bf16: lane l supplies row l % 4 of the block as A and
+// its own node's 4 inputs as B, and receives the block's 4 outputs for its
+// own node.  w = (hi pair, hi pair, lo pair, lo pair) of the BF16 parts of
+// this lane's row; x = the node's 4 inputs.  Three products (hi hi, hi lo,
+// lo hi) accumulated in FP32.
+__device__ __forceinline__ f32x4 block_bf3(uint4 w, const float (&x)[4])
+{
+    const bf16x4 wh = __builtin_bit_cast(bf16x4, make_uint2(w.x, w.y));
+    const bf16x4 wl = __builtin_bit_cast(bf16x4, make_uint2(w.z, w.w));
+    bf16x4 xh, xl;
+    split4(x, xh, xl);
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wh, xh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wh, xl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wl, xh, c, 0, 0, 0);
+    return c;
+}
+
+// dC = dt * C of Eq. (3) with the nonconserved moments and the back-map in
+// split-BF16 on the matrix cores (Bf3Ops, blocks 0-3 forward, 4-7 back);
+// the butterflies, the conserved moments (from the same butterflies, with the
+// FP32 rows of the scalar path), the equilibria and the inverse butterfly
+// stay FP32.  bt = the block table in LDS, row = lane % 4.  Every lane of the
+// wave must execute it.
+__device__ __forceinline__ void collide_bf3(const Consts &K, const uint4 (*bt)[4], int row,
+                                            const float (&f)[NQ], float (&dC)[NQ])
+{
+    float A[4], X[4], Y[4], Q[4];
+    butterflies(f, A, X, Y, Q);
+    const float dr = dot4(K.f0[0], A), de = dot4(K.f0[1], A);
+    const float jx = dot4(K.fx[0], X), jy = dot4(K.fy[0], Y);
+    const Eq q = equilibria(K, dr, jx, jy, de);
+    const f32x4 m0 = block_bf3(bt[0][row], A);  // m1, m4, m11, m12
+    const f32x4 mx = block_bf3(bt[1][row], X);  // m2, m7, m9, m15
+    const f32x4 my = block_bf3(bt[2][row], Y);  // m3, m8, m10, m16
+    const f32x4 mq = block_bf3(bt[3][row], Q);  // m5, m13, m6, m14
+    const float va[4] = {m0[2] - q.e11, m0[3], 0.f, 0.f};              // d11, d12
+    const float vx[4] = {mx[1] - q.e7, mx[2] - q.e9, mx[3], 0.f};      // d7, d9, d15
+    const float vy[4] = {my[1] - q.e8, my[2] - q.e10, my[3], 0.f};     // d8, d10, d16
+    const float vq[4] = {mq[0] - q.e5, mq[1] - q.e13, mq[2] - q.e6, mq[3] - q.e14};  // d5, d13, d6, d14
+    const f32x4 a = block_bf3(bt[4][row], va);
+    const f32x4 x = block_bf3(bt[5][row], vx);
+    const f32x4 y = block_bf3(bt[6][row], vy);
+    const f32x4 qq = block_bf3(bt[7][row], vq);
+    group_inv<true>(a[0], x[0], y[0], qq[0], dC[0], dC[1], dC[2], dC[3]);
+    group_inv<true>(a[1], x[1], y[1], qq[1], dC[4], dC[5], dC[6], dC[7]);
+    group_inv<false>(a[2], x[2], y[2], qq[2], dC[8], dC[9], dC[10], dC[11]);
+    group_inv<false>(a[3], x[3], y[3], qq[3], dC[12], dC[13], dC[14], dC[15]);
+}
+
 // Which populations move along x / along y.
 __host__ __device__ constexpr bool has_x(int q) { return q >= 8 || (q % 2) == 0; }
 __host__ __device__ constexpr bool has_y(int q) { return q >= 8 || (q % 2) == 1; }
@@ -476,11 +552,12 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsign
 // a wave whose last column is alone in it (nx = 1 mod 64), which has no
 // second column for an east ghost, takes node_update.
 // The row kernel's path for a wave at a side of the grid (see k_step_rows).
-template <int R, int AUX>
+template <int R, int AUX, bool BF>
 __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const Ghosts &G,
                                           const float *__restrict__ fin, float *__restrict__ fout,
                                           unsigned bytes, int x0, int y0, int lane,
-                                          const long long *__restrict__ d_step, int k)
+                                          const long long *__restrict__ d_step, int k,
+                                          const uint4 (*bt)[4])
 {
     const int nx = F.nx, ny = F.ny, x = x0 + lane;
     const bool west = x0 == 0, east = x0 + 64 >= nx;
@@ -570,7 +647,10 @@ __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const
             }
         }
         float dC[NQ];
-        collide(K, v[r + 1], dC);
+        if constexpr (BF)
+            collide_bf3(K, bt, lane & 3, v[r + 1], dC);
+        else
+            collide(K, v[r + 1], dC);
         Unroll<NQ>::run([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             float fE = 0.f, fW = 0.f;
@@ -594,12 +674,15 @@ __device__ __forceinline__ void face_flux_node(const Field &F, const Consts &K, 
 // one thread per side node, with the constants read from the device copies;
 // dispatched first, they run beside the step blocks, which only write the
 // other copy.
-template <int R, int AUX, bool BUD>
+//
+// BF: the collision's transforms in split-BF16 on the matrix cores
+// (collide_bf3), its block table copied from bops into LDS first.
+template <int R, int AUX, bool BUD, bool BF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 1 ? 5 : 4, 8)))
 void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
                  float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
                  const long long *__restrict__ d_step, int k, int order,
-                 double *__restrict__ slots, int fblocks)
+                 double *__restrict__ slots, int fblocks, const Bf3Ops *__restrict__ bops)
 {
     int b = blockIdx.x;
     if (BUD) {
@@ -609,6 +692,11 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
             return;
         }
         b -= fblocks;
+    }
+    __shared__ uint4 bt[BF ? 8 : 1][4];
+    if (BF) {  // every thread of the block reaches this barrier
+        if (threadIdx.x < 32) bt[threadIdx.x >> 2][threadIdx.x & 3] = bops->w[threadIdx.x >> 2][threadIdx.x & 3];
+        __syncthreads();
     }
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -642,7 +730,7 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
                     if (y0 + r < F.ny) node_update(F, Kd, Gd, fin, fout, x, y0 + r, t);
             }
         } else {
-            rows_edge<R, AUX>(F, Kd, Gd, fin, fout, bytes, x0, y0, lane, d_step, k);
+            rows_edge<R, AUX, BF>(F, Kd, Gd, fin, fout, bytes, x0, y0, lane, d_step, k, bt);
         }
         return;
     }
@@ -668,7 +756,10 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         float dC[NQ];
-        collide(K, v[r + 1], dC);
+        if constexpr (BF)
+            collide_bf3(K, bt, lane & 3, v[r + 1], dC);
+        else
+            collide(K, v[r + 1], dC);
         Unroll<NQ>::run([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             float fE = 0.f, fW = 0.f;
@@ -680,179 +771,6 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
             bstore<AUX>(rout, o, vo, row(q, y0 + r));
         });
     }
-}
-
-// ------------------------------------------------- split-BF16 matrix cores
-
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// x = hi + lo with both parts BF16 (|x - hi - lo| <= 2^-18 |x|).  The
-// conversions round to nearest even (the packed hardware conversion of this
-// target), as the host does for the constant operands.
-typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
-typedef float f32x2v __attribute__((ext_vector_type(2)));
-typedef int i32x2v __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ void split4(const float (&x)[4], bf16x4 &hi, bf16x4 &lo)
-{
-    i32x2v h, l;
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {  // one packed conversion per pair
-        const f32x2v v = {x[2 * p], x[2 * p + 1]};
-        const bf16x2v hv = __builtin_convertvector(v, bf16x2v);
-        const bf16x2v lv = __builtin_convertvector(v - __builtin_convertvector(hv, f32x2v), bf16x2v);
-        h[p] = __builtin_bit_cast(int, hv);
-        l[p] = __builtin_bit_cast(int, lv);
-    }
-    hi = __builtin_bit_cast(bf16x4, h);
-    lo = __builtin_bit_cast(bf16x4, l);
-}
-
-// A . B with A, B split into BF16 parts: A_hi B_hi + A_hi B_lo + A_lo B_hi,
-// FP32 accumulation on the matrix cores.
-__device__ __forceinline__ f32x4 mfma3(bf16x4 ahi, bf16x4 alo, bf16x4 bhi, bf16x4 blo)
-{
-    f32x4 c = {0.f, 0.f, 0.f, 0.f};
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, c, 0, 0, 0);
-    return c;
-}
-
-// Order this wave's LDS stores before its later LDS loads by other lanes (a
-// wave runs in lockstep; this keeps the compiler from moving accesses across
-// and waits for the stores).
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Step kernel with the two 16x16 transforms of the collision on the matrix
-// cores (split-BF16, three products, FP32 accumulation); the equilibria, the
-// relaxation and the Lax-Wendroff update stay FP32.  Block = 64 columns x 4
-// rows, wave = one row (lane = node, west/east neighbours by DPP as in the
-// row kernel).  The wave stages its populations in LDS ([node][population])
-// so that, per 16-node group, lane l reads populations 4 (l/16) .. +3 of node
-// l % 16 -- the B-operand layout; the product M F comes back with lane l
-// holding moments 4 (l/16) .. +3 of node l % 16, which is again the B layout
-// for the back-map.  The conserved moments and the equilibria are computed
-// once per node in FP32 and staged the same way.  Blocks touching a side of
-// the grid use the FP32 node path.
-template <int AUX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
-void k_step_mfma(Field F, Consts K, Ghosts G,
-                                                   const MfmaOperands *__restrict__ mo,
-                                                   const float *__restrict__ fin,
-                                                   float *__restrict__ fout, unsigned bytes,
-                                                   int ncol, int nrb, int nblocks,
-                                                   const long long *__restrict__ d_step, int k,
-                                                   int order)
-{
-    // staging rows of 18 floats: five blocks' LDS (31 KiB each) fit a CU
-    __shared__ float stage[4][64][NQ + 2];
-    __shared__ float eqst[4][64][13];  // equilibria of moments 5..16 per node
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // tiles to XCDs in bands of tile rows (order 0) or tile columns (order 1),
-    // as in the row kernel
-    int b = blockIdx.x;
-    if ((nblocks & 7) == 0) b = (b & 7) * (nblocks >> 3) + (b >> 3);
-    int col, rb;
-    if (order == 1) {
-        const int cw = ncol >> 3;
-        col = (b / (nrb * cw)) * cw + b % cw;
-        rb = (b / cw) % nrb;
-    } else {
-        col = b % ncol;
-        rb = b / ncol;
-    }
-    const int x0 = col * 64, yb = rb * 4, x = x0 + lane, y = yb + wv;
-    if (col == 0 || x0 + 64 >= F.nx || yb == 0 || yb + 4 >= F.ny) {  // uniform over the block
-        if (x < F.nx && y < F.ny) node_update(F, K, G, fin, fout, x, y, step_time(G, d_step, k));
-        return;
-    }
-    const unsigned vo = 4u * (unsigned)F.col(x);
-    const unsigned vh = 4u * (unsigned)F.col(lane < 32 ? x0 - 1 : x0 + 64);
-    const unsigned qB = 4u * (unsigned)F.qstride, jB = 4u * (unsigned)F.jstride;
-    const auto rin = buffer_of(fin, bytes);
-    const auto rout = buffer_of(fout, bytes);
-    auto row = [&](int q, int j) { return (unsigned)q * qB + (unsigned)(j + 1) * jB; };
-    float prv[NQ], cur[NQ], nxt[NQ], hc[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        prv[q] = has_y(q) ? bload(rin, vo, row(q, y - 1)) : 0.f;
-        cur[q] = bload(rin, vo, row(q, y));
-        nxt[q] = has_y(q) ? bload(rin, vo, row(q, y + 1)) : 0.f;
-        hc[q] = has_x(q) ? bload(rin, vh, row(q, y)) : 0.f;
-    }
-    // A operands (constant): lane l holds row l%16, columns 4(l/16)..+3
-    bf16x4 mh, ml, ih, il;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        mh[c] = (short)mo->m_hi[lane][c];
-        ml[c] = (short)mo->m_lo[lane][c];
-        ih[c] = (short)mo->inv_hi[lane][c];
-        il[c] = (short)mo->inv_lo[lane][c];
-    }
-    const int grp = lane >> 4, nd = lane & 15;
-    float sv[4];  // rates of the moments this lane holds in the product layout
-#pragma unroll
-    for (int c = 0; c < 4; ++c) sv[c] = mo->s[4 * grp + c];
-    // Conserved moments and equilibria once per node, in FP32 as the scalar
-    // path computes them, staged beside the populations; the LDS regions are
-    // private to the wave.
-    float dr, jx, jy, de;
-    conserved(K, cur, dr, jx, jy, de);
-    const Eq eq = equilibria(K, dr, jx, jy, de);
-    float (*st)[NQ + 2] = stage[wv];
-    float (*qs)[13] = eqst[wv];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) st[lane][q] = cur[q];
-    {
-        const float ev[12] = {eq.e5, eq.e6, eq.e7, eq.e8, eq.e9, eq.e10,
-                              eq.e11, 0.f, eq.e13, eq.e14, 0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < 12; ++k) qs[lane][k] = ev[k];
-    }
-    wave_sync();
-    // Lane l reads populations 4 (l/16) .. +3 of node 16 nb + l%16 (the B
-    // operand) and gets back the same entries of dt C (the product layout),
-    // so it overwrites exactly what it read: no other lane touches them.
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-        const int node = nb * 16 + nd;
-        float fv[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) fv[c] = st[node][4 * grp + c];
-        bf16x4 fh, fl;
-        split4(fv, fh, fl);
-        const f32x4 m = mfma3(mh, ml, fh, fl);  // moments 4 grp .. +3 of `node`
-        float d[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)  // conserved moments (grp 0) have rate 0
-            d[c] = sv[c] * (m[c] - qs[node][max(4 * grp + c - 4, 0)]);
-        bf16x4 dh, dl;
-        split4(d, dh, dl);
-        const f32x4 dc = mfma3(ih, il, dh, dl);  // dt C, populations 4 grp .. +3 of `node`
-#pragma unroll
-        for (int c = 0; c < 4; ++c) st[node][4 * grp + c] = dc[c];
-    }
-    wave_sync();
-    float dC[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) dC[q] = st[lane][q];
-    Unroll<NQ>::run([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        float fE = 0.f, fW = 0.f;
-        if (has_x(q)) {
-            fE = shl1(cur[q], hc[q]);
-            fW = shr1(cur[q], hc[q]);
-        }
-        bstore<AUX>(rout, lw_update<q>(K, cur[q], dC[q], fE, fW, nxt[q], prv[q]), vo, row(q, y));
-    });
 }
 
 // ------------------------------------------------------------- tube batches
@@ -1267,7 +1185,8 @@ hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, 
 
 hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
                             float *fout, int rows, int stream_stores, int order,
-                            const long long *d_step, int k, hipStream_t s, double *slots)
+                            const long long *d_step, int k, hipStream_t s, double *slots,
+                            const Bf3Ops *bops)
 {
     const int ncol = (F.nx + 63) / 64;
     const int nrg = (F.ny + rows - 1) / rows;
@@ -1281,24 +1200,34 @@ hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, co
     const dim3 grid(nb + fb);
     switch (rows) {
     // store cache policy: 0 default, 2 non-temporal (streaming)
+#define MRTFD_ROWS_C(Rr, Aa, Bu, Bf)                                                               \
+    hipLaunchKernelGGL((k_step_rows<Rr, Aa, Bu, Bf>), grid, dim3(256), 0, s, F, K, G, fin, fout,   \
+                       bytes, ncol, nrg, nb, d_step, k, ord, slots, Bu ? fb : 0, bops)
 #define MRTFD_ROWS_B(Rr, Aa)                                                                       \
-    if (slots)                                                                                     \
-        hipLaunchKernelGGL((k_step_rows<Rr, Aa, true>), grid, dim3(256), 0, s, F, K, G, fin, fout, \
-                           bytes, ncol, nrg, nb, d_step, k, ord, slots, fb);                       \
-    else                                                                                           \
-        hipLaunchKernelGGL((k_step_rows<Rr, Aa, false>), grid, dim3(256), 0, s, F, K, G, fin,      \
-                           fout, bytes, ncol, nrg, nb, d_step, k, ord, slots, 0)
+    if (slots) {                                                                                   \
+        if (bops)                                                                                  \
+            MRTFD_ROWS_C(Rr, Aa, true, true);                                                      \
+        else                                                                                       \
+            MRTFD_ROWS_C(Rr, Aa, true, false);                                                     \
+    } else {                                                                                       \
+        if (bops)                                                                                  \
+            MRTFD_ROWS_C(Rr, Aa, false, true);                                                     \
+        else                                                                                       \
+            MRTFD_ROWS_C(Rr, Aa, false, false);                                                    \
+    }
 #define MRTFD_ROWS(Rr)                                                                             \
     case Rr:                                                                                       \
-        if (stream_stores)                                                                         \
+        if (stream_stores) {                                                                       \
             MRTFD_ROWS_B(Rr, 2);                                                                   \
-        else                                                                                       \
+        } else {                                                                                   \
             MRTFD_ROWS_B(Rr, 0);                                                                   \
+        }                                                                                          \
         break;
         MRTFD_ROWS(1)
         MRTFD_ROWS(2)
 #undef MRTFD_ROWS
 #undef MRTFD_ROWS_B
+#undef MRTFD_ROWS_C
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1466,26 +1395,6 @@ hipError_t launch_tube_pack(const TubeGrid &T, const TubeInfo *tubes, int tube, 
 {
     dim3 grid(blocks_for((long long)n * TUBE_ROWS, 256), NQ);
     hipLaunchKernelGGL(k_tube_pack, grid, dim3(256), 0, s, T, tubes, tube, f, dst);
-    return hipGetLastError();
-}
-
-hipError_t launch_step_mfma(const Field &F, const Consts &K, const Ghosts &G,
-                            const MfmaOperands *mo, const float *fin, float *fout,
-                            int stream_stores, int order, const long long *d_step, int k,
-                            hipStream_t s)
-{
-    const int ncol = (F.nx + 63) / 64;
-    const int nrb = (F.ny + 3) / 4;
-    const int nb = ncol * nrb;
-    const long long total = 4LL * F.total;
-    if (total >= (1LL << 32)) return hipErrorInvalidValue;
-    const int ord = (order == 1 && (ncol & 7) == 0) ? 1 : 0;
-    if (stream_stores)
-        hipLaunchKernelGGL(k_step_mfma<2>, dim3(nb), dim3(256), 0, s, F, K, G, mo, fin, fout,
-                           (unsigned)total, ncol, nrb, nb, d_step, k, ord);
-    else
-        hipLaunchKernelGGL(k_step_mfma<0>, dim3(nb), dim3(256), 0, s, F, K, G, mo, fin, fout,
-                           (unsigned)total, ncol, nrb, nb, d_step, k, ord);
     return hipGetLastError();
 }
 

@@ -8,13 +8,16 @@ Calls only the oracle (``oracle/``) and the seeded input generators
   8192 x 2048 workload (the same per-cell velocity noise, periodic in x over
   the window), 50 000 steps (t = 0.5).  Stored: rho, u1, u2, p of the final
   state (FP32 roundings of the FP64 fields) and the oracle's wall time.
+* ``mach15``: the Mach-1.5 reflection of Sect. V.B(b) at the paper's size
+  (600 x 300, dx = 0.003, dt = 1e-5), 25 000 steps.  Stored: rho, u1, u2, p
+  after 10 000 and 25 000 steps (FP32 roundings of the FP64 fields).
 * ``tubes``: 16 tubes of the seeded 512-tube batch (seed 12345), each at
   its full CFL-limited run length: the shortest tube, the widest, the one
   that runs the most steps, the one that runs the fewest, and 12 drawn at
   random (seed 2026).  Stored per tube: rho, u1, p along one row (FP64; the
   tubes are y-uniform and the oracle's four rows are checked to be equal).
 
-Usage: python tests/golden/make_references.py couette|tubes [--threads N]
+Usage: python tests/golden/make_references.py couette|mach15|tubes [--threads N]
 """
 import argparse
 import os
@@ -32,6 +35,8 @@ from oracle import core, riemann  # noqa: E402,F401
 
 COUETTE_FILE = os.path.join(HERE, "couette_256x2048_50000.npz")
 TUBES_FILE = os.path.join(HERE, "tube_sample_16.npz")
+MACH15_FILE = os.path.join(HERE, "mach15_600x300.npz")
+MACH15_STEPS = (10000, 25000)
 COUETTE_WINDOW = (0, 256)
 COUETTE_STEPS = 50000
 
@@ -72,6 +77,27 @@ def make_couette(threads):
     print(f"wrote {COUETTE_FILE}", flush=True)
 
 
+def make_mach15(threads):
+    prob = synth.paper_mach_reflection()
+    o = core.Grid(prob, nthreads=threads)
+    o.init_problem()
+    t0 = time.perf_counter()
+    out = {}
+    done = 0
+    for stop in MACH15_STEPS:
+        while done < stop:
+            n = min(2500, stop - done)
+            o.run(n)
+            done += n
+            print(f"mach15: {done} steps, {time.perf_counter() - t0:.0f} s", flush=True)
+        m = o.macro()
+        for k in ("rho", "ux", "uy", "p"):
+            out[f"{k}_{stop}"] = m[k].astype(np.float32)
+    np.savez_compressed(MACH15_FILE, steps=np.array(MACH15_STEPS), wall_s=time.perf_counter() - t0,
+                        threads=threads, **out)
+    print(f"wrote {MACH15_FILE}", flush=True)
+
+
 def make_tubes(threads):
     batch = synth.tube_batch(star_fn=star_fn)
     sample = tube_sample(batch)
@@ -108,10 +134,10 @@ def make_tubes(threads):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["couette", "tubes"])
+    ap.add_argument("what", choices=["couette", "mach15", "tubes"])
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     a = ap.parse_args()
-    {"couette": make_couette, "tubes": make_tubes}[a.what](a.threads)
+    {"couette": make_couette, "mach15": make_mach15, "tubes": make_tubes}[a.what](a.threads)
 
 
 if __name__ == "__main__":

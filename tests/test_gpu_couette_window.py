@@ -10,9 +10,8 @@ the stored FP64 oracle run of the same window
   1e-5 on rho, u1 and p;
 * FP32: node by node within 1e-5 U on u1 and on u2 (a field that has decayed
   to the noise floor, mean |u2| ~ 4e-5, whose relative L1 says little);
-* the window puts columns 64..191 on the matrix cores: after one step those
-  nodes differ from the FP32 run and every node of the FP32-path blocks
-  (first and last 64 columns, first and last 4 rows) is identical.
+* the split-BF16x3 run really takes the matrix-core products: one step from
+  a state off equilibrium differs from the FP32 step at nearly every node.
 
 Why FP32 holds the target over 50 000 steps: the populations are stored as
 g = f - f_ref (near the gas at rest |g| is a few per cent of |f|), and each
@@ -82,22 +81,22 @@ def test_couette_window_50000_steps(gpu, stored, precision):
 
 
 def test_couette_window_runs_the_matrix_cores(gpu, stored):
-    """One step from the initial state: the interior blocks (columns 64..191,
-    rows 4..2043) run the split-BF16x3 transforms and differ from the FP32
-    step; the blocks touching a side of the window run the FP32 node path and
-    equal it bit for bit."""
+    """One step from the state after 100 FP32 steps (off the initial
+    equilibrium, so that the collision acts): the split-BF16x3 step differs
+    from the FP32 step at nearly every node of the window."""
     crop, _, _ = stored
+    g = gpu.from_problem(crop, ref=REF)
+    g.init_problem(crop)
+    g.step(100)
+    start = g.get_f_numpy()
+    g.close()
     outs = {}
     for prec in ("fp32", "bf16x3"):
         g = gpu.from_problem(crop, ref=REF, precision=prec)
-        g.init_problem(crop)
+        g.set_f(start)
         g.step(1)
         outs[prec] = g.get_f_numpy()
         g.close()
     diff = np.any(outs["bf16x3"] != outs["fp32"], axis=0)
-    inner = diff[4:-4, 64:crop.nx - 64]
-    print(f"one step: {inner.mean():.4f} of the matrix-core nodes differ from FP32")
-    assert inner.mean() > 0.9
-    edge = np.ones_like(diff)
-    edge[4:-4, 64:crop.nx - 64] = False
-    assert not np.any(diff[edge])
+    print(f"one step: {diff.mean():.4f} of the nodes differ from FP32")
+    assert diff.mean() > 0.9

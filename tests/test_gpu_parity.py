@@ -739,12 +739,13 @@ def test_couette_strip(gpu):
 
 
 def test_bf16x3_one_step_error_bound(gpu):
-    """Split-BF16 transforms on the matrix cores: each operand x = hi + lo with
-    |x - hi - lo| <= 2^-18 |x|, three products (the lo*lo term, <= 2^-18,
-    dropped), FP32 accumulation.  Per population the collision then errs by
-    at most c 2^-18 (|dt M^-1| |S| |M| |f|)_i; with c = 16 (representation of
-    both operands of both products, the dropped term, accumulation) on top of
-    the FP32 bound.  Interior nodes only (nodes next to a side use FP32)."""
+    """Split-BF16 block products on the matrix cores: each operand x = hi +
+    lo with |x - hi - lo| <= 2^-17 |x|, three products (the lo*lo term,
+    <= 2^-16, dropped), FP32 accumulation.  Per population the collision then
+    errs by at most c 2^-18 (|dt M^-1| |S| |M| |f|)_i; with c = 16
+    (representation of both operands of both block products, the dropped
+    term, accumulation) on top of the FP32 bound.  Every node runs the split
+    products (the boundary waves too); the variants agree bit for bit."""
     nx, ny = 200, 40
     f0 = synth.random_populations(nx, ny, seed=8, spread=0.3)
     prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"], None)
@@ -755,13 +756,12 @@ def test_bf16x3_one_step_error_bound(gpu):
     A = np.abs(m.Minv) * prob.dt @ np.diag(np.abs(RATES)) @ np.abs(m.M)
     scale = np.einsum("ik,kyx->iyx", A, np.abs(f0))
     bound = 16 * 2.0 ** -18 * scale + 2e-6 * np.max(np.abs(want))
-    inner = (slice(None), slice(4, ny - 4), slice(64, 128))
-    ratio = np.abs(got - want)[inner] / bound[inner]
-    print(f"bf16x3 one step: max err {np.max(np.abs(got - want)[inner]):.3e}, max err/bound {ratio.max():.3f}")
+    ratio = np.abs(got - want) / bound
+    print(f"bf16x3 one step: max err {np.max(np.abs(got - want)):.3e}, max err/bound {ratio.max():.3f}")
     assert np.all(ratio <= 1.0)
     fp32, _, _ = run_gpu(gpu, prob, f0, 1)
-    # edge blocks run the FP32 path: identical there
-    assert np.array_equal(got[:, :4, :], fp32[:, :4, :])
+    # the split products differ from the FP32 ones at nearly every node
+    assert np.mean(np.any(got != fp32, axis=0)) > 0.9
 
 
 def test_bf16x3_couette_strip(gpu):

@@ -96,9 +96,9 @@ def test_one_step_every_variant(gpu, sides):
 
 
 def test_one_step_bf16x3(gpu):
-    """The matrix-core step on stored deviations: interior nodes within the
-    split-BF16 bound 16 2^-18 (|dt M^-1| |S| |M| |g|)_i on top of the FP32
-    one (the transforms now act on g), edge blocks equal to the FP32 path."""
+    """The split-BF16 block products on stored deviations: every node within
+    the split-BF16 bound 16 2^-18 (|dt M^-1| |S| |M| |g|)_i on top of the FP32
+    one (the transforms now act on g), and different from the FP32 step."""
     nx, ny = 200, 40
     prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"], None)
     fr = f_ref(prob)[:, None, None]
@@ -120,12 +120,10 @@ def test_one_step_bf16x3(gpu):
     A = np.abs(m.Minv) * prob.dt @ np.diag(np.abs(RATES)) @ np.abs(m.M)
     scale = np.einsum("ik,kyx->iyx", A, np.abs(g0.astype(np.float64)))
     bound = 16 * 2.0 ** -18 * scale + 2e-6 * np.max(np.abs(want))
-    inner = (slice(None), slice(4, ny - 4), slice(64, 128))
     err = np.abs(got.astype(np.float64) + fr - want)
-    print(f"bf16x3 with reference: max err/bound {np.max(err[inner] / bound[inner]):.3f}")
-    assert np.all(err[inner] <= bound[inner])
-    assert np.array_equal(got[:, :4, :], fp32[:, :4, :])
-    assert not np.array_equal(got[inner], fp32[inner])
+    print(f"bf16x3 with reference: max err/bound {np.max(err / bound):.3f}")
+    assert np.all(err <= bound)
+    assert np.mean(np.any(got != fp32, axis=0)) > 0.9
 
 
 @pytest.mark.parametrize("sides", ["periodic", "wall_rest"])
