@@ -5,8 +5,8 @@ their tolerances against the FP64 oracle.
 * transform_scale: what the collision cancels down from;
 * equilibrium_scale: the rounding of the conserved moments carried through
   the equilibria (Eq. 14) and the back-map;
-* conserved_rounding: per node and step, the rounding of the conserved
-  moments themselves, and what it makes of rho, u1 and p.
+* storage_field_bounds: what the storage rounding of the populations makes
+  of rho, u1 and p after n steps (the tube-batch bounds).
 """
 import numpy as np
 
@@ -50,4 +50,32 @@ def equilibrium_scale(prob, f):
             xm[k] -= h
             J[:, k] = (core.feq_moments(*xp) - core.feq_moments(*xm)) / (2 * h)
         out = max(out, float(np.max(A @ np.abs(J) @ cerr[:, i])))
+    return out
+
+
+def storage_field_bounds(states, nsteps):
+    """Per-node error bounds on (rho, u1, p) after nsteps FP32 steps of a flow
+    made of the given macroscopic states (rho, u1, T), from the rounding of
+    the stored populations.  Each step stores population i with an error of
+    at most u/2 |f_i| (u = 2^-24; the step's increment is summed first, so
+    this last rounding is the one at the scale of f); those of different
+    steps are independent (round to nearest) and add as a random walk, sqrt(n)
+    u/2 |f_i| after n steps.  The conserved moments sum them with weights
+    (1, |v_i1|, |v_i|^2 / 2), and u1 = j1 / rho, p = e - j1^2 / (2 rho) (the
+    model's gamma = 2) carry them on:
+      d rho <= s sum_i |f_i|,  d j1 <= s sum_i |v_i1| |f_i|,
+      d e <= s sum_i |v_i|^2/2 |f_i|,  s = sqrt(n) u / 2,
+      d u1 <= (d j1 + |u1| d rho) / rho,  d p <= d e + |u1| d j1 + u1^2/2 d rho,
+    with f = f^eq of each state; the maximum over the states is returned."""
+    m = core.model()
+    vx = np.abs(m.v[:, 0])
+    v2 = 0.5 * np.sum(m.v ** 2, axis=1)
+    s = np.sqrt(float(nsteps)) * 2.0 ** -24 / 2.0
+    out = {"rho": 0.0, "ux": 0.0, "p": 0.0}
+    for rho, u, T in states:
+        f = np.abs(core.feq_velocity(rho, u, 0.0, T))
+        drho, dj, de = s * f.sum(), s * (vx * f).sum(), s * (v2 * f).sum()
+        out["rho"] = max(out["rho"], drho)
+        out["ux"] = max(out["ux"], (dj + abs(u) * drho) / rho)
+        out["p"] = max(out["p"], de + abs(u) * dj + 0.5 * u * u * drho)
     return out

@@ -1,19 +1,17 @@
 """GPU batches of independent shock tubes (temporally blocked in LDS): each
 tube equals the single-grid run of the same tube bit for bit, for every
 work-item width, steps-per-round and with or without graph replay; and the
-tubes agree with the FP64 oracle and the gamma = 2 exact Riemann solution."""
+tubes agree with stored FP64 oracle runs and the gamma = 2 exact Riemann
+solution."""
 import os
 
 import numpy as np
 import pytest
 
 import synth
-from oracle import core, metrics, riemann
+from oracle import metrics, riemann
 
 pytestmark = pytest.mark.gpu
-
-THREADS = max(1, min(16, os.cpu_count() or 1))
-
 
 def star_fn(L, R):
     W = riemann.wave_speeds(L, R)
@@ -79,46 +77,83 @@ def test_batch_run_needs_fresh_init(gpu, small_batch):
     B.close()
 
 
-def test_batch_tubes_match_oracle_and_exact(gpu):
-    """Two seeded tubes at their full CFL-limited run length: FP32 batch vs
-    FP64 oracle and the gamma = 2 exact solution.  Shocks (the criterion for
-    discontinuous flow): each shock's density midpoint within one cell of the
-    oracle's and within three cells of the exact position.  Fields: these
-    tubes reach T = 70, where populations are ~20 rho and every FP32 step
-    rounds at ~1e-6 of them; over thousands of steps the relative L1 error is
-    held to <= 2e-3 (observed 1e-4 .. 5e-4)."""
-    batch = synth.tube_batch(ntubes=2, nmin=300, nmax=500, seed=2024, star_fn=star_fn)
-    B = gpu.TubeBatch.from_description(batch)
+def test_batch_tubes_match_stored_oracle(gpu):
+    """The 512-tube batch bench.py times, at full length, against stored FP64
+    oracle runs of 16 of its tubes (tests/golden/make_references.py: the
+    shortest, the widest, the one that runs longest, the one that runs
+    fewest steps, 12 at random):
+
+    * rho, u1, p along every row within the relative L1 bound of the storage
+      rounding (tests/rounding.py, storage_field_bounds: sqrt(n) u/2 of the
+      populations' magnitudes, on the tube's end and star states);
+    * every shock whose density jump is at least a tenth of the pre-shock
+      density within one cell of the oracle's and within three of the exact
+      position.  Weaker shocks are left to the field bound: the midpoint of
+      a jump of a few per cent moves by the field error over the jump (in
+      hot gas, where the model's equilibrium populations sum to ~0.7 T^2
+      times rho and FP32 rounds rho by that much more, a 6 % jump moved by
+      3 cells); even the FP64 run places them up to 5 cells from the exact
+      position."""
+    from tests.rounding import storage_field_bounds
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "tube_sample_16.npz"))
+    batch = synth.tube_batch(star_fn=star_fn)
+    B = gpu.TubeBatch.from_description(batch, use_graph=True)
     B.init()
     B.run()
-    for k, t in enumerate(batch["tubes"]):
+    for i, k in enumerate(ref["index"].tolist()):
+        n = int(ref["n"][i])
+        t = batch["tubes"][k]
         prob = synth.tube_problem(batch, k)
+        assert (n, prob.nsteps) == (prob.nx, int(ref["steps"][i]))
         got = B.macro_numpy(k)
-        o = core.Grid(prob, nthreads=THREADS)
-        o.init_problem()
-        o.run(prob.nsteps)
-        want = o.macro()
-        errs = {q: metrics.rel_l1(got[q], want[q]) for q in ("rho", "ux", "p")}
-        print(f"tube {k} n={t['n']} steps={t['steps']}: rel L1 {errs}")
-        for q, v in errs.items():
-            assert v <= 2e-3, (k, q, v)
-        L, R = t["left"], t["right"]
-        W = riemann.wave_speeds(L, R)
+        want = {q: ref[q][i, :n] for q in ("rho", "ux", "p")}
+        W = riemann.wave_speeds(t["left"], t["right"])
+        (rl, ul, pl), (rr, ur, pr) = t["left"], t["right"]
+        states = [(rl, ul, pl / rl), (rr, ur, pr / rr),
+                  (W["rho_star_left"], W["ustar"], W["pstar"] / W["rho_star_left"]),
+                  (W["rho_star_right"], W["ustar"], W["pstar"] / W["rho_star_right"])]
+        dq = storage_field_bounds(states, prob.nsteps)
+        for q in ("rho", "ux", "p"):
+            bound = dq[q] * n / np.sum(np.abs(want[q]))
+            for row in range(4):
+                err = metrics.rel_l1(got[q][row], want[q])
+                assert err <= bound, (k, q, row, err, bound)
+        print(f"tube {k}: n {n}, steps {prob.nsteps}, rel L1 "
+              f"{ {q: float(f'{metrics.rel_l1(got[q][0], want[q]):.2e}') for q in want} }", flush=True)
         x = prob.x_centres()
-        for side in ("left", "right"):
+        for side, far in (("left", rl), ("right", rr)):
             if not W[side + "_shock"]:
                 continue
-            xs = prob.meta["x0"] + W[side + "_head"] * prob.t_end
-            pre = L[0] if side == "left" else R[0]
             post = W["rho_star_" + side]
-            lvl = 0.5 * (pre + post)
+            xs = prob.meta["x0"] + W[side + "_head"] * prob.t_end
+            lvl = 0.5 * (far + post)
             lo, hi = xs - 6 * prob.dx, xs + 6 * prob.dx
-            a = metrics.crossing(x, want["rho"][1], lvl, lo=lo, hi=hi)
-            b = metrics.crossing(x, got["rho"][1], lvl, lo=lo, hi=hi)
+            a = metrics.crossing(x, want["rho"], lvl, lo=lo, hi=hi)
+            b = metrics.crossing(x, got["rho"][0], lvl, lo=lo, hi=hi)
             assert a is not None and b is not None, (k, side)
-            assert abs(a - b) <= prob.dx, (k, side, a, b)
-            assert abs(b - xs) <= 3 * prob.dx, (k, side, b, xs)
+            print(f"  {side} shock: jump {(post - far) / far:.3f}, GPU - oracle {(b - a) / prob.dx:+.4f} cells")
+            if (post - far) / far >= 0.1:
+                assert abs(a - b) <= prob.dx, (k, side, a, b)
+                assert abs(b - xs) <= 3 * prob.dx, (k, side, b, xs)
     B.close()
+
+
+def test_full_batch_stays_physical(gpu):
+    """Every tube of the 512-tube batch (the draws whose FP64 run fails at
+    the initial jump are not part of it) ends its run with rho > 0, T > 0
+    and finite values on the GPU."""
+    batch = synth.tube_batch(star_fn=star_fn)
+    B = gpu.TubeBatch.from_description(batch, use_graph=True)
+    B.init()
+    B.run()
+    bad = []
+    for k in range(len(batch["tubes"])):
+        m = B.macro_numpy(k)
+        if not (np.all(np.isfinite(m["rho"])) and np.all(np.isfinite(m["T"]))
+                and m["rho"].min() > 0 and m["T"].min() > 0):
+            bad.append(k)
+    B.close()
+    assert not bad, bad
 
 
 def test_full_batch_sampled_tubes_bitwise(gpu):
