@@ -678,7 +678,7 @@ __device__ __forceinline__ void face_flux_node(const Field &F, const Consts &K, 
 // BF: the collision's transforms in split-BF16 on the matrix cores
 // (collide_bf3), its block table copied from bops into LDS first.
 template <int R, int AUX, bool BUD, bool BF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 1 ? 5 : 4, 8)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 1 ? 5 : 3, 8)))
 void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
                  float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
                  const long long *__restrict__ d_step, int k, int order,
