@@ -73,12 +73,16 @@ extern "C" {
 /* ---- arithmetic of the moment transforms ------------------------------- */
 #define MRTFD_FP32 0  /* FP32 everywhere (FP64 only in mrtfd_sums)            */
 #define MRTFD_BF16X3 1 /* the collision's transforms (the 4x4 blocks of the
-                          factored M and M^-1) on the matrix cores, operands
-                          split into high and low BF16 parts, three products,
-                          FP32 accumulation; the butterflies, conserved
-                          moments, equilibria and stencil FP32 (a last grid
-                          column alone in its 64-column wave takes the FP32
-                          collision)                                        */
+                          factored M and M^-1) on the matrix cores in BF16
+                          parts, FP32 accumulation: M's blocks, exact in
+                          BF16 (a sqrt 2 factor of two columns moved onto
+                          the inputs), against inputs split exactly into
+                          three parts; the back-map's FP32 weights split
+                          exactly into three parts against the
+                          nonequilibrium moments split into two.  The
+                          butterflies, equilibria and stencil FP32 (a last
+                          grid column alone in its 64-column wave takes the
+                          FP32 collision)                                   */
 
 /* ---- collision operator ------------------------------------------------ */
 #define MRTFD_COLLISION_MRT 0 /* Eq. (3): M^-1 S-hat (f-hat - f-hat^eq)            */

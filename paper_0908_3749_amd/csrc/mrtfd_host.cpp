@@ -317,17 +317,21 @@ double bf16_value(unsigned short b)
     return f;
 }
 
-// Split-BF16 block table (Bf3Ops) from the FP32 constants: for each 4x4
-// block and row, the BF16 high parts (round to nearest even) and the BF16
-// roundings of the remainders, packed two per 32-bit word, element 0 low.
-void fill_bf3(const Consts &K, Bf3Ops &out)
+// Block table (Bf3Ops) from the FP32 constants.  Forward blocks 0-3: their
+// entries are small dyadic numbers, or sqrt 2 times one in the diagonal
+// groups' columns (2, 3) of fx and fy, which the table holds divided by
+// sqrt 2; each must then be exact in BF16 (false if not).  Back-map blocks
+// 4-7: each FP32 entry as three BF16 parts (round to nearest even, then the
+// remainders likewise), which add up to it exactly.
+bool fill_bf3(const Consts &K, Bf3Ops &out)
 {
-    float W[8][4][4] = {};
+    double W[8][4][4] = {};
     for (int i = 0; i < 4; ++i)
         for (int c = 0; c < 4; ++c) {
+            const double r = c >= 2 ? 1.0 / std::sqrt(2.0) : 1.0;
             W[0][i][c] = K.f0[i][c];
-            W[1][i][c] = K.fx[i][c];
-            W[2][i][c] = K.fy[i][c];
+            W[1][i][c] = K.fx[i][c] * r;
+            W[2][i][c] = K.fy[i][c] * r;
         }
     for (int i = 0; i < 2; ++i) {
         W[3][i][0] = K.fqa[i][0];      // m5, m13 over Q0, Q1
@@ -347,16 +351,29 @@ void fill_bf3(const Consts &K, Bf3Ops &out)
             W[6][g][c] = K.cy[g][c];
         }
     }
+    std::memset(&out, 0, sizeof out);
     for (int b = 0; b < 8; ++b)
         for (int i = 0; i < 4; ++i) {
-            unsigned short hi[4], lo[4];
+            unsigned short hi[4], mid[4] = {}, lo[4] = {};
             for (int c = 0; c < 4; ++c) {
-                hi[c] = bf16_of(W[b][i][c]);
-                lo[c] = bf16_of((float)(W[b][i][c] - bf16_value(hi[c])));
+                const double w = W[b][i][c];
+                hi[c] = bf16_of((float)w);
+                if (b < 4) {
+                    // FP32 constants: exact up to their own rounding
+                    if (std::fabs(w - bf16_value(hi[c])) > 0x1p-22 * std::fabs(w)) return false;
+                    continue;
+                }
+                const float r = (float)(w - bf16_value(hi[c]));  // exact: w is an FP32 value
+                mid[c] = bf16_of(r);
+                lo[c] = bf16_of((float)(r - bf16_value(mid[c])));
+                if (bf16_value(hi[c]) + bf16_value(mid[c]) + bf16_value(lo[c]) != w) return false;
             }
             out.w[b][i] = make_uint4(hi[0] | (unsigned)hi[1] << 16, hi[2] | (unsigned)hi[3] << 16,
-                                     lo[0] | (unsigned)lo[1] << 16, lo[2] | (unsigned)lo[3] << 16);
+                                     mid[0] | (unsigned)mid[1] << 16, mid[2] | (unsigned)mid[3] << 16);
+            if (b >= 4)
+                out.w[b + 4][i] = make_uint4(lo[0] | (unsigned)lo[1] << 16, lo[2] | (unsigned)lo[3] << 16, 0u, 0u);
         }
+    return true;
 }
 
 // --------------------------------------------------------------- validation
@@ -915,7 +932,10 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     }
     c->stream = static_cast<hipStream_t>(stream);
     fill_consts(m, *p, c->K);
-    fill_bf3(c->K, c->h_bf3);
+    if (!fill_bf3(c->K, c->h_bf3) && p->precision == MRTFD_BF16X3) {
+        delete c;  // a weight that its BF16 parts do not hold exactly
+        return MRTFD_ERR_UNSUPPORTED;
+    }
     double rho0, T0;
     ref_state(*p, rho0, T0);
     ref_populations(m, *p, c->fref);

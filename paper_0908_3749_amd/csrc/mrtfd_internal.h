@@ -75,16 +75,20 @@ struct Field {
     }
 };
 
-// Split-BF16 operands of the factored transform's eight 4x4 blocks for the
+// BF16 operands of the factored transform's eight 4x4 blocks for the
 // matrix instruction v_mfma_f32_4x4x4_16b_bf16, where lane l supplies row
-// l % 4: w[b][i] = (BF16 high parts of row i's 4 entries as two packed
-// pairs, then the low parts likewise).  Blocks: 0 f0, 1 fx, 2 fy (columns
-// A/X/Y 0..3), 3 the quadrupole block (rows m5, m13, m6, m14 over Q0..Q3);
-// 4 c0 (columns m11, m12, 0, 0), 5 cx (m7, m9, m15, 0), 6 cy (m8, m10, m16,
-// 0), 7 the quadrupole back-map (rows Q0..Q3 over m5, m13, m6, m14), with
-// dt s_k folded in as in Consts.
+// l % 4; w[b][i] = row i of block b, two BF16 values per 32-bit word,
+// element 0 low.  Forward blocks: 0 f0, 1 fx, 2 fy (columns A/X/Y 0..3; the
+// diagonal groups' columns 2, 3 of fx and fy divided by sqrt 2), 3 the
+// quadrupole block (rows m5, m13, m6, m14 over Q0..Q3): every entry exact in
+// BF16, held in (.x, .y).  Back-map blocks: 4 c0 (columns m11, m12, 0, 0),
+// 5 cx (m7, m9, m15, 0), 6 cy (m8, m10, m16, 0), 7 the quadrupole back-map
+// (rows Q0..Q3 over m5, m13, m6, m14), with dt s_k folded in as in Consts:
+// each FP32 entry split exactly into three BF16 parts, the high parts in
+// (.x, .y) and the middle ones in (.z, .w) of w[b], the low ones in (.x,
+// .y) of w[b + 4].
 struct Bf3Ops {
-    uint4 w[8][4];
+    uint4 w[12][4];
 };
 
 enum Kind { K_PERIODIC = 0, K_DIRICHLET = 1, K_REFLECT = 2, K_EXTRAPOLATE = 3, K_WALL = 4 };

@@ -259,51 +259,102 @@ __device__ __forceinline__ void split4(const float (&x)[4], bf16x4 &hi, bf16x4 &
     lo = __builtin_bit_cast(bf16x4, l);
 }
 
+// x = hi + mid + lo exactly, all three BF16: each remainder is exact in
+// FP32 and the last one has at most 8 significant bits.
+__device__ __forceinline__ void split4_exact(const float (&x)[4], bf16x4 &hi, bf16x4 &mid, bf16x4 &lo)
+{
+    i32x2v h, m, l;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const f32x2v v = {x[2 * p], x[2 * p + 1]};
+        const bf16x2v hv = __builtin_convertvector(v, bf16x2v);
+        const f32x2v r = v - __builtin_convertvector(hv, f32x2v);
+        const bf16x2v mv = __builtin_convertvector(r, bf16x2v);
+        const bf16x2v lv = __builtin_convertvector(r - __builtin_convertvector(mv, f32x2v), bf16x2v);
+        h[p] = __builtin_bit_cast(int, hv);
+        m[p] = __builtin_bit_cast(int, mv);
+        l[p] = __builtin_bit_cast(int, lv);
+    }
+    hi = __builtin_bit_cast(bf16x4, h);
+    mid = __builtin_bit_cast(bf16x4, m);
+    lo = __builtin_bit_cast(bf16x4, l);
+}
+
 // The factored transform's 4x4 blocks on the matrix instruction
 // v_mfma_f32_4x4x4_16b_bf16: lane l supplies row l % 4 of the block as A and
 // its own node's 4 inputs as B, and receives the block's 4 outputs for its
-// own node.  w = (hi pair, hi pair, lo pair, lo pair) of the BF16 parts of
-// this lane's row; x = the node's 4 inputs.  Three products (hi hi, hi lo,
-// lo hi) accumulated in FP32.
-__device__ __forceinline__ f32x4 block_bf3(uint4 w, const float (&x)[4])
+// own node; FP32 accumulation.
+//
+// Forward blocks (exact BF16 weights, w.x and w.y = this lane's row packed):
+// the inputs split exactly in three parts, smallest products first, so that
+// the result is the FP32 dot product up to the accumulation's rounding.
+__device__ __forceinline__ f32x4 block_fwd(uint4 w, const float (&x)[4])
 {
     const bf16x4 wh = __builtin_bit_cast(bf16x4, make_uint2(w.x, w.y));
-    const bf16x4 wl = __builtin_bit_cast(bf16x4, make_uint2(w.z, w.w));
-    bf16x4 xh, xl;
-    split4(x, xh, xl);
+    bf16x4 xh, xm, xl;
+    split4_exact(x, xh, xm, xl);
     f32x4 c = {0.f, 0.f, 0.f, 0.f};
-    c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wh, xh, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wh, xl, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wl, xh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wh, xm, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wh, xh, c, 0, 0, 0);
     return c;
 }
 
-// dC = dt * C of Eq. (3) with the nonconserved moments and the back-map in
-// split-BF16 on the matrix cores (Bf3Ops, blocks 0-3 forward, 4-7 back);
-// the butterflies, the conserved moments (from the same butterflies, with the
-// FP32 rows of the scalar path), the equilibria and the inverse butterfly
-// stay FP32.  bt = the block table in LDS, row = lane % 4.  Every lane of the
-// wave must execute it.
+// Back-map blocks (weights dt s_k M^-1, not exact in BF16): w = (hi pair,
+// hi pair, mid pair, mid pair) and w3 = (lo pair, lo pair, -, -) of this
+// lane's row, hi + mid + lo = the FP32 weight exactly, so that the products
+// carry no fixed bias of the relaxation rates; the inputs split in two.
+// Four products, smallest first; what is left out (mid and lo times the
+// inputs' low parts) and the inputs' own split remainder are about 2^-17 of
+// the result and vary from node to node.
+__device__ __forceinline__ f32x4 block_back(uint4 w, uint4 w3, const float (&x)[4])
+{
+    const bf16x4 wh = __builtin_bit_cast(bf16x4, make_uint2(w.x, w.y));
+    const bf16x4 wm = __builtin_bit_cast(bf16x4, make_uint2(w.z, w.w));
+    const bf16x4 wl = __builtin_bit_cast(bf16x4, make_uint2(w3.x, w3.y));
+    bf16x4 xh, xl;
+    split4(x, xh, xl);
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wl, xh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wm, xh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wh, xl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(wh, xh, c, 0, 0, 0);
+    return c;
+}
+
+// dC = dt * C of Eq. (3) with the moments and the back-map on the matrix
+// cores (Bf3Ops: blocks 0-3 forward, 4-7 back, 8-11 the back blocks' third
+// parts).  The forward blocks give all 16 moments, the conserved ones
+// included, to FP32 accuracy; the back-map holds its weights exactly and
+// rounds its inputs, the nonequilibrium moments, to two BF16 parts (about
+// 2^-17 of dt s_k times them).  The butterflies, the equilibria and the
+// inverse butterfly stay FP32.  bt = the block table in LDS, row = lane % 4.
+// Every lane of the wave must execute it.
 __device__ __forceinline__ void collide_bf3(const Consts &K, const uint4 (*bt)[4], int row,
                                             const float (&f)[NQ], float (&dC)[NQ])
 {
+    // the table holds the diagonal groups' columns of fx and fy divided by
+    // sqrt 2 (exact in BF16 then), so those inputs carry the factor
+    constexpr float SQRT2 = 0x1.6a09e6p+0f;
     float A[4], X[4], Y[4], Q[4];
     butterflies(f, A, X, Y, Q);
-    const float dr = dot4(K.f0[0], A), de = dot4(K.f0[1], A);
-    const float jx = dot4(K.fx[0], X), jy = dot4(K.fy[0], Y);
-    const Eq q = equilibria(K, dr, jx, jy, de);
-    const f32x4 m0 = block_bf3(bt[0][row], A);  // m1, m4, m11, m12
-    const f32x4 mx = block_bf3(bt[1][row], X);  // m2, m7, m9, m15
-    const f32x4 my = block_bf3(bt[2][row], Y);  // m3, m8, m10, m16
-    const f32x4 mq = block_bf3(bt[3][row], Q);  // m5, m13, m6, m14
+    X[2] *= SQRT2;
+    X[3] *= SQRT2;
+    Y[2] *= SQRT2;
+    Y[3] *= SQRT2;
+    const f32x4 m0 = block_fwd(bt[0][row], A);  // rho - rho0, e - e0, m11, m12
+    const f32x4 mx = block_fwd(bt[1][row], X);  // j_x, m7, m9, m15
+    const f32x4 my = block_fwd(bt[2][row], Y);  // j_y, m8, m10, m16
+    const f32x4 mq = block_fwd(bt[3][row], Q);  // m5, m13, m6, m14
+    const Eq q = equilibria(K, m0[0], mx[0], my[0], m0[1]);
     const float va[4] = {m0[2] - q.e11, m0[3], 0.f, 0.f};              // d11, d12
     const float vx[4] = {mx[1] - q.e7, mx[2] - q.e9, mx[3], 0.f};      // d7, d9, d15
     const float vy[4] = {my[1] - q.e8, my[2] - q.e10, my[3], 0.f};     // d8, d10, d16
     const float vq[4] = {mq[0] - q.e5, mq[1] - q.e13, mq[2] - q.e6, mq[3] - q.e14};  // d5, d13, d6, d14
-    const f32x4 a = block_bf3(bt[4][row], va);
-    const f32x4 x = block_bf3(bt[5][row], vx);
-    const f32x4 y = block_bf3(bt[6][row], vy);
-    const f32x4 qq = block_bf3(bt[7][row], vq);
+    const f32x4 a = block_back(bt[4][row], bt[8][row], va);
+    const f32x4 x = block_back(bt[5][row], bt[9][row], vx);
+    const f32x4 y = block_back(bt[6][row], bt[10][row], vy);
+    const f32x4 qq = block_back(bt[7][row], bt[11][row], vq);
     group_inv<true>(a[0], x[0], y[0], qq[0], dC[0], dC[1], dC[2], dC[3]);
     group_inv<true>(a[1], x[1], y[1], qq[1], dC[4], dC[5], dC[6], dC[7]);
     group_inv<false>(a[2], x[2], y[2], qq[2], dC[8], dC[9], dC[10], dC[11]);
@@ -693,9 +744,9 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
         }
         b -= fblocks;
     }
-    __shared__ uint4 bt[BF ? 8 : 1][4];
+    __shared__ uint4 bt[BF ? 12 : 1][4];
     if (BF) {  // every thread of the block reaches this barrier
-        if (threadIdx.x < 32) bt[threadIdx.x >> 2][threadIdx.x & 3] = bops->w[threadIdx.x >> 2][threadIdx.x & 3];
+        if (threadIdx.x < 48) bt[threadIdx.x >> 2][threadIdx.x & 3] = bops->w[threadIdx.x >> 2][threadIdx.x & 3];
         __syncthreads();
     }
     const int lane = threadIdx.x & 63;

@@ -220,10 +220,9 @@ def test_uniform_flow_stays_bitwise_uniform(gpu):
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_periodic_conservation_fp64_sums(gpu, precision):
     """On a periodic grid the FP64 totals of rho, j, e drift by FP32
-    round-off only -- in the split-BF16x3 mode too, whose back-map is not
-    exactly blind to the conserved moments (observed: 1e-8 .. 1e-7 of the
-    totals after 5000 steps in both modes, so no projection of the collision
-    increment is needed)."""
+    round-off only -- in the split-BF16x3 mode too, whose back-map has no
+    columns for the conserved moments, as in FP32 (observed: 1e-8 .. 1e-7
+    of the totals after 5000 steps in both modes)."""
     nx, ny = 200, 120
     ic = synth.smooth_macro(nx, ny, seed=9, du=0.3, dr=0.2)
     prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"], ic)
@@ -438,12 +437,13 @@ def test_outflow_budget(gpu, sides):
 
 
 def test_outflow_budget_bf16x3(gpu):
-    """The matrix-core step gets its outflow budget from the side-stream
-    kernel: the step results are unchanged by the budget, graph replay and
-    direct launches give the same totals, the totals close against the FP64
-    sums as in FP32, and they follow the oracle's outflow to the FP32 bound
-    (the split-BF16x3 back-map perturbs the populations by ~2^-17 of the
-    collision increment only; observed 4e-5 against a bound of 1e-2)."""
+    """The matrix-core step with the outflow budget (fused into its grid or
+    on the side stream, whichever the autotuned rows per wave allows): the
+    step results are unchanged by the budget, graph replay and direct
+    launches give the same totals, the totals close against the FP64 sums as
+    in FP32, and they follow the oracle's outflow to the FP32 bound (the
+    matrix-core back-map perturbs the populations by ~2^-17 of the collision
+    increment only)."""
     nx, ny, n = 150, 37, 300
     ic = synth.smooth_macro(nx, ny, seed=12, du=0.2, dr=0.1)
     prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["wall_split"], ic)
@@ -739,13 +739,17 @@ def test_couette_strip(gpu):
 
 
 def test_bf16x3_one_step_error_bound(gpu):
-    """Split-BF16 block products on the matrix cores: each operand x = hi +
-    lo with |x - hi - lo| <= 2^-17 |x|, three products (the lo*lo term,
-    <= 2^-16, dropped), FP32 accumulation.  Per population the collision then
-    errs by at most c 2^-18 (|dt M^-1| |S| |M| |f|)_i; with c = 16
-    (representation of both operands of both block products, the dropped
-    term, accumulation) on top of the FP32 bound.  Every node runs the split
-    products (the boundary waves too); the variants agree bit for bit."""
+    """Block products on the matrix cores: the forward blocks hold exact BF16
+    weights against inputs split exactly into three BF16 parts, so the
+    moments are FP32-accurate; the back-map holds its FP32 weights exactly
+    as three BF16 parts and splits its inputs x, the nonequilibrium moments
+    d, into two (|x - hi - lo| <= 2^-18 |x|), leaving out the products of
+    the weights' middle and low parts with the inputs' low parts (<= 2^-18
+    |w| |x|).  Per population the collision then errs by about 2^-17
+    (|dt M^-1| |S| |d|)_i; the bound takes 2^-16 (|dt M^-1| |S| |M| |f|)_i
+    (|d| <= |M f| + |M f^eq| is within twice the moment scale) on top of the
+    FP32 bound.  Every node runs the matrix-core products (the boundary waves
+    too); the variants agree bit for bit."""
     nx, ny = 200, 40
     f0 = synth.random_populations(nx, ny, seed=8, spread=0.3)
     prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"], None)
@@ -755,7 +759,7 @@ def test_bf16x3_one_step_error_bound(gpu):
     m = core.model()
     A = np.abs(m.Minv) * prob.dt @ np.diag(np.abs(RATES)) @ np.abs(m.M)
     scale = np.einsum("ik,kyx->iyx", A, np.abs(f0))
-    bound = 16 * 2.0 ** -18 * scale + 2e-6 * np.max(np.abs(want))
+    bound = 2.0 ** -16 * scale + 2e-6 * np.max(np.abs(want))
     ratio = np.abs(got - want) / bound
     print(f"bf16x3 one step: max err {np.max(np.abs(got - want)):.3e}, max err/bound {ratio.max():.3f}")
     assert np.all(ratio <= 1.0)
@@ -765,6 +769,10 @@ def test_bf16x3_one_step_error_bound(gpu):
 
 
 def test_bf16x3_couette_strip(gpu):
+    """Couette strip 256 x 256 (plainly stored populations, 500 steps): the
+    matrix-core products add nothing visible to the FP32 step's error, which
+    here comes from rounding the stored populations at the scale of |f| --
+    relative L1 within 1.25 times FP32's on rho, u1 and p."""
     prob = synth.couette(nx=256, ny=256, noise=1e-3)
     _, want = run_oracle(prob, None, 500)
     _, got32, _ = run_gpu(gpu, prob, None, 500)
@@ -772,8 +780,8 @@ def test_bf16x3_couette_strip(gpu):
     e32 = {k: metrics.rel_l1(got32[k], want[k]) for k in ("rho", "ux", "p")}
     e16 = {k: metrics.rel_l1(got16[k], want[k]) for k in ("rho", "ux", "p")}
     print("couette 256x256 500 steps rel L1: fp32", e32, "bf16x3", e16)
-    for k in ("rho", "p"):
-        assert e16[k] <= 1e-4, (k, e16[k])
+    for k in ("rho", "ux", "p"):
+        assert e16[k] <= 1.25 * e32[k], (k, e16[k], e32[k])
 
 
 def test_single_relaxation_time_mode(gpu):
