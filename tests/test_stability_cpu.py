@@ -159,3 +159,33 @@ def test_oracle_follows_the_screens_eigenvalue(S, state, theta, case):
         assert growth > case["grows"]   # the oracle's own run grows: unstable configuration
     else:
         assert growth < 1.0
+
+
+def test_high_mach_tube_is_unstable_whichever_moment_takes_each_rate(S):
+    """Sect. V.A(e) names its rates by moment index (s5 = s6 = 1.5e4, s10 =
+    5e4, the others 1e5).  Under every other assignment of the two reduced
+    rates -- the pair on moments (a, a + 1) for a = 5..15 and the single one
+    on any moment 5..16 -- and with all rates at 1e5, the west state (5, 45,
+    0, 10) still has a growing 1D mode (max |omega| > 1.01 per step), so no
+    reading of the indices makes the test pass as reported."""
+    state = (5.0, 45.0, 0.0, 10.0)
+    dx, dt = 0.003, 1e-5
+    mats = S.model()
+
+    def growth_1d(s):
+        return max(np.max(np.abs(np.linalg.eigvals(S.amplification(state, s, dx, dx, dt, tx, 0.0, mats)))) for tx in np.linspace(0.0, math.pi, 25))
+
+    def rates(pair, single):
+        s = [0.0] * 4 + [1e5] * 12
+        for k in pair:
+            s[k - 1] = 1.5e4
+        if single:
+            s[single - 1] = 5e4
+        return s
+
+    best = growth_1d(rates((), None))
+    for a in range(5, 16):
+        for k in range(5, 17):
+            best = min(best, growth_1d(rates((a, a + 1), k)))
+    print("least growth over the index readings", best)
+    assert best > 1.01
