@@ -24,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -43,7 +44,7 @@ OPS_PER_UPDATE = 330
 ALU_NODE_RATE = 256 * ALU_LANE_OPS_PER_CU_CLOCK * 2.4e9 / OPS_PER_UPDATE
 BYTES_PER_UPDATE = 128  # 16 FP32 populations read + 16 written
 SETUP_STEPS = 1024      # untimed: covers the autotuner's trials (<= ~600 steps) and graph capture
-KERNEL_SRC = os.path.join(ROOT, "paper_0908_3749_amd", "csrc", "mrtfd_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_0908_3749_amd", "csrc", f) for f in ("mrtfd_kernels.hip", "mrtfd_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 COUETTE_REF = os.path.join(ROOT, "tests", "golden", "couette_256x2048_50000.npz")
 TUBE_REF = os.path.join(ROOT, "tests", "golden", "tube_sample_16.npz")
@@ -87,8 +88,17 @@ def host_threads():
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """sha256[:16] of the step kernels' code -- the kernel source and its
+    internal header with comments and whitespace removed -- the key under
+    which profiles/traffic.json holds the HBM counters."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()[:16]
 
 
 def traffic_entry(workload, kernel, seg, streaming, tile_order, per_launch_cells, ref):

@@ -237,7 +237,7 @@ __device__ __forceinline__ void macro_of(const Consts &K, const float (&f)[NQ], 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// x = hi + lo with both parts BF16 (|x - hi - lo| <= 2^-18 |x|).  The
+// x = hi + lo with both parts BF16 (|x - hi - lo| <= 2^-17 |x|).  The
 // conversions round to nearest even (the packed hardware conversion of this
 // target), as the host does for the constant operands.
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
@@ -304,9 +304,9 @@ __device__ __forceinline__ f32x4 block_fwd(uint4 w, const float (&x)[4])
 // hi pair, mid pair, mid pair) and w3 = (lo pair, lo pair, -, -) of this
 // lane's row, hi + mid + lo = the FP32 weight exactly, so that the products
 // carry no fixed bias of the relaxation rates; the inputs split in two.
-// Four products, smallest first; what is left out (mid and lo times the
-// inputs' low parts) and the inputs' own split remainder are about 2^-17 of
-// the result and vary from node to node.
+// Four products, smallest first.  Left out: the weights' middle and low
+// parts times the inputs' low parts (at most 2^-16 |w| |x|), and the inputs'
+// own split remainder (at most 2^-17 |x|); both vary from node to node.
 __device__ __forceinline__ f32x4 block_back(uint4 w, uint4 w3, const float (&x)[4])
 {
     const bf16x4 wh = __builtin_bit_cast(bf16x4, make_uint2(w.x, w.y));
@@ -326,8 +326,8 @@ __device__ __forceinline__ f32x4 block_back(uint4 w, uint4 w3, const float (&x)[
 // cores (Bf3Ops: blocks 0-3 forward, 4-7 back, 8-11 the back blocks' third
 // parts).  The forward blocks give all 16 moments, the conserved ones
 // included, to FP32 accuracy; the back-map holds its weights exactly and
-// rounds its inputs, the nonequilibrium moments, to two BF16 parts (about
-// 2^-17 of dt s_k times them).  The butterflies, the equilibria and the
+// splits its inputs, the nonequilibrium moments, into two BF16 parts (an
+// error of at most 1.5 2^-16 of |dt s_k M^-1| times them).  The butterflies, the equilibria and the
 // inverse butterfly stay FP32.  bt = the block table in LDS, row = lane % 4.
 // Every lane of the wave must execute it.
 __device__ __forceinline__ void collide_bf3(const Consts &K, const uint4 (*bt)[4], int row,

@@ -20,9 +20,10 @@ it is added to g, so that one rounding per step acts at the scale of |g|
 and the others at the scale of the increment.  The matrix-core form keeps
 that: its forward products give the moments to FP32 accuracy and its
 back-map holds the FP32 weights exactly (no fixed bias of the relaxation
-rates, hence of the viscosity), rounding only the nonequilibrium moments to
-about 2^-17 of themselves (observed: u1 relative L1 5.7e-7 against FP32's
-2.8e-7, node by node 1.0e-6 U).
+rates, hence of the viscosity), rounding only its products with the
+nonequilibrium moments, by at most 1.5 2^-16 of them and varying from node
+to node (observed: u1 relative L1 5.7e-7 against FP32's 2.8e-7, node by
+node 1.0e-6 U).
 """
 import os
 

@@ -442,8 +442,8 @@ def test_outflow_budget_bf16x3(gpu):
     step results are unchanged by the budget, graph replay and direct
     launches give the same totals, the totals close against the FP64 sums as
     in FP32, and they follow the oracle's outflow to the FP32 bound (the
-    matrix-core back-map perturbs the populations by ~2^-17 of the collision
-    increment only)."""
+    matrix-core back-map perturbs the populations by at most ~2^-15 of the
+    collision increment)."""
     nx, ny, n = 150, 37, 300
     ic = synth.smooth_macro(nx, ny, seed=12, du=0.2, dr=0.1)
     prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["wall_split"], ic)
@@ -577,6 +577,22 @@ def _steps_to_autotune(nx, ny):
     return 2 * ncand * (reps + 2) + 4
 
 
+def _full_size_start(prob, ref):
+    """(stored FP32 start g0, f_ref per population, an oracle grid holding
+    g0 + f_ref in FP64): the oracle's initial equilibrium, less f_ref when a
+    reference state is set, rounded to FP32 as the library stores it."""
+    from paper_0908_3749_amd import make_params, ref_populations
+    o = core.Grid(prob, nthreads=THREADS)
+    o.init_problem()
+    fr = np.zeros(16)
+    if ref is not None:
+        fr = ref_populations(make_params(prob.nx, prob.ny, prob.dx, prob.dy, prob.dt, prob.s, prob.sides,
+                                         ref=ref))
+    g0 = (o.get_f() - fr[:, None, None]).astype(np.float32)
+    o.set_f(g0.astype(np.float64) + fr[:, None, None])
+    return g0, fr, o
+
+
 @pytest.mark.parametrize("config", ["mach3", "bubble", "couette"])
 def test_full_size_steps_match_oracle(gpu, config):
     """At the benchmark's full sizes (2048x512 Mach reflection, 4096x1024
@@ -586,23 +602,25 @@ def test_full_size_steps_match_oracle(gpu, config):
     to FP32) for the autotuner to finish agree with the whole-grid FP64
     oracle node by node, within 4 n u S after n steps, S = transform_scale
     (each step's rounding is a few u of the magnitudes the collision
-    cancels)."""
+    cancels).  Couette runs stored relative to the gas at rest (1, 1), as
+    bench.py runs it: the oracle starts from the GPU's stored values plus
+    f_ref in FP64, and the GPU's result plus f_ref is compared."""
     prob = {"mach3": synth.mach_reflection, "bubble": synth.shock_bubble, "couette": synth.couette}[config]()
+    ref = (1.0, 1.0) if config == "couette" else None
     n = _steps_to_autotune(prob.nx, prob.ny)
-    o = core.Grid(prob, nthreads=THREADS)
-    o.init_problem()
-    f0 = o.get_f().astype(np.float32)
-    o.set_f(f0.astype(np.float64))
+    g0, fr, o = _full_size_start(prob, ref)
     scale = transform_scale(prob, o.get_f())
     o.run(n)
     want = o.get_f()
-    g = gpu.from_problem(prob, graph_steps=64)
-    g.set_f(f0)
+    del o
+    g = gpu.from_problem(prob, graph_steps=64, ref=ref)
+    g.set_f(g0)
+    del g0
     g.step(n)
     got = g.get_f_numpy()
     variant = g.kernel_variant()
     g.close()
-    err = np.max(np.abs(got - want))
+    err = max(float(np.max(np.abs(got[q] + fr[q] - want[q]))) for q in range(16))
     bound = 4 * n * U32 * scale
     print(f"full size {config}, {n} steps, variant {variant}: max err {err:.3e}, bound {bound:.3e}")
     assert err <= bound
@@ -610,34 +628,35 @@ def test_full_size_steps_match_oracle(gpu, config):
 
 def test_full_size_bf16x3_couette_matches_oracle(gpu):
     """The mixed-precision workload at its full size (Couette 8192 x 2048,
-    split-BF16x3 transforms on the matrix cores) in bench.py's launch
-    configuration (graph of 64 steps, store kind and tile order autotuned on
-    the run's first steps): after the autotune's two passes it agrees with
-    the whole-grid FP64 oracle node by node within n (16 2^-18 + 4 u) S per
-    step bound of the split products on top of the FP32 one, S =
-    transform_scale."""
+    stored relative to (1, 1), the collision's blocks on the matrix cores)
+    in bench.py's launch configuration (graph of 64 steps, rows per wave,
+    store kind and tile order autotuned on the run's first steps): after the
+    autotune's two passes it agrees with the whole-grid FP64 oracle node by
+    node within n (2^-14 + 4 u) S, the one-step bound of the matrix-core
+    products (test_bf16x3_one_step_error_bound) on top of the FP32 one per
+    step, S = transform_scale."""
     prob = synth.couette()
+    ref = (1.0, 1.0)
     cells = prob.nx * prob.ny
     reps = 2 * int(max(4.0, min(16.0, 1e7 / cells)))
-    ncand = 4 if ((prob.nx + 63) // 64) % 8 == 0 else 2  # store kind x tile order
+    # rows per wave x store kind x tile order
+    ncand = 8 if ((prob.nx + 63) // 64) % 8 == 0 else 4
     n = 2 * ncand * (reps + 2) + 4
-    o = core.Grid(prob, nthreads=THREADS)
-    o.init_problem()
-    f0 = o.get_f().astype(np.float32)
-    o.set_f(f0.astype(np.float64))
+    g0, fr, o = _full_size_start(prob, ref)
     scale = transform_scale(prob, o.get_f())
     o.run(n)
     want = o.get_f()
     del o
-    g = gpu.from_problem(prob, graph_steps=64, precision="bf16x3")
-    g.set_f(f0)
+    g = gpu.from_problem(prob, graph_steps=64, precision="bf16x3", ref=ref)
+    g.set_f(g0)
+    del g0
     g.step(n)
     got = g.get_f_numpy()
     variant = g.kernel_variant()
     g.close()
     assert variant[0] == "mfma"
-    err = max(float(np.max(np.abs(got[q] - want[q]))) for q in range(16))
-    bound = n * (16 * 2.0 ** -18 + 4 * U32) * scale
+    err = max(float(np.max(np.abs(got[q] + fr[q] - want[q]))) for q in range(16))
+    bound = n * (2.0 ** -14 + 4 * U32) * scale
     print(f"full size couette bf16x3, {n} steps, variant {variant}: max err {err:.3e}, bound {bound:.3e}")
     assert err <= bound
 
@@ -741,15 +760,16 @@ def test_couette_strip(gpu):
 def test_bf16x3_one_step_error_bound(gpu):
     """Block products on the matrix cores: the forward blocks hold exact BF16
     weights against inputs split exactly into three BF16 parts, so the
-    moments are FP32-accurate; the back-map holds its FP32 weights exactly
-    as three BF16 parts and splits its inputs x, the nonequilibrium moments
-    d, into two (|x - hi - lo| <= 2^-18 |x|), leaving out the products of
-    the weights' middle and low parts with the inputs' low parts (<= 2^-18
-    |w| |x|).  Per population the collision then errs by about 2^-17
-    (|dt M^-1| |S| |d|)_i; the bound takes 2^-16 (|dt M^-1| |S| |M| |f|)_i
-    (|d| <= |M f| + |M f^eq| is within twice the moment scale) on top of the
-    FP32 bound.  Every node runs the matrix-core products (the boundary waves
-    too); the variants agree bit for bit."""
+    moments are FP32-accurate (tests/test_bf16_blocks_cpu.py).  The back-map
+    holds its FP32 weights w exactly as three BF16 parts and splits its
+    inputs x, the nonequilibrium moments d, into two (|x - hi - lo| <= 2^-17
+    |x|); it leaves out the products of the weights' middle and low parts
+    (<= 2^-8 |w|) with the inputs' low parts (<= 2^-8 |x|).  Per product that
+    is at most (2^-16 + 2^-17) |w| |x|, so per population the collision errs
+    by at most 1.5 2^-16 (|dt M^-1| |S| |d|)_i; with |d| <= |M f| + |M f^eq|,
+    within twice the moment scale, the bound is 2^-14 (|dt M^-1| |S| |M|
+    |f|)_i on top of the FP32 bound.  Every node runs the matrix-core
+    products (the boundary waves too); the variants agree bit for bit."""
     nx, ny = 200, 40
     f0 = synth.random_populations(nx, ny, seed=8, spread=0.3)
     prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS["periodic"], None)
@@ -759,7 +779,7 @@ def test_bf16x3_one_step_error_bound(gpu):
     m = core.model()
     A = np.abs(m.Minv) * prob.dt @ np.diag(np.abs(RATES)) @ np.abs(m.M)
     scale = np.einsum("ik,kyx->iyx", A, np.abs(f0))
-    bound = 2.0 ** -16 * scale + 2e-6 * np.max(np.abs(want))
+    bound = 2.0 ** -14 * scale + 2e-6 * np.max(np.abs(want))
     ratio = np.abs(got - want) / bound
     print(f"bf16x3 one step: max err {np.max(np.abs(got - want)):.3e}, max err/bound {ratio.max():.3f}")
     assert np.all(ratio <= 1.0)

@@ -97,7 +97,7 @@ def test_one_step_every_variant(gpu, sides):
 
 def test_one_step_bf16x3(gpu):
     """The matrix-core block products on stored deviations: every node within
-    the bound 2^-16 (|dt M^-1| |S| |M| |g|)_i of the back-map's split inputs
+    the bound 2^-14 (|dt M^-1| |S| |M| |g|)_i of the back-map's split inputs
     (test_gpu_parity.test_bf16x3_one_step_error_bound; the transforms act on
     g here) on top of the FP32 one, and different from the FP32 step."""
     nx, ny = 200, 40
@@ -120,7 +120,7 @@ def test_one_step_bf16x3(gpu):
     m = core.model()
     A = np.abs(m.Minv) * prob.dt @ np.diag(np.abs(RATES)) @ np.abs(m.M)
     scale = np.einsum("ik,kyx->iyx", A, np.abs(g0.astype(np.float64)))
-    bound = 2.0 ** -16 * scale + 2e-6 * np.max(np.abs(want))
+    bound = 2.0 ** -14 * scale + 2e-6 * np.max(np.abs(want))
     err = np.abs(got.astype(np.float64) + fr - want)
     print(f"bf16x3 with reference: max err/bound {np.max(err / bound):.3f}")
     assert np.all(err <= bound)
