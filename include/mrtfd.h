@@ -181,7 +181,12 @@ int32_t mrtfd_check_params(const mrtfd_params *p, char *msg, size_t msg_len);
  * and uploads the FP32 constants.  d_workspace: device buffer of at least
  * mrtfd_workspace_bytes(p) bytes, 256-byte aligned, owned by the caller and
  * kept alive until mrtfd_destroy.  stream: a hipStream_t (NULL = default
- * stream).  On success *out receives the context. */
+ * stream).  On success *out receives the context.  Errors: the codes of
+ * mrtfd_check_params; MRTFD_ERR_ARG for a NULL, short or misaligned
+ * workspace; MRTFD_ERR_HIP if a runtime call fails; MRTFD_ERR_UNSUPPORTED
+ * with MRTFD_BF16X3 if the factored transform's blocks are not held exactly
+ * by their BF16 parts (a consistency check of the model, which the
+ * 16-velocity M of Eq. 5 passes). */
 int32_t mrtfd_create(const mrtfd_params *p, void *d_workspace, size_t workspace_bytes,
                      void *stream, mrtfd_ctx **out);
 
