@@ -339,14 +339,16 @@ def bench_batch(with_separate=True, with_accuracy=True, no_graph=False):
 def comparison(warmup):
     """The metric's other forms in the same run: the Mach-3 reflection
     (2048x512, cache-resident) and the shock-bubble (4096x1024) in FP32, the
-    Couette 8192x2048 with the split-BF16x3 matrix-core transforms, each 2000
+    Couette 8192x2048 with the split-BF16x3 matrix-core transforms and in
+    FP64 (populations stored in FP64: 256 B per node update), each 2000
     timed steps after the set-up and warm-up; and the 512-tube batch."""
     import synth
 
     out = {}
     cases = (("mach3_reflection_2048x512", synth.mach_reflection(), {}),
              ("shock_bubble_4096x1024", synth.shock_bubble(), {}),
-             ("couette_8192x2048_bf16x3", synth.couette(), dict(ref=(1.0, 1.0), precision="bf16x3")))
+             ("couette_8192x2048_bf16x3", synth.couette(), dict(ref=(1.0, 1.0), precision="bf16x3")),
+             ("couette_8192x2048_fp64", synth.couette(), dict(ref=(1.0, 1.0), precision="fp64")))
     for name, prob, kw in cases:
         n = 2000
         g, ms, G, _ = timed_steps(prob, n, warmup, **kw)
@@ -354,9 +356,11 @@ def comparison(warmup):
         g.close()
         cells = prob.nx * prob.ny
         step_ms = ms / n
+        per_node = 2 * BYTES_PER_UPDATE if kw.get("precision") == "fp64" else BYTES_PER_UPDATE
         out[name] = {"value": round(cells * n / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
                      "ms_per_step": round(step_ms, 6),
-                     "hbm_frac": round(BYTES_PER_UPDATE * cells / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "hbm_frac": round(per_node * cells / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "bytes_per_node_update": per_node,
                      "kernel": variant_name(v), "steps": n, "graph_steps": G}
     out["batched"] = bench_batch()
     return out
@@ -373,7 +377,7 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "simple", "rows"])
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--graph-steps", type=int, default=64)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
     ap.add_argument("--layout", default="rows", choices=["rows", "planes", "tiles"])
     ap.add_argument("--no-ref", action="store_true", help="store f itself (no reference state)")
     ap.add_argument("--cpu-steps", type=int, default=None,
@@ -467,8 +471,11 @@ def main():
                           "kernel's grid at one row per wave, else its own kernel on a second stream "
                           "beside each step); residual = sums(end) - sums(start) + outflow over all steps"}
 
-    achieved = BYTES_PER_UPDATE * cells / (ms_step * 1e-3) / 1e9
-    traffic = traffic_entry(W["name"], kernel, seg, streaming, tile_order, cells, ref)
+    per_node = 2 * BYTES_PER_UPDATE if args.precision == "fp64" else BYTES_PER_UPDATE
+    achieved = per_node * cells / (ms_step * 1e-3) / 1e9
+    # the counter entries are FP32-stored variants (fp32 rows/simple, bf16x3 mfma)
+    traffic = None if args.precision == "fp64" else traffic_entry(W["name"], kernel, seg, streaming,
+                                                                   tile_order, cells, ref)
     print(f"bench: {W['name']} {steps} steps, {ms_step * 1e3:.2f} us/step, step kernel "
           f"{variant_name((kernel, seg, streaming, tile_order))}, {mlups:.0f} MLUPS, {achieved:.0f} GB/s",
           file=sys.stderr, flush=True)
@@ -484,7 +491,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "bf16x3+f32",
+        "dtype": {"fp32": "f32", "bf16x3": "bf16x3+f32", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": W["name"], "nx": prob.nx, "ny": prob.ny, "dt": prob.dt,
                    "precision": args.precision, "layout": args.layout,
@@ -496,7 +503,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic["bytes_per_launch"]),
                      "step_us": round(ms_step * 1e3, 3),
-                     "algorithmic_bytes_per_launch": BYTES_PER_UPDATE * cells,
+                     "algorithmic_bytes_per_launch": per_node * cells,
                      "timing": "HIP events on the context's stream around the timed steps: one step-kernel "
                                "launch per step plus one single-thread clock kernel per replayed graph"},
         "fp64_sums": [float(v) for v in sums],

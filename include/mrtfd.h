@@ -83,6 +83,16 @@ extern "C" {
                           butterflies, equilibria and stencil FP32 (a last
                           grid column alone in its 64-column wave takes the
                           FP32 collision)                                   */
+#define MRTFD_FP64 2   /* the whole step in FP64, populations stored in FP64
+                          (one thread per node: MRTFD_KERNEL_SIMPLE, at 256
+                          bytes of populations per node update): for states
+                          whose populations sum to far more than rho (hot
+                          gas: the 16-velocity equilibrium sums to about
+                          0.7 T^2 rho), where FP32 storage rounds rho by that
+                          factor more than u (Sect. V.A(c), (d)).  Outputs
+                          of mrtfd_read_macro are FP32 roundings;
+                          mrtfd_get_f64 / mrtfd_set_f64 exchange the stored
+                          values exactly                                     */
 
 /* ---- collision operator ------------------------------------------------ */
 #define MRTFD_COLLISION_MRT 0 /* Eq. (3): M^-1 S-hat (f-hat - f-hat^eq)            */
@@ -134,7 +144,7 @@ typedef struct mrtfd_params {
     double dx, dy, dt;
     double s[16];
     mrtfd_side side[4];
-    int32_t precision;  /* MRTFD_FP32 or MRTFD_BF16X3                        */
+    int32_t precision;  /* MRTFD_FP32, MRTFD_BF16X3 or MRTFD_FP64             */
     int32_t kernel;     /* MRTFD_KERNEL_*                                    */
     int32_t rows;       /* rows per wave for MRTFD_KERNEL_ROWS (1 or 2),
                            0 = auto                                          */
@@ -241,6 +251,13 @@ int32_t mrtfd_sums_noalloc(mrtfd_ctx *ctx, double *d_out);
  * taken with mrtfd_get_f restarts bit for bit. */
 int32_t mrtfd_get_f(mrtfd_ctx *ctx, float *d_f);
 int32_t mrtfd_set_f(mrtfd_ctx *ctx, const float *d_f);
+
+/* The same exchange as a packed device FP64 array [16][ny][nx]: exact for
+ * MRTFD_FP64 contexts (checkpoint and restart bit for bit); for FP32-stored
+ * contexts get widens exactly and set rounds to nearest FP32 (mrtfd_get_f /
+ * mrtfd_set_f do the reverse for MRTFD_FP64 contexts). */
+int32_t mrtfd_get_f64(mrtfd_ctx *ctx, double *d_f);
+int32_t mrtfd_set_f64(mrtfd_ctx *ctx, const double *d_f);
 
 /* f_ref = M^-1 f-hat^eq(ref_rho, 0, 0, ref_rho ref_T) (Eq. 14, FP64, from
  * the FP32 roundings of ref_rho and ref_T) of these parameters into the host

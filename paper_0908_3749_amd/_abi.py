@@ -29,6 +29,7 @@ BC_KINDS = {"periodic": MRTFD_BC_PERIODIC, "dirichlet": MRTFD_BC_DIRICHLET,
 
 MRTFD_FP32 = 0
 MRTFD_BF16X3 = 1
+MRTFD_FP64 = 2
 
 MRTFD_LAYOUT_ROWS = 0
 MRTFD_LAYOUT_PLANES = 1
@@ -89,6 +90,8 @@ _PROTOS = {
     "mrtfd_sums_noalloc": (C.c_int32, [_vp, _vp]),
     "mrtfd_get_f": (C.c_int32, [_vp, _fp]),
     "mrtfd_set_f": (C.c_int32, [_vp, _fp]),
+    "mrtfd_get_f64": (C.c_int32, [_vp, _vp]),
+    "mrtfd_set_f64": (C.c_int32, [_vp, _vp]),
     "mrtfd_ref_populations": (C.c_int32, [C.POINTER(mrtfd_params), C.POINTER(C.c_double)]),
     "mrtfd_time": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "mrtfd_set_step": (C.c_int32, [_vp, C.c_int64]),

@@ -250,30 +250,32 @@ void ref_populations(const Model &m, const mrtfd_params &p, double out[NQ])
         for (int q = 0; q < NQ; ++q) out[q] = 0.0;
 }
 
-void fill_consts(const Model &m, const mrtfd_params &p, Consts &K)
+// The step constants in the stored precision (FP64 products, then rounded).
+template <class Real>
+void fill_consts(const Model &m, const mrtfd_params &p, ConstsT<Real> &K)
 {
     std::memset(&K, 0, sizeof K);
     const int r0[4] = {0, 3, 10, 11}, rx[4] = {1, 6, 8, 14}, ry[4] = {2, 7, 9, 15};
     const int rqa[2] = {4, 12}, rqd[2] = {5, 13};
     for (int a = 0; a < 4; ++a)
         for (int g = 0; g < 4; ++g) {
-            K.f0[a][g] = (float)m.B[r0[a]][g];
-            K.fx[a][g] = (float)m.B[rx[a]][4 + g];
-            K.fy[a][g] = (float)m.B[ry[a]][8 + g];
-            K.i0[g][a] = (float)m.DBinv[g][r0[a]];
-            K.ix[g][a] = (float)m.DBinv[4 + g][rx[a]];
-            K.iy[g][a] = (float)m.DBinv[8 + g][ry[a]];
+            K.f0[a][g] = (Real)m.B[r0[a]][g];
+            K.fx[a][g] = (Real)m.B[rx[a]][4 + g];
+            K.fy[a][g] = (Real)m.B[ry[a]][8 + g];
+            K.i0[g][a] = (Real)m.DBinv[g][r0[a]];
+            K.ix[g][a] = (Real)m.DBinv[4 + g][rx[a]];
+            K.iy[g][a] = (Real)m.DBinv[8 + g][ry[a]];
         }
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
-            K.fqa[a][b] = (float)m.B[rqa[a]][12 + b];
-            K.fqd[a][b] = (float)m.B[rqd[a]][14 + b];
-            K.iqa[a][b] = (float)m.DBinv[12 + a][rqa[b]];
-            K.iqd[a][b] = (float)m.DBinv[14 + a][rqd[b]];
+            K.fqa[a][b] = (Real)m.B[rqa[a]][12 + b];
+            K.fqd[a][b] = (Real)m.B[rqd[a]][14 + b];
+            K.iqa[a][b] = (Real)m.DBinv[12 + a][rqa[b]];
+            K.iqd[a][b] = (Real)m.DBinv[14 + a][rqd[b]];
         }
     // collision columns: D B^-1 scaled by dt s_k (FP64 product, then rounded)
     const double dt = p.dt;
-    auto cs = [&](int row, int k) { return (float)(m.DBinv[row][k] * dt * p.s[k]); };
+    auto cs = [&](int row, int k) { return (Real)(m.DBinv[row][k] * dt * p.s[k]); };
     const int k0[2] = {10, 11}, kx[3] = {6, 8, 14}, ky[3] = {7, 9, 15};
     for (int g = 0; g < 4; ++g) {
         for (int a = 0; a < 2; ++a) K.c0[g][a] = cs(g, k0[a]);
@@ -289,17 +291,17 @@ void fill_consts(const Model &m, const mrtfd_params &p, Consts &K)
         }
     for (int q = 0; q < NQ; ++q) {
         const double a = m.v[q][0] * dt / p.dx, b = m.v[q][1] * dt / p.dy;
-        K.lw[q][0] = (float)(0.5 * (a * a - a));
-        K.lw[q][1] = (float)(0.5 * (a * a + a));
-        K.lw[q][2] = (float)(0.5 * (b * b - b));
-        K.lw[q][3] = (float)(0.5 * (b * b + b));
+        K.lw[q][0] = (Real)(0.5 * (a * a - a));
+        K.lw[q][1] = (Real)(0.5 * (a * a + a));
+        K.lw[q][2] = (Real)(0.5 * (b * b - b));
+        K.lw[q][3] = (Real)(0.5 * (b * b + b));
     }
     double rho0, T0;
     ref_state(p, rho0, T0);
-    K.rho0 = (float)rho0;
-    K.T0 = (float)T0;
-    K.e0 = (float)(rho0 * T0);
-    K.Te0 = (float)(T0 * rho0 * T0);
+    K.rho0 = (Real)rho0;
+    K.T0 = (Real)T0;
+    K.e0 = (Real)(rho0 * T0);
+    K.Te0 = (Real)(T0 * rho0 * T0);
 }
 
 // BF16 bits of an FP32 value, round to nearest even (as the kernels do).
@@ -376,6 +378,50 @@ bool fill_bf3(const Consts &K, Bf3Ops &out)
     return true;
 }
 
+// Boundary description of the step kernels in the stored precision: per side
+// its rule pair and switch point, the states as deviations from the
+// reference state (rho - rho0, u1, u2, T - T0) and the Dirichlet equilibria
+// as f^eq - f_ref, both formed in FP64 and then rounded.  kcopy, gcopy and
+// fcopy are the workspace addresses of the device copies of the constants,
+// of this struct and of the outflow coefficients.
+template <class Real>
+void fill_ghosts(const Model &m, const mrtfd_params &p, const double (&fref)[NQ], char *kcopy,
+                 char *gcopy, char *fcopy, GhostsT<Real> &G)
+{
+    double rho0, T0;
+    ref_state(p, rho0, T0);
+    G.dt = p.dt;
+    G.kd = reinterpret_cast<const ConstsT<Real> *>(kcopy);
+    G.gd = reinterpret_cast<const GhostsT<Real> *>(gcopy);
+    G.fd = reinterpret_cast<const FluxCoef *>(fcopy);
+    G.per_x = p.side[0].kind_lo == MRTFD_BC_PERIODIC;
+    G.per_y = p.side[2].kind_lo == MRTFD_BC_PERIODIC;
+    for (int s = 0; s < 4; ++s) {
+        const mrtfd_side &S = p.side[s];
+        GhostSideT<Real> &g = G.side[s];
+        g.kind_lo = S.kind_lo;
+        g.kind_hi = S.kind_hi;
+        g.split0 = S.split0;
+        g.split_rate = S.split_rate;
+        g.h = s < 2 ? p.dy : p.dx;
+        const double off[4] = {rho0, 0.0, 0.0, T0};
+        for (int k = 0; k < 4; ++k) {
+            g.st_lo[k] = (Real)(S.state_lo[k] - off[k]);
+            g.st_hi[k] = (Real)(S.state_hi[k] - off[k]);
+        }
+        double fe[NQ];
+        for (int q = 0; q < NQ; ++q) g.feq_lo[q] = g.feq_hi[q] = Real(0);
+        if (S.kind_lo == MRTFD_BC_DIRICHLET) {
+            feq_host(m, S.state_lo[0], S.state_lo[1], S.state_lo[2], S.state_lo[3], fe);
+            for (int q = 0; q < NQ; ++q) g.feq_lo[q] = (Real)(fe[q] - fref[q]);
+        }
+        if (S.kind_hi == MRTFD_BC_DIRICHLET) {
+            feq_host(m, S.state_hi[0], S.state_hi[1], S.state_hi[2], S.state_hi[3], fe);
+            for (int q = 0; q < NQ; ++q) g.feq_hi[q] = (Real)(fe[q] - fref[q]);
+        }
+    }
+}
+
 // --------------------------------------------------------------- validation
 
 int check(const mrtfd_params *p, char *msg, size_t len)
@@ -398,12 +444,12 @@ int check(const mrtfd_params *p, char *msg, size_t len)
         // byte offsets: (ny + 2) rows of 16 x pitch floats must stay below 4 GiB
         const long long pitch = ((long long)p->nx + 65 + 63) / 64 * 64;
         const long long bytes = 4LL * NQ * pitch * ((long long)p->ny + 2);
-        if (bytes >= (1LL << 32) && p->kernel != MRTFD_KERNEL_SIMPLE)
+        if (bytes >= (1LL << 32) && p->kernel != MRTFD_KERNEL_SIMPLE && p->precision != MRTFD_FP64)
             return fail(MRTFD_ERR_ARG,
                         "grid %d x %d needs %lld bytes per copy of f: above 4 GiB only "
                         "MRTFD_KERNEL_SIMPLE (FP32) runs it", p->nx, p->ny, bytes);
-        if (bytes >= (1LL << 32) && p->precision != MRTFD_FP32)
-            return fail(MRTFD_ERR_ARG, "grids above 4 GiB per copy run in FP32 only");
+        if (bytes >= (1LL << 32) && p->precision == MRTFD_BF16X3)
+            return fail(MRTFD_ERR_ARG, "grids above 4 GiB per copy of FP32 values run in FP32 or FP64");
     }
     if (!(p->dx > 0) || !(p->dy > 0) || !(p->dt > 0) || !std::isfinite(p->dx) ||
         !std::isfinite(p->dy) || !std::isfinite(p->dt))
@@ -416,8 +462,10 @@ int check(const mrtfd_params *p, char *msg, size_t len)
     }
     const double cfl = 6.0 * p->dt / std::min(p->dx, p->dy);
     if (cfl > 1.0) return fail(MRTFD_ERR_UNSTABLE, "Courant number 6 dt / min(dx,dy) = %g exceeds 1", cfl);
-    if (p->precision != MRTFD_FP32 && p->precision != MRTFD_BF16X3)
+    if (p->precision != MRTFD_FP32 && p->precision != MRTFD_BF16X3 && p->precision != MRTFD_FP64)
         return fail(MRTFD_ERR_ARG, "unknown precision mode %d", p->precision);
+    if (p->precision == MRTFD_FP64 && p->kernel == MRTFD_KERNEL_ROWS)
+        return fail(MRTFD_ERR_ARG, "MRTFD_FP64 runs the one-thread-per-node kernel (kernel AUTO or SIMPLE)");
     if (p->collision != MRTFD_COLLISION_MRT && p->collision != MRTFD_COLLISION_SRT)
         return fail(MRTFD_ERR_ARG, "unknown collision %d", p->collision);
     if (p->collision == MRTFD_COLLISION_SRT) {
@@ -502,7 +550,8 @@ Layout layout(const mrtfd_params &p)
 {
     const Field F = make_field(p);
     Layout L;
-    const size_t fbytes = align256((size_t)F.total * sizeof(float));
+    const size_t esize = p.precision == MRTFD_FP64 ? sizeof(double) : sizeof(float);
+    const size_t fbytes = align256((size_t)F.total * esize);
     L.fA = 0;
     L.fB = L.fA + fbytes;
     L.partials = L.fB + fbytes;
@@ -511,8 +560,8 @@ Layout layout(const mrtfd_params &p)
     L.flag = L.step + 256;
     L.bf3 = L.flag + 256;
     L.kcopy = L.bf3 + align256(sizeof(Bf3Ops));
-    L.gcopy = L.kcopy + align256(sizeof(Consts));
-    L.fcopy = L.gcopy + align256(sizeof(Ghosts));
+    L.gcopy = L.kcopy + align256(sizeof(Consts64));  // room for either precision
+    L.fcopy = L.gcopy + align256(sizeof(Ghosts64));
     L.flux = L.fcopy + align256(sizeof(FluxCoef));
     L.outflow = L.flux + (p.flux_budget ? align256(2 * ((size_t)p.nx + p.ny) * 4 * sizeof(double)) : 0);
     L.total = L.outflow + 256;
@@ -546,10 +595,13 @@ struct mrtfd_ctx {
     Field F;
     Consts K;
     Ghosts G;
+    Consts64 K64;                // FP64 mode: constants and boundary states in FP64
+    Ghosts64 G64;
     SumW W;
     Layout L;
     char *ws = nullptr;
-    float *f[2] = {nullptr, nullptr};
+    float *f[2] = {nullptr, nullptr};      // the two copies of the stored values (FP32)
+    double *f64[2] = {nullptr, nullptr};   // the same copies in the FP64 mode
     double *partials = nullptr, *sums = nullptr;
     long long *d_step = nullptr;
     int *d_flag = nullptr;
@@ -610,8 +662,15 @@ bool budget_fused(const mrtfd_ctx *c)
            (c->seg & 15) == 1;
 }
 
-hipError_t launch_step(mrtfd_ctx *c, const float *fin, float *fout, int k, hipStream_t s)
+bool is64(const mrtfd_ctx *c) { return c->p.precision == MRTFD_FP64; }
+
+// One step from copy a to copy a ^ 1.
+hipError_t launch_step(mrtfd_ctx *c, int a, int k, hipStream_t s)
 {
+    if (is64(c))
+        return launch_step_simple(c->F, c->K64, c->G64, c->f64[a], c->f64[a ^ 1], c->d_step, k, s);
+    const float *fin = c->f[a];
+    float *fout = c->f[a ^ 1];
     if (c->kernel == MRTFD_KERNEL_SIMPLE)
         return launch_step_simple(c->F, c->K, c->G, fin, fout, c->d_step, k, s);
     // the row kernels; with MRTFD_KERNEL_MFMA their split-BF16 variant
@@ -635,10 +694,13 @@ hipError_t enqueue_steps(mrtfd_ctx *c, int start, int n, hipStream_t s)
             e = hipEventRecord(c->ev_fork, s);
             if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_fork, 0);
             if (e == hipSuccess)
-                e = launch_face_flux(c->F, c->K, c->G, c->FC, c->f[a], c->flux, c->d_step, k, c->side);
+                e = is64(c) ? launch_face_flux(c->F, c->K64, c->G64, c->FC, c->f64[a], c->flux, c->d_step,
+                                               k, c->side)
+                            : launch_face_flux(c->F, c->K, c->G, c->FC, c->f[a], c->flux, c->d_step, k,
+                                               c->side);
             if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->side);
         }
-        if (e == hipSuccess) e = launch_step(c, c->f[a], c->f[a ^ 1], k, s);
+        if (e == hipSuccess) e = launch_step(c, a, k, s);
         if (e == hipSuccess && side) e = hipStreamWaitEvent(s, c->ev_join, 0);
         if (e != hipSuccess) return e;
         a ^= 1;
@@ -913,8 +975,13 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     c->F = make_field(*p);
     c->L = L;
     c->ws = static_cast<char *>(d_ws);
-    c->f[0] = reinterpret_cast<float *>(c->ws + L.fA);
-    c->f[1] = reinterpret_cast<float *>(c->ws + L.fB);
+    if (p->precision == MRTFD_FP64) {
+        c->f64[0] = reinterpret_cast<double *>(c->ws + L.fA);
+        c->f64[1] = reinterpret_cast<double *>(c->ws + L.fB);
+    } else {
+        c->f[0] = reinterpret_cast<float *>(c->ws + L.fA);
+        c->f[1] = reinterpret_cast<float *>(c->ws + L.fB);
+    }
     c->partials = reinterpret_cast<double *>(c->ws + L.partials);
     c->sums = reinterpret_cast<double *>(c->ws + L.sums);
     c->d_step = reinterpret_cast<long long *>(c->ws + L.step);
@@ -932,12 +999,11 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     }
     c->stream = static_cast<hipStream_t>(stream);
     fill_consts(m, *p, c->K);
+    fill_consts(m, *p, c->K64);
     if (!fill_bf3(c->K, c->h_bf3) && p->precision == MRTFD_BF16X3) {
         delete c;  // a weight that its BF16 parts do not hold exactly
         return MRTFD_ERR_UNSUPPORTED;
     }
-    double rho0, T0;
-    ref_state(*p, rho0, T0);
     ref_populations(m, *p, c->fref);
     // outflow of the uniform f_ref through one node of each side per step
     // (its face value is v f_ref), added to the budget's totals on readout
@@ -962,40 +1028,8 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         c->W.add[1] = c->W.add[2] = 0.0;
         c->W.add[3] = nodes * (rho0 * T0);
     }
-    c->G.dt = p->dt;
-    c->G.kd = reinterpret_cast<const Consts *>(c->ws + L.kcopy);
-    c->G.gd = reinterpret_cast<const Ghosts *>(c->ws + L.gcopy);
-    c->G.fd = reinterpret_cast<const FluxCoef *>(c->ws + L.fcopy);
-    c->G.per_x = p->side[0].kind_lo == MRTFD_BC_PERIODIC;
-    c->G.per_y = p->side[2].kind_lo == MRTFD_BC_PERIODIC;
-    for (int s = 0; s < 4; ++s) {
-        const mrtfd_side &S = p->side[s];
-        GhostSide &g = c->G.side[s];
-        g.kind_lo = S.kind_lo;
-        g.kind_hi = S.kind_hi;
-        g.split0 = S.split0;
-        g.split_rate = S.split_rate;
-        g.h = s < 2 ? p->dy : p->dx;
-        double fe[NQ];
-        // states as deviations from the reference (rho - rho0, u1, u2, T - T0)
-        // and Dirichlet equilibria as f^eq - f_ref, both in FP64, then rounded
-        const double off[4] = {rho0, 0.0, 0.0, T0};
-        for (int k = 0; k < 4; ++k) {
-            g.st_lo[k] = (float)(S.state_lo[k] - off[k]);
-            g.st_hi[k] = (float)(S.state_hi[k] - off[k]);
-        }
-        const bool dlo = S.kind_lo == MRTFD_BC_DIRICHLET, dhi = S.kind_hi == MRTFD_BC_DIRICHLET;
-        std::memset(g.feq_lo, 0, sizeof g.feq_lo);
-        std::memset(g.feq_hi, 0, sizeof g.feq_hi);
-        if (dlo) {
-            feq_host(m, S.state_lo[0], S.state_lo[1], S.state_lo[2], S.state_lo[3], fe);
-            for (int q = 0; q < NQ; ++q) g.feq_lo[q] = (float)(fe[q] - c->fref[q]);
-        }
-        if (dhi) {
-            feq_host(m, S.state_hi[0], S.state_hi[1], S.state_hi[2], S.state_hi[3], fe);
-            for (int q = 0; q < NQ; ++q) g.feq_hi[q] = (float)(fe[q] - c->fref[q]);
-        }
-    }
+    fill_ghosts(m, *p, c->fref, c->ws + L.kcopy, c->ws + L.gcopy, c->ws + L.fcopy, c->G);
+    fill_ghosts(m, *p, c->fref, c->ws + L.kcopy, c->ws + L.gcopy, c->ws + L.fcopy, c->G64);
     // default until tuned: rows kernel, one row per wave, plain stores
     c->kernel = p->kernel == MRTFD_KERNEL_SIMPLE ? MRTFD_KERNEL_SIMPLE : MRTFD_KERNEL_ROWS;
     c->seg = p->kernel == MRTFD_KERNEL_SIMPLE ? 0 : 1;
@@ -1007,6 +1041,11 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         c->kernel = MRTFD_KERNEL_MFMA;
         c->seg = 1;
         c->tuned = false;
+    }
+    if (p->precision == MRTFD_FP64) {  // the one-thread-per-node kernel, nothing to tune
+        c->kernel = MRTFD_KERNEL_SIMPLE;
+        c->seg = 0;
+        c->tuned = true;
     }
     hipError_t e = hipGetDevice(&c->device);
     // this device's copy of the library scratch (mrtfd_sums_noalloc)
@@ -1022,9 +1061,13 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_bf3, &c->h_bf3, sizeof(Bf3Ops), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->ws + L.kcopy, &c->K, sizeof(Consts), hipMemcpyHostToDevice, c->stream);
+        e = p->precision == MRTFD_FP64
+                ? hipMemcpyAsync(c->ws + L.kcopy, &c->K64, sizeof(Consts64), hipMemcpyHostToDevice, c->stream)
+                : hipMemcpyAsync(c->ws + L.kcopy, &c->K, sizeof(Consts), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->ws + L.gcopy, &c->G, sizeof(Ghosts), hipMemcpyHostToDevice, c->stream);
+        e = p->precision == MRTFD_FP64
+                ? hipMemcpyAsync(c->ws + L.gcopy, &c->G64, sizeof(Ghosts64), hipMemcpyHostToDevice, c->stream)
+                : hipMemcpyAsync(c->ws + L.gcopy, &c->G, sizeof(Ghosts), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->ws + L.fcopy, &c->FC, sizeof(FluxCoef), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1050,7 +1093,10 @@ int32_t mrtfd_init_macro(mrtfd_ctx *c, const float *rho, const float *ux, const 
     if (!rho || !ux || !uy || !T) return set_err(c, MRTFD_ERR_ARG, "init_macro: NULL field");
     HIPCHK(c, launch_zero(c->d_flag, sizeof(int), c->stream));
     c->cur = 0;
-    HIPCHK(c, launch_init(c->F, c->K, c->f[0], rho, ux, uy, T, c->d_flag, c->stream));
+    if (is64(c))
+        HIPCHK(c, launch_init(c->F, c->K64, c->f64[0], rho, ux, uy, T, c->d_flag, c->stream));
+    else
+        HIPCHK(c, launch_init(c->F, c->K, c->f[0], rho, ux, uy, T, c->d_flag, c->stream));
     HIPCHK(c, launch_counter_set(c->d_step, 0, c->stream));
     if (c->p.flux_budget)
         HIPCHK(c, launch_zero(c->flux, c->L.outflow - c->L.flux, c->stream));
@@ -1064,7 +1110,10 @@ int32_t mrtfd_set_f(mrtfd_ctx *c, const float *src)
 {
     if (!c) return MRTFD_ERR_ARG;
     if (!src) return set_err(c, MRTFD_ERR_ARG, "set_f: NULL array");
-    HIPCHK(c, launch_unpack(c->F, src, c->f[c->cur], c->stream));
+    if (is64(c))
+        HIPCHK(c, launch_unpack(c->F, src, c->f64[c->cur], c->stream));
+    else
+        HIPCHK(c, launch_unpack(c->F, src, c->f[c->cur], c->stream));
     if (c->p.flux_budget)
         HIPCHK(c, launch_zero(c->flux, c->L.outflow - c->L.flux, c->stream));
     c->budget_steps = 0;
@@ -1077,7 +1126,37 @@ int32_t mrtfd_get_f(mrtfd_ctx *c, float *dst)
     if (!c) return MRTFD_ERR_ARG;
     if (!dst) return set_err(c, MRTFD_ERR_ARG, "get_f: NULL array");
     if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "get_f before init");
-    HIPCHK(c, launch_pack(c->F, c->f[c->cur], dst, c->stream));
+    if (is64(c))
+        HIPCHK(c, launch_pack(c->F, c->f64[c->cur], dst, c->stream));
+    else
+        HIPCHK(c, launch_pack(c->F, c->f[c->cur], dst, c->stream));
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_set_f64(mrtfd_ctx *c, const double *src)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    if (!src) return set_err(c, MRTFD_ERR_ARG, "set_f64: NULL array");
+    if (is64(c))
+        HIPCHK(c, launch_unpack(c->F, src, c->f64[c->cur], c->stream));
+    else
+        HIPCHK(c, launch_unpack(c->F, src, c->f[c->cur], c->stream));
+    if (c->p.flux_budget)
+        HIPCHK(c, launch_zero(c->flux, c->L.outflow - c->L.flux, c->stream));
+    c->budget_steps = 0;
+    c->initialised = true;
+    return MRTFD_OK;
+}
+
+int32_t mrtfd_get_f64(mrtfd_ctx *c, double *dst)
+{
+    if (!c) return MRTFD_ERR_ARG;
+    if (!dst) return set_err(c, MRTFD_ERR_ARG, "get_f64: NULL array");
+    if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "get_f64 before init");
+    if (is64(c))
+        HIPCHK(c, launch_pack(c->F, c->f64[c->cur], dst, c->stream));
+    else
+        HIPCHK(c, launch_pack(c->F, c->f[c->cur], dst, c->stream));
     return MRTFD_OK;
 }
 
@@ -1115,7 +1194,10 @@ int32_t mrtfd_read_macro(mrtfd_ctx *c, float *rho, float *ux, float *uy, float *
 {
     if (!c) return MRTFD_ERR_ARG;
     if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "read_macro before init");
-    HIPCHK(c, launch_read_macro(c->F, c->K, c->f[c->cur], rho, ux, uy, T, p, c->stream));
+    if (is64(c))
+        HIPCHK(c, launch_read_macro(c->F, c->K64, c->f64[c->cur], rho, ux, uy, T, p, c->stream));
+    else
+        HIPCHK(c, launch_read_macro(c->F, c->K, c->f[c->cur], rho, ux, uy, T, p, c->stream));
     return MRTFD_OK;
 }
 
@@ -1123,7 +1205,10 @@ int32_t mrtfd_sums(mrtfd_ctx *c, double out[4])
 {
     if (!c || !out) return MRTFD_ERR_ARG;
     if (!c->initialised) return set_err(c, MRTFD_ERR_STATE, "sums before init");
-    HIPCHK(c, launch_sums(c->F, c->W, c->f[c->cur], c->partials, c->sums, c->stream));
+    if (is64(c))
+        HIPCHK(c, launch_sums(c->F, c->W, c->f64[c->cur], c->partials, c->sums, c->stream));
+    else
+        HIPCHK(c, launch_sums(c->F, c->W, c->f[c->cur], c->partials, c->sums, c->stream));
     double h[4];
     int flag = 0;
     HIPCHK(c, hipMemcpyAsync(h, c->sums, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -1146,7 +1231,10 @@ int32_t mrtfd_sums_noalloc(mrtfd_ctx *c, double *d_out)
     if (4 * nb > SCRATCH_DOUBLES)
         return set_err(c, MRTFD_ERR_ARG, "sums_noalloc: %d partial sums exceed the scratch of %d",
                        4 * nb, SCRATCH_DOUBLES);
-    HIPCHK(c, launch_sums(c->F, c->W, c->f[c->cur], c->scratch, d_out, c->stream));
+    if (is64(c))
+        HIPCHK(c, launch_sums(c->F, c->W, c->f64[c->cur], c->scratch, d_out, c->stream));
+    else
+        HIPCHK(c, launch_sums(c->F, c->W, c->f[c->cur], c->scratch, d_out, c->stream));
     return MRTFD_OK;
 }
 

@@ -12,7 +12,8 @@ namespace mrtfd {
 
 constexpr int NQ = 16;
 
-// FP32 constants of one step.  The moment transform f-hat = M f is done in two
+// Constants of one step (FP32, or FP64 in the FP64 mode).  The moment
+// transform f-hat = M f is done in two
 // stages.  Stage 1, a butterfly of adds per velocity group g (4 velocities
 // each): A_g = sum of the group, X_g / Y_g = the combinations odd in v_x /
 // v_y, Q_g = the quadrupole combination.  Stage 2, small dense blocks that
@@ -24,34 +25,38 @@ constexpr int NQ = 16;
 //   diagonal quadrupole (m6, m14) <- Q_2, Q_3.
 // The inverse is P^-1 B^-1 with the butterfly's 1/4 and 1/2 scales folded
 // into the rows of B^-1, so that the inverse butterfly is adds only.
-struct Consts {
-    float f0[4][4];   // rows m1, m4, m11, m12; columns A0..A3
-    float fx[4][4];   // rows m2, m7, m9, m15;  columns X0..X3
-    float fy[4][4];   // rows m3, m8, m10, m16; columns Y0..Y3
-    float fqa[2][2];  // rows m5, m13; columns Q0, Q1
-    float fqd[2][2];  // rows m6, m14; columns Q2, Q3
-    float i0[4][4];   // rows A'0..3; columns m1, m4, m11, m12 (scaled)
-    float ix[4][4];   // rows X'0..3; columns m2, m7, m9, m15
-    float iy[4][4];   // rows Y'0..3; columns m3, m8, m10, m16
-    float iqa[2][2];  // rows Q'0, Q'1; columns m5, m13
-    float iqd[2][2];  // rows Q'2, Q'3; columns m6, m14
+template <class Real>
+struct ConstsT {
+    Real f0[4][4];   // rows m1, m4, m11, m12; columns A0..A3
+    Real fx[4][4];   // rows m2, m7, m9, m15;  columns X0..X3
+    Real fy[4][4];   // rows m3, m8, m10, m16; columns Y0..Y3
+    Real fqa[2][2];  // rows m5, m13; columns Q0, Q1
+    Real fqd[2][2];  // rows m6, m14; columns Q2, Q3
+    Real i0[4][4];   // rows A'0..3; columns m1, m4, m11, m12 (scaled)
+    Real ix[4][4];   // rows X'0..3; columns m2, m7, m9, m15
+    Real iy[4][4];   // rows Y'0..3; columns m3, m8, m10, m16
+    Real iqa[2][2];  // rows Q'0, Q'1; columns m5, m13
+    Real iqd[2][2];  // rows Q'2, Q'3; columns m6, m14
     // collision back-map: inverse blocks times dt*s_k (nonconserved columns)
-    float c0[4][2];   // columns m11, m12
-    float cx[4][3];   // columns m7, m9, m15
-    float cy[4][3];   // columns m8, m10, m16
-    float cqa[2][2];  // columns m5, m13
-    float cqd[2][2];  // columns m6, m14
+    Real c0[4][2];   // columns m11, m12
+    Real cx[4][3];   // columns m7, m9, m15
+    Real cy[4][3];   // columns m8, m10, m16
+    Real cqa[2][2];  // columns m5, m13
+    Real cqd[2][2];  // columns m6, m14
     // Lax-Wendroff + Euler weights per population: f + cE (fE - f) + cW (fW - f)
     // + cN (fN - f) + cS (fS - f), cE = (a^2 - a)/2, cW = (a^2 + a)/2 with
     // a = v_x dt / dx (likewise N/S with b = v_y dt / dy).
-    float lw[NQ][4];  // cE, cW, cN, cS
+    Real lw[NQ][4];  // cE, cW, cN, cS
     // Reference state at rest: the copies of f hold g = f - f^eq(rho0, 0, 0,
     // T0); e0 = rho0 T0 is its energy and Te0 = T0 e0.  All zero when no
     // reference is set (g = f).
-    float rho0, T0, e0, Te0;
+    Real rho0, T0, e0, Te0;
 };
+using Consts = ConstsT<float>;
+using Consts64 = ConstsT<double>;
 
-// Device layout of one copy of f.  Rows j = -1 .. ny of 16 x `pitch` floats;
+// Device layout of one copy of f (FP32 values, FP64 in the FP64 mode: the
+// same element offsets).  Rows j = -1 .. ny of 16 x `pitch` elements;
 // column i sits at c = xoff + i (xoff = 64 keeps every interior row start
 // 256-byte aligned; the ring around the interior is padding that no kernel
 // reads), and node (i, j) of population q at
@@ -65,7 +70,7 @@ struct Field {
     int nx, ny;
     int pitch, xoff;
     long long qstride, jstride, tstride;
-    long long total;  // floats in one copy
+    long long total;  // elements in one copy
     __host__ __device__ long long col(int i) const {
         const int c = xoff + i;
         return (long long)(c >> 6) * tstride + (c & 63);
@@ -93,37 +98,46 @@ struct Bf3Ops {
 
 enum Kind { K_PERIODIC = 0, K_DIRICHLET = 1, K_REFLECT = 2, K_EXTRAPOLATE = 3, K_WALL = 4 };
 
-struct GhostSide {
+template <class Real>
+struct GhostSideT {
     int kind_lo, kind_hi;
-    float st_lo[4], st_hi[4];        // rho - rho0, u1, u2, T - T0 (host FP64, rounded)
-    float feq_lo[NQ], feq_hi[NQ];    // f^eq - f_ref of the states (host FP64, rounded)
-    double split0, split_rate;       // rule switch point along the side
-    double h;                        // node spacing along the side
+    Real st_lo[4], st_hi[4];        // rho - rho0, u1, u2, T - T0 (host FP64, rounded)
+    Real feq_lo[NQ], feq_hi[NQ];    // f^eq - f_ref of the states (host FP64, rounded)
+    double split0, split_rate;      // rule switch point along the side
+    double h;                       // node spacing along the side
 };
 
 struct FluxCoef;
 
-struct Ghosts {
-    GhostSide side[4];  // west, east, south, north
+template <class Real>
+struct GhostsT {
+    GhostSideT<Real> side[4];  // west, east, south, north
     double dt;
     int per_x, per_y;   // periodic in x (west/east) / in y (south/north)
     // device copies of the step constants and of this struct: the boundary
     // paths of the step kernels read these, so that the interior path keeps
     // the kernel arguments to itself
-    const Consts *kd;
-    const Ghosts *gd;
+    const ConstsT<Real> *kd;
+    const GhostsT<Real> *gd;
     const FluxCoef *fd;  // device copy of the outflow-budget coefficients
 };
+using GhostSide = GhostSideT<float>;
+using Ghosts = GhostsT<float>;
+using Ghosts64 = GhostsT<double>;
 
 // Launchers (mrtfd_kernels.hip).  All enqueue on `s` and return the HIP
-// status of the launch.
-hipError_t launch_init(const Field &F, const Consts &K, float *f, const float *rho,
+// status of the launch.  Those templated on Real exist for float (FP32
+// storage) and double (the FP64 mode).
+template <class Real>
+hipError_t launch_init(const Field &F, const ConstsT<Real> &K, Real *f, const float *rho,
                        const float *ux, const float *uy, const float *T, int *flag,
                        hipStream_t s);
 // One time step from fin to fout at step index *d_step + k (the boundary
 // rules read the clock from there).
-hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
-                              float *fout, const long long *d_step, int k, hipStream_t s);
+template <class Real>
+hipError_t launch_step_simple(const Field &F, const ConstsT<Real> &K, const GhostsT<Real> &G,
+                              const Real *fin, Real *fout, const long long *d_step, int k,
+                              hipStream_t s);
 // rows per wave (1 or 2); stream_stores: non-temporal stores; order: tiles
 // to XCDs in bands of tile rows (0) or of tile columns (1, when the number of
 // tile columns divides by 8; else 0).  slots != nullptr: the launch also
@@ -146,9 +160,10 @@ struct FluxCoef {
 // Per step: add each side node's outflow of (rho, j1, j2, e) to its slot
 // (slots: 4 doubles per node, west rows, east rows, south columns, north
 // columns).  Then, on demand, the per-side totals into out[16].
-hipError_t launch_face_flux(const Field &F, const Consts &K, const Ghosts &G, const FluxCoef &C,
-                            const float *fin, double *slots, const long long *d_step, int k,
-                            hipStream_t s);
+template <class Real>
+hipError_t launch_face_flux(const Field &F, const ConstsT<Real> &K, const GhostsT<Real> &G,
+                            const FluxCoef &C, const Real *fin, double *slots,
+                            const long long *d_step, int k, hipStream_t s);
 hipError_t launch_flux_totals(int nx, int ny, const double *slots, double *out, hipStream_t s);
 
 // Fill `bytes` (a multiple of 4) at p (16-byte aligned) with a 32-bit pattern,
@@ -157,7 +172,8 @@ hipError_t launch_fill(void *p, size_t bytes, unsigned pattern, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_counter_add(long long *d_step, long long n, hipStream_t s);
 hipError_t launch_counter_set(long long *d_step, long long n, hipStream_t s);
-hipError_t launch_read_macro(const Field &F, const Consts &K, const float *f, float *rho,
+template <class Real>
+hipError_t launch_read_macro(const Field &F, const ConstsT<Real> &K, const Real *f, float *rho,
                              float *ux, float *uy, float *T, float *p, hipStream_t s);
 // FP64 weights of the conserved rows m1..m4 at the 16 velocities, and the
 // reference state's share of the totals (its moments times the node count),
@@ -171,13 +187,19 @@ constexpr int SUM_BLOCKS_MAX = 1024;
 constexpr int SCRATCH_DOUBLES = 4 * SUM_BLOCKS_MAX;
 int sums_blocks(const Field &F);
 // partials: 4 * sums_blocks(F) doubles; out: 4 doubles (device).
-hipError_t launch_sums(const Field &F, const SumW &W, const float *f, double *partials,
+template <class Real>
+hipError_t launch_sums(const Field &F, const SumW &W, const Real *f, double *partials,
                        double *out, hipStream_t s);
 // Device address of the library's file-scope scratch array (SCRATCH_DOUBLES
 // doubles) on `device`, which must be the current device: looked up with
 // hipGetSymbolAddress on the first call per device and kept.
 hipError_t scratch_address(int device, double **out);
-hipError_t launch_pack(const Field &F, const float *f, float *dst, hipStream_t s);
+// Stored values between a copy of f and a packed [16][ny][nx] array of the
+// same or the other precision (Src -> Dst, rounded to nearest where narrower).
+template <class Src, class Dst>
+hipError_t launch_pack(const Field &F, const Src *f, Dst *dst, hipStream_t s);
+template <class Src, class Dst>
+hipError_t launch_unpack(const Field &F, const Src *src, Dst *f, hipStream_t s);
 
 // ------------------------------------------------------------------ tubes
 // Batched independent tubes: tube k has n columns and TUBE_ROWS rows,
@@ -216,6 +238,5 @@ hipError_t launch_tube_macro(const TubeGrid &T, const Consts &K, const TubeInfo 
                              float *p, hipStream_t s);
 hipError_t launch_tube_pack(const TubeGrid &T, const TubeInfo *tubes, int tube, int n,
                             const float *f, float *dst, hipStream_t s);
-hipError_t launch_unpack(const Field &F, const float *src, float *f, hipStream_t s);
 
 }  // namespace mrtfd

@@ -24,15 +24,16 @@ namespace mrtfd {
 namespace {
 
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // ---------------------------------------------------------------- transforms
 
 // Stage 1 of f-hat = M f for one velocity group (see Consts).
-template <bool AXIS>
-__device__ __forceinline__ void group_fwd(float q0, float q1, float q2, float q3, float &A,
-                                          float &X, float &Y, float &Q)
+template <bool AXIS, class Real>
+__device__ __forceinline__ void group_fwd(Real q0, Real q1, Real q2, Real q3, Real &A,
+                                          Real &X, Real &Y, Real &Q)
 {
-    const float s02 = q0 + q2, d02 = q0 - q2, s13 = q1 + q3, d13 = q1 - q3;
+    const Real s02 = q0 + q2, d02 = q0 - q2, s13 = q1 + q3, d13 = q1 - q3;
     A = s02 + s13;
     Q = s02 - s13;
     if (AXIS) {  // (+,0),(0,+),(-,0),(0,-)
@@ -45,18 +46,18 @@ __device__ __forceinline__ void group_fwd(float q0, float q1, float q2, float q3
 }
 
 // Inverse butterfly of one group (scales already folded into A, X, Y, Q).
-template <bool AXIS>
-__device__ __forceinline__ void group_inv(float A, float X, float Y, float Q, float &q0, float &q1,
-                                          float &q2, float &q3)
+template <bool AXIS, class Real>
+__device__ __forceinline__ void group_inv(Real A, Real X, Real Y, Real Q, Real &q0, Real &q1,
+                                          Real &q2, Real &q3)
 {
-    const float p = A + Q, m = A - Q;
+    const Real p = A + Q, m = A - Q;
     if (AXIS) {
         q0 = p + X;
         q2 = p - X;
         q1 = m + Y;
         q3 = m - Y;
     } else {
-        const float xy = X + Y, yx = Y - X;
+        const Real xy = X + Y, yx = Y - X;
         q0 = p + xy;
         q2 = p - xy;
         q1 = m + yx;
@@ -64,13 +65,15 @@ __device__ __forceinline__ void group_inv(float A, float X, float Y, float Q, fl
     }
 }
 
-__device__ __forceinline__ float dot4(const float (&w)[4], const float (&v)[4])
+template <class Real>
+__device__ __forceinline__ Real dot4(const Real (&w)[4], const Real (&v)[4])
 {
     return fma_(w[3], v[3], fma_(w[2], v[2], fma_(w[1], v[1], w[0] * v[0])));
 }
 
-__device__ __forceinline__ void butterflies(const float (&f)[NQ], float (&A)[4], float (&X)[4],
-                                            float (&Y)[4], float (&Q)[4])
+template <class Real>
+__device__ __forceinline__ void butterflies(const Real (&f)[NQ], Real (&A)[4], Real (&X)[4],
+                                            Real (&Y)[4], Real (&Q)[4])
 {
     group_fwd<true>(f[0], f[1], f[2], f[3], A[0], X[0], Y[0], Q[0]);
     group_fwd<true>(f[4], f[5], f[6], f[7], A[1], X[1], Y[1], Q[1]);
@@ -79,9 +82,10 @@ __device__ __forceinline__ void butterflies(const float (&f)[NQ], float (&A)[4],
 }
 
 // All 16 moments, m[k] = f-hat_{k+1}.
-__device__ __forceinline__ void moments(const Consts &K, const float (&f)[NQ], float (&m)[NQ])
+template <class Real>
+__device__ __forceinline__ void moments(const ConstsT<Real> &K, const Real (&f)[NQ], Real (&m)[NQ])
 {
-    float A[4], X[4], Y[4], Q[4];
+    Real A[4], X[4], Y[4], Q[4];
     butterflies(f, A, X, Y, Q);
     m[0] = dot4(K.f0[0], A);
     m[3] = dot4(K.f0[1], A);
@@ -105,10 +109,11 @@ __device__ __forceinline__ void moments(const Consts &K, const float (&f)[NQ], f
 // f_ref, f_ref = f^eq of a reference state at rest (rho0, 0, 0, T0) (all
 // zero when no reference is set, so that g = f): the moments of g are rho -
 // rho0, j_x, j_y, e - e0 with e0 = rho0 T0.
-__device__ __forceinline__ void conserved(const Consts &K, const float (&f)[NQ], float &dr,
-                                          float &jx, float &jy, float &de)
+template <class Real>
+__device__ __forceinline__ void conserved(const ConstsT<Real> &K, const Real (&f)[NQ], Real &dr,
+                                          Real &jx, Real &jy, Real &de)
 {
-    float A[4], X[4], Y[4], Q[4];
+    Real A[4], X[4], Y[4], Q[4];
     butterflies(f, A, X, Y, Q);
     dr = dot4(K.f0[0], A);
     de = dot4(K.f0[1], A);
@@ -123,31 +128,33 @@ __device__ __forceinline__ void conserved(const Consts &K, const float (&f)[NQ],
 // f-hat_11^eq = 2 e^2 / rho - |j|^4 / (4 rho^3) is nonzero, 2 rho0 T0^2, and
 // 2 e^2/rho - 2 e0^2/rho0 = (2/rho) (de (2 e0 + de) - T0 e0 dr) is formed from
 // the deviations so that its rounding scales with them.
-struct Eq {
-    float e5, e6, e7, e8, e9, e10, e11, e13, e14;
+template <class Real>
+struct EqT {
+    Real e5, e6, e7, e8, e9, e10, e11, e13, e14;
 };
 
-__device__ __forceinline__ Eq equilibria(const Consts &K, float dr, float jx, float jy, float de)
+template <class Real>
+__device__ __forceinline__ EqT<Real> equilibria(const ConstsT<Real> &K, Real dr, Real jx, Real jy, Real de)
 {
-    Eq q;
-    const float rho = K.rho0 + dr, e = K.e0 + de;
-    const float r = 1.0f / rho;  // IEEE division
-    const float ux = jx * r, uy = jy * r;
-    const float jux = jx * ux, juy = jy * uy;
-    const float P = fma_(-0.5f, jux + juy, e);
-    const float h = e + P;
-    const float uxx = ux * ux, uyy = uy * uy;
-    const float u2 = uxx + uyy;
+    EqT<Real> q;
+    const Real rho = K.rho0 + dr, e = K.e0 + de;
+    const Real r = Real(1.0) / rho;  // IEEE division
+    const Real ux = jx * r, uy = jy * r;
+    const Real jux = jx * ux, juy = jy * uy;
+    const Real P = fma_(-Real(0.5), jux + juy, e);
+    const Real h = e + P;
+    const Real uxx = ux * ux, uyy = uy * uy;
+    const Real u2 = uxx + uyy;
     q.e5 = jux - juy;                                 // (jx^2 - jy^2) / rho
     q.e6 = jx * uy;                                   // jx jy / rho
     q.e7 = h * ux;                                    // (e + P) jx / rho
     q.e8 = h * uy;                                    // (e + P) jy / rho
-    q.e9 = fma_(-3.0f, uyy, uxx) * jx;                // (jx^2 - 3 jy^2) jx / rho^2
-    q.e10 = fma_(3.0f, uxx, -uyy) * jy;               // (3 jx^2 - jy^2) jy / rho^2
-    const float dd = fma_(de, 2.0f * K.e0 + de, -(K.Te0 * dr));
-    q.e11 = fma_(2.0f * dd, r, (-0.25f * rho) * (u2 * u2));  // 2 e^2/rho - |j|^4/(4 rho^3) - 2 e0^2/rho0
-    const float er = e * r;
-    const float kap = fma_(6.0f, er, -2.0f * u2);    // (6 rho e - 2 |j|^2) / rho^2
+    q.e9 = fma_(-Real(3.0), uyy, uxx) * jx;                // (jx^2 - 3 jy^2) jx / rho^2
+    q.e10 = fma_(Real(3.0), uxx, -uyy) * jy;               // (3 jx^2 - jy^2) jy / rho^2
+    const Real dd = fma_(de, Real(2.0) * K.e0 + de, -(K.Te0 * dr));
+    q.e11 = fma_(Real(2.0) * dd, r, (-Real(0.25) * rho) * (u2 * u2));  // 2 e^2/rho - |j|^4/(4 rho^3) - 2 e0^2/rho0
+    const Real er = e * r;
+    const Real kap = fma_(Real(6.0), er, -Real(2.0) * u2);    // (6 rho e - 2 |j|^2) / rho^2
     q.e13 = kap * q.e5;
     q.e14 = kap * q.e6;
     return q;
@@ -156,15 +163,16 @@ __device__ __forceinline__ Eq equilibria(const Consts &K, float dr, float jx, fl
 // dC = dt * C of Eq. (3) for one node.  A single relaxation time (Sect. II,
 // S = I / tau) is the case of equal rates: the same arithmetic, so that
 // mass, momentum and energy stay exactly out of the back-map.
-__device__ __forceinline__ void collide(const Consts &K, const float (&f)[NQ], float (&dC)[NQ])
+template <class Real>
+__device__ __forceinline__ void collide(const ConstsT<Real> &K, const Real (&f)[NQ], Real (&dC)[NQ])
 {
-    float m[NQ];
+    Real m[NQ];
     moments(K, f, m);
-    const Eq q = equilibria(K, m[0], m[1], m[2], m[3]);
-    const float d5 = m[4] - q.e5, d6 = m[5] - q.e6, d7 = m[6] - q.e7, d8 = m[7] - q.e8;
-    const float d9 = m[8] - q.e9, d10 = m[9] - q.e10, d11 = m[10] - q.e11, d12 = m[11];
-    const float d13 = m[12] - q.e13, d14 = m[13] - q.e14, d15 = m[14], d16 = m[15];
-    float A[4], X[4], Y[4], Q[4];
+    const EqT<Real> q = equilibria(K, m[0], m[1], m[2], m[3]);
+    const Real d5 = m[4] - q.e5, d6 = m[5] - q.e6, d7 = m[6] - q.e7, d8 = m[7] - q.e8;
+    const Real d9 = m[8] - q.e9, d10 = m[9] - q.e10, d11 = m[10] - q.e11, d12 = m[11];
+    const Real d13 = m[12] - q.e13, d14 = m[13] - q.e14, d15 = m[14], d16 = m[15];
+    Real A[4], X[4], Y[4], Q[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         A[g] = fma_(K.c0[g][1], d12, K.c0[g][0] * d11);
@@ -183,14 +191,15 @@ __device__ __forceinline__ void collide(const Consts &K, const float (&f)[NQ], f
 
 // g^eq = M^-1 (f-hat^eq - f-hat_ref) from the conserved moments as
 // deviations (dr = rho - rho0, j, de = e - e0): initial and boundary nodes.
-__device__ __forceinline__ void feq_of_moments(const Consts &K, float dr, float jx, float jy,
-                                               float de, float (&f)[NQ])
+template <class Real>
+__device__ __forceinline__ void feq_of_moments(const ConstsT<Real> &K, Real dr, Real jx, Real jy,
+                                               Real de, Real (&f)[NQ])
 {
-    const Eq q = equilibria(K, dr, jx, jy, de);
-    const float h0[4] = {dr, de, q.e11, 0.0f};
-    const float hx[4] = {jx, q.e7, q.e9, 0.0f};
-    const float hy[4] = {jy, q.e8, q.e10, 0.0f};
-    float A[4], X[4], Y[4], Q[4];
+    const EqT<Real> q = equilibria(K, dr, jx, jy, de);
+    const Real h0[4] = {dr, de, q.e11, Real(0.0)};
+    const Real hx[4] = {jx, q.e7, q.e9, Real(0.0)};
+    const Real hy[4] = {jy, q.e8, q.e10, Real(0.0)};
+    Real A[4], X[4], Y[4], Q[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         A[g] = dot4(K.i0[g], h0);
@@ -210,24 +219,26 @@ __device__ __forceinline__ void feq_of_moments(const Consts &K, float dr, float 
 // g^eq of a macroscopic state given as (rho - rho0, u1, u2, T - T0): initial
 // and boundary nodes.  e - e0 = rho T - rho0 T0 + rho |u|^2 / 2 = rho0 (T - T0)
 // + (rho - rho0) T + rho |u|^2 / 2.
-__device__ __forceinline__ void feq_velocity(const Consts &K, float dr, float ux, float uy,
-                                             float dT, float (&f)[NQ])
+template <class Real>
+__device__ __forceinline__ void feq_velocity(const ConstsT<Real> &K, Real dr, Real ux, Real uy,
+                                             Real dT, Real (&f)[NQ])
 {
-    const float rho = K.rho0 + dr, T = K.T0 + dT;
-    const float jx = rho * ux, jy = rho * uy;
-    const float de = fma_(0.5f * rho, fma_(ux, ux, uy * uy), fma_(dr, T, K.rho0 * dT));
+    const Real rho = K.rho0 + dr, T = K.T0 + dT;
+    const Real jx = rho * ux, jy = rho * uy;
+    const Real de = fma_(Real(0.5) * rho, fma_(ux, ux, uy * uy), fma_(dr, T, K.rho0 * dT));
     feq_of_moments(K, dr, jx, jy, de, f);
 }
 
 // (rho - rho0, u1, u2, T - T0) of one node's stored populations:
 // T - T0 = (P - T0 rho) / rho = (de - T0 dr - |j|^2 / (2 rho)) / rho.
-__device__ __forceinline__ void macro_of(const Consts &K, const float (&f)[NQ], float (&q)[4])
+template <class Real>
+__device__ __forceinline__ void macro_of(const ConstsT<Real> &K, const Real (&f)[NQ], Real (&q)[4])
 {
-    float dr, jx, jy, de;
+    Real dr, jx, jy, de;
     conserved(K, f, dr, jx, jy, de);
-    const float r = 1.0f / (K.rho0 + dr);
-    const float ux = jx * r, uy = jy * r;
-    const float dP = fma_(-0.5f, jx * ux + jy * uy, fma_(-K.T0, dr, de));
+    const Real r = Real(1.0) / (K.rho0 + dr);
+    const Real ux = jx * r, uy = jy * r;
+    const Real dP = fma_(-Real(0.5), jx * ux + jy * uy, fma_(-K.T0, dr, de));
     q[0] = dr;
     q[1] = ux;
     q[2] = uy;
@@ -346,7 +357,7 @@ __device__ __forceinline__ void collide_bf3(const Consts &K, const uint4 (*bt)[4
     const f32x4 mx = block_fwd(bt[1][row], X);  // j_x, m7, m9, m15
     const f32x4 my = block_fwd(bt[2][row], Y);  // j_y, m8, m10, m16
     const f32x4 mq = block_fwd(bt[3][row], Q);  // m5, m13, m6, m14
-    const Eq q = equilibria(K, m0[0], mx[0], my[0], m0[1]);
+    const EqT<float> q = equilibria(K, m0[0], mx[0], my[0], m0[1]);
     const float va[4] = {m0[2] - q.e11, m0[3], 0.f, 0.f};              // d11, d12
     const float vx[4] = {mx[1] - q.e7, mx[2] - q.e9, mx[3], 0.f};      // d7, d9, d15
     const float vy[4] = {my[1] - q.e8, my[2] - q.e10, my[3], 0.f};     // d8, d10, d16
@@ -370,11 +381,11 @@ __host__ __device__ constexpr bool has_y(int q) { return q >= 8 || (q % 2) == 1;
 // collision) is summed first and added to the node's value last, so that
 // only that final addition rounds at the scale of the stored value; the
 // others round at the scale of the increment.
-template <int Q>
-__device__ __forceinline__ float lw_update(const Consts &K, float fc, float dC, float fE, float fW,
-                                           float fN, float fS)
+template <int Q, class Real>
+__device__ __forceinline__ Real lw_update(const ConstsT<Real> &K, Real fc, Real dC, Real fE, Real fW,
+                                           Real fN, Real fS)
 {
-    float r = -dC;
+    Real r = -dC;
     if (has_x(Q)) {
         r = fma_(K.lw[Q][0], fE - fc, r);
         r = fma_(K.lw[Q][1], fW - fc, r);
@@ -414,12 +425,12 @@ struct Unroll<0> {
 // the next node inward, at time t.  The rule switches from kind_lo to kind_hi
 // where the ghost's along-side coordinate passes split0 + split_rate t; that
 // comparison is done in FP64.
-template <int SD>
-__device__ __forceinline__ void ghost_of(const Consts &K, const Ghosts &G, double t, int a,
-                                         const float (&n1)[NQ], const float (&n2)[NQ],
-                                         float (&out)[NQ])
+template <int SD, class Real>
+__device__ __forceinline__ void ghost_of(const ConstsT<Real> &K, const GhostsT<Real> &G, double t, int a,
+                                         const Real (&n1)[NQ], const Real (&n2)[NQ],
+                                         Real (&out)[NQ])
 {
-    const GhostSide &S = G.side[SD];
+    const GhostSideT<Real> &S = G.side[SD];
     const double split = S.split0 + S.split_rate * t;
     const bool lo = ((double)a + 0.5) * S.h <= split;
     const int kind = lo ? S.kind_lo : S.kind_hi;
@@ -428,7 +439,7 @@ __device__ __forceinline__ void ghost_of(const Consts &K, const Ghosts &G, doubl
         for (int q = 0; q < NQ; ++q) out[q] = lo ? S.feq_lo[q] : S.feq_hi[q];
         return;
     }
-    float q1[4], st[4];
+    Real q1[4], st[4];
     macro_of(K, n1, q1);
     if (kind == K_REFLECT) {
         st[0] = q1[0];
@@ -436,11 +447,11 @@ __device__ __forceinline__ void ghost_of(const Consts &K, const Ghosts &G, doubl
         st[2] = SD < 2 ? q1[2] : -q1[2];
         st[3] = q1[3];
     } else if (kind == K_EXTRAPOLATE) {
-        float q2[4];
+        Real q2[4];
         macro_of(K, n2, q2);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) st[c] = fma_(2.0f, q1[c], -q2[c]);
-        if (!(K.rho0 + st[0] > 0.f) || !(K.T0 + st[3] > 0.f)) {
+        for (int c = 0; c < 4; ++c) st[c] = fma_(Real(2.0), q1[c], -q2[c]);
+        if (!(K.rho0 + st[0] > Real(0.)) || !(K.T0 + st[3] > Real(0.))) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) st[c] = q1[c];
         }
@@ -459,22 +470,23 @@ __device__ __forceinline__ void ghost_of(const Consts &K, const Ghosts &G, doubl
 // boundary rule handled.  The Lax-Wendroff terms are added in the order east,
 // west, north, south for every population, the order lw_update uses, so all
 // kernel variants agree bit for bit.
-__device__ __forceinline__ void node_update(const Field &F, const Consts &K, const Ghosts &G,
-                                            const float *__restrict__ fin,
-                                            float *__restrict__ fout, int i, int j, double t)
+template <class Real>
+__device__ __forceinline__ void node_update(const Field &F, const ConstsT<Real> &K, const GhostsT<Real> &G,
+                                            const Real *__restrict__ fin,
+                                            Real *__restrict__ fout, int i, int j, double t)
 {
     const int nx = F.nx, ny = F.ny;
-    float fc[NQ], out[NQ];
+    Real fc[NQ], out[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) fc[q] = fin[F.at(q, i, j)];
     {
-        float dC[NQ];
+        Real dC[NQ];
         collide(K, fc, dC);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) out[q] = -dC[q];  // the increment, as in lw_update
     }
     if (i == nx - 1 && !G.per_x) {
-        float n2[NQ], g[NQ];
+        Real n2[NQ], g[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) n2[q] = fin[F.at(q, i - 1, j)];
         ghost_of<1>(K, G, t, j, fc, n2, g);
@@ -488,7 +500,7 @@ __device__ __forceinline__ void node_update(const Field &F, const Consts &K, con
             if (has_x(q)) out[q] = fma_(K.lw[q][0], fin[F.at(q, ie, j)] - fc[q], out[q]);
     }
     if (i == 0 && !G.per_x) {
-        float n2[NQ], g[NQ];
+        Real n2[NQ], g[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) n2[q] = fin[F.at(q, i + 1, j)];
         ghost_of<0>(K, G, t, j, fc, n2, g);
@@ -502,7 +514,7 @@ __device__ __forceinline__ void node_update(const Field &F, const Consts &K, con
             if (has_x(q)) out[q] = fma_(K.lw[q][1], fin[F.at(q, iw, j)] - fc[q], out[q]);
     }
     if (j == ny - 1 && !G.per_y) {
-        float n2[NQ], g[NQ];
+        Real n2[NQ], g[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) n2[q] = fin[F.at(q, i, j - 1)];
         ghost_of<3>(K, G, t, i, fc, n2, g);
@@ -516,7 +528,7 @@ __device__ __forceinline__ void node_update(const Field &F, const Consts &K, con
             if (has_y(q)) out[q] = fma_(K.lw[q][2], fin[F.at(q, i, jn)] - fc[q], out[q]);
     }
     if (j == 0 && !G.per_y) {
-        float n2[NQ], g[NQ];
+        Real n2[NQ], g[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) n2[q] = fin[F.at(q, i, j + 1)];
         ghost_of<2>(K, G, t, i, fc, n2, g);
@@ -533,16 +545,18 @@ __device__ __forceinline__ void node_update(const Field &F, const Consts &K, con
     for (int q = 0; q < NQ; ++q) fout[F.at(q, i, j)] = fc[q] + out[q];
 }
 
-__device__ __forceinline__ double step_time(const Ghosts &G, const long long *d_step, int k)
+template <class Real>
+__device__ __forceinline__ double step_time(const GhostsT<Real> &G, const long long *d_step, int k)
 {
     return (double)(*d_step + k) * G.dt;
 }
 
 // One thread per node, 64x4 nodes per block; neighbours read straight from
 // global memory (the caches absorb the re-reads).
-__global__ __launch_bounds__(256) void k_step_simple(Field F, Consts K, Ghosts G,
-                                                     const float *__restrict__ fin,
-                                                     float *__restrict__ fout,
+template <class Real>
+__global__ __launch_bounds__(256) void k_step_simple(Field F, ConstsT<Real> K, GhostsT<Real> G,
+                                                     const Real *__restrict__ fin,
+                                                     Real *__restrict__ fout,
                                                      const long long *__restrict__ d_step, int k)
 {
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -715,8 +729,10 @@ __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const
     }
 }
 
-__device__ __forceinline__ void face_flux_node(const Field &F, const Consts &K, const Ghosts &G,
-                                               const FluxCoef &C, const float *__restrict__ fin,
+template <class Real>
+__device__ __forceinline__ void face_flux_node(const Field &F, const ConstsT<Real> &K,
+                                               const GhostsT<Real> &G, const FluxCoef &C,
+                                               const Real *__restrict__ fin,
                                                double *__restrict__ slots,
                                                const long long *__restrict__ d_step, int k, int t);
 
@@ -969,7 +985,8 @@ __global__ __launch_bounds__(256) void k_tube_pack(TubeGrid TG, const TubeInfo *
 
 // ------------------------------------------------------------ other kernels
 
-__global__ __launch_bounds__(256) void k_init(Field F, Consts K, float *__restrict__ f,
+template <class Real>
+__global__ __launch_bounds__(256) void k_init(Field F, ConstsT<Real> K, Real *__restrict__ f,
                                               const float *__restrict__ rho,
                                               const float *__restrict__ ux,
                                               const float *__restrict__ uy,
@@ -983,8 +1000,8 @@ __global__ __launch_bounds__(256) void k_init(Field F, Consts K, float *__restri
     if (!(r > 0.f) || !(t > 0.f) || !isfinite(ux[c]) || !isfinite(uy[c]) || !isfinite(r) ||
         !isfinite(t))
         atomicOr(flag, 1);
-    float fe[NQ];
-    feq_velocity(K, r - K.rho0, ux[c], uy[c], t - K.T0, fe);
+    Real fe[NQ];
+    feq_velocity(K, Real(r) - K.rho0, Real(ux[c]), Real(uy[c]), Real(t) - K.T0, fe);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) f[F.at(q, i, j)] = fe[q];
 }
@@ -1011,31 +1028,34 @@ __global__ void k_counter(long long *d_step, long long n, int set)
     }
 }
 
-__global__ __launch_bounds__(256) void k_read_macro(Field F, Consts K, const float *__restrict__ f,
-                                                    float *rho, float *ux, float *uy, float *T,
-                                                    float *p)
+// Readout in the stored precision, written as FP32 fields.
+template <class Real>
+__global__ __launch_bounds__(256) void k_read_macro(Field F, ConstsT<Real> K,
+                                                    const Real *__restrict__ f, float *rho,
+                                                    float *ux, float *uy, float *T, float *p)
 {
     const long long n = (long long)F.nx * F.ny;
     const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
     if (c >= n) return;
     const int i = (int)(c % F.nx), j = (int)(c / F.nx);
-    float fc[NQ], q[4];
+    Real fc[NQ], q[4];
 #pragma unroll
     for (int k = 0; k < NQ; ++k) fc[k] = f[F.at(k, i, j)];
     macro_of(K, fc, q);
-    const float rh = K.rho0 + q[0], tt = K.T0 + q[3];
-    if (rho) rho[c] = rh;
-    if (ux) ux[c] = q[1];
-    if (uy) uy[c] = q[2];
-    if (T) T[c] = tt;
-    if (p) p[c] = rh * tt;
+    const Real rh = K.rho0 + q[0], tt = K.T0 + q[3];
+    if (rho) rho[c] = (float)rh;
+    if (ux) ux[c] = (float)q[1];
+    if (uy) uy[c] = (float)q[2];
+    if (T) T[c] = (float)tt;
+    if (p) p[c] = (float)(rh * tt);
 }
 
 
 // FP64 sums of rho, j_x, j_y, e.  Each thread walks a fixed set of nodes,
 // then a fixed-order tree reduction per block; a second kernel adds the block
 // partials in order.  The result is independent of timing.
-__global__ __launch_bounds__(256) void k_sums_partial(Field F, SumW W, const float *__restrict__ f,
+template <class Real>
+__global__ __launch_bounds__(256) void k_sums_partial(Field F, SumW W, const Real *__restrict__ f,
                                                       double *partials)
 {
     __shared__ double sh[4][256];
@@ -1094,8 +1114,10 @@ __global__ __launch_bounds__(256) void k_sums_final(const double *__restrict__ p
 // the FP32 populations and added to the thread's own slot, so the totals do
 // not depend on scheduling.  Periodic faces are counted on both sides with
 // equal and opposite values.
-__device__ __forceinline__ void face_flux_node(const Field &F, const Consts &K, const Ghosts &G,
-                                               const FluxCoef &C, const float *__restrict__ fin,
+template <class Real>
+__device__ __forceinline__ void face_flux_node(const Field &F, const ConstsT<Real> &K,
+                                               const GhostsT<Real> &G, const FluxCoef &C,
+                                               const Real *__restrict__ fin,
                                                double *__restrict__ slots,
                                                const long long *__restrict__ d_step, int k, int t)
 {
@@ -1117,7 +1139,7 @@ __device__ __forceinline__ void face_flux_node(const Field &F, const Consts &K, 
     else if (sd == 1) i1 = nx - 1, i2 = nx - 2, j1 = j2 = a;
     else if (sd == 2) j1 = 0, j2 = 1, i1 = i2 = a;
     else j1 = ny - 1, j2 = ny - 2, i1 = i2 = a;
-    float n1[NQ], n2[NQ], g[NQ];
+    Real n1[NQ], n2[NQ], g[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) n1[q] = fin[F.at(q, i1, j1)];
     const bool per = sd < 2 ? G.per_x : G.per_y;
@@ -1155,8 +1177,9 @@ __device__ __forceinline__ void face_flux_node(const Field &F, const Consts &K, 
     for (int m = 0; m < 4; ++m) sl[m] += acc[m];
 }
 
-__global__ __launch_bounds__(256) void k_face_flux(Field F, Consts K, Ghosts G, FluxCoef C,
-                                                   const float *__restrict__ fin,
+template <class Real>
+__global__ __launch_bounds__(256) void k_face_flux(Field F, ConstsT<Real> K, GhostsT<Real> G,
+                                                   FluxCoef C, const Real *__restrict__ fin,
                                                    double *__restrict__ slots,
                                                    const long long *__restrict__ d_step, int k)
 {
@@ -1190,26 +1213,28 @@ __global__ __launch_bounds__(256) void k_flux_totals(int nx, int ny,
     if (threadIdx.x < 4) out[4 * sd + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(256) void k_pack(Field F, const float *__restrict__ f,
-                                              float *__restrict__ dst)
+template <class Src, class Dst>
+__global__ __launch_bounds__(256) void k_pack(Field F, const Src *__restrict__ f,
+                                              Dst *__restrict__ dst)
 {
     const long long n = (long long)F.nx * F.ny;
     const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
     const int q = blockIdx.y;
     if (c >= n) return;
     const int i = (int)(c % F.nx), j = (int)(c / F.nx);
-    dst[(long long)q * n + c] = f[F.at(q, i, j)];
+    dst[(long long)q * n + c] = (Dst)f[F.at(q, i, j)];
 }
 
-__global__ __launch_bounds__(256) void k_unpack(Field F, const float *__restrict__ src,
-                                                float *__restrict__ f)
+template <class Src, class Dst>
+__global__ __launch_bounds__(256) void k_unpack(Field F, const Src *__restrict__ src,
+                                                Dst *__restrict__ f)
 {
     const long long n = (long long)F.nx * F.ny;
     const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
     const int q = blockIdx.y;
     if (c >= n) return;
     const int i = (int)(c % F.nx), j = (int)(c / F.nx);
-    f[F.at(q, i, j)] = src[(long long)q * n + c];
+    f[F.at(q, i, j)] = (Dst)src[(long long)q * n + c];
 }
 
 inline unsigned blocks_for(long long n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -1218,19 +1243,22 @@ inline unsigned blocks_for(long long n, int per) { return (unsigned)((n + per - 
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_init(const Field &F, const Consts &K, float *f, const float *rho, const float *ux,
-                       const float *uy, const float *T, int *flag, hipStream_t s)
+template <class Real>
+hipError_t launch_init(const Field &F, const ConstsT<Real> &K, Real *f, const float *rho,
+                       const float *ux, const float *uy, const float *T, int *flag, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_init, dim3(blocks_for((long long)F.nx * F.ny, 256)), dim3(256), 0, s, F,
-                       K, f, rho, ux, uy, T, flag);
+    hipLaunchKernelGGL((k_init<Real>), dim3(blocks_for((long long)F.nx * F.ny, 256)), dim3(256), 0,
+                       s, F, K, f, rho, ux, uy, T, flag);
     return hipGetLastError();
 }
 
-hipError_t launch_step_simple(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
-                              float *fout, const long long *d_step, int k, hipStream_t s)
+template <class Real>
+hipError_t launch_step_simple(const Field &F, const ConstsT<Real> &K, const GhostsT<Real> &G,
+                              const Real *fin, Real *fout, const long long *d_step, int k,
+                              hipStream_t s)
 {
     dim3 grid(blocks_for(F.nx, 64), blocks_for(F.ny, 4));
-    hipLaunchKernelGGL(k_step_simple, grid, dim3(256), 0, s, F, K, G, fin, fout, d_step, k);
+    hipLaunchKernelGGL((k_step_simple<Real>), grid, dim3(256), 0, s, F, K, G, fin, fout, d_step, k);
     return hipGetLastError();
 }
 
@@ -1310,11 +1338,12 @@ hipError_t launch_counter_set(long long *d_step, long long n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_read_macro(const Field &F, const Consts &K, const float *f, float *rho,
+template <class Real>
+hipError_t launch_read_macro(const Field &F, const ConstsT<Real> &K, const Real *f, float *rho,
                              float *ux, float *uy, float *T, float *p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_read_macro, dim3(blocks_for((long long)F.nx * F.ny, 256)), dim3(256), 0,
-                       s, F, K, f, rho, ux, uy, T, p);
+    hipLaunchKernelGGL((k_read_macro<Real>), dim3(blocks_for((long long)F.nx * F.ny, 256)),
+                       dim3(256), 0, s, F, K, f, rho, ux, uy, T, p);
     return hipGetLastError();
 }
 
@@ -1325,11 +1354,12 @@ int sums_blocks(const Field &F)
     return (int)(b < SUM_BLOCKS_MAX ? b : SUM_BLOCKS_MAX);
 }
 
-hipError_t launch_sums(const Field &F, const SumW &W, const float *f, double *partials,
+template <class Real>
+hipError_t launch_sums(const Field &F, const SumW &W, const Real *f, double *partials,
                        double *out, hipStream_t s)
 {
     const int nb = sums_blocks(F);
-    hipLaunchKernelGGL(k_sums_partial, dim3(nb), dim3(256), 0, s, F, W, f, partials);
+    hipLaunchKernelGGL((k_sums_partial<Real>), dim3(nb), dim3(256), 0, s, F, W, f, partials);
     hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s, partials, nb, W, out);
     return hipGetLastError();
 }
@@ -1366,13 +1396,14 @@ hipError_t scratch_address(int device, double **out)
     return hipSuccess;
 }
 
-hipError_t launch_face_flux(const Field &F, const Consts &K, const Ghosts &G, const FluxCoef &C,
-                            const float *fin, double *slots, const long long *d_step, int k,
-                            hipStream_t s)
+template <class Real>
+hipError_t launch_face_flux(const Field &F, const ConstsT<Real> &K, const GhostsT<Real> &G,
+                            const FluxCoef &C, const Real *fin, double *slots,
+                            const long long *d_step, int k, hipStream_t s)
 {
     const long long n = 2LL * (F.nx + F.ny);
-    hipLaunchKernelGGL(k_face_flux, dim3(blocks_for(n, 256)), dim3(256), 0, s, F, K, G, C, fin,
-                       slots, d_step, k);
+    hipLaunchKernelGGL((k_face_flux<Real>), dim3(blocks_for(n, 256)), dim3(256), 0, s, F, K, G, C,
+                       fin, slots, d_step, k);
     return hipGetLastError();
 }
 
@@ -1382,19 +1413,50 @@ hipError_t launch_flux_totals(int nx, int ny, const double *slots, double *out, 
     return hipGetLastError();
 }
 
-hipError_t launch_pack(const Field &F, const float *f, float *dst, hipStream_t s)
+template <class Src, class Dst>
+hipError_t launch_pack(const Field &F, const Src *f, Dst *dst, hipStream_t s)
 {
     dim3 grid(blocks_for((long long)F.nx * F.ny, 256), NQ);
-    hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, s, F, f, dst);
+    hipLaunchKernelGGL((k_pack<Src, Dst>), grid, dim3(256), 0, s, F, f, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_unpack(const Field &F, const float *src, float *f, hipStream_t s)
+template <class Src, class Dst>
+hipError_t launch_unpack(const Field &F, const Src *src, Dst *f, hipStream_t s)
 {
     dim3 grid(blocks_for((long long)F.nx * F.ny, 256), NQ);
-    hipLaunchKernelGGL(k_unpack, grid, dim3(256), 0, s, F, src, f);
+    hipLaunchKernelGGL((k_unpack<Src, Dst>), grid, dim3(256), 0, s, F, src, f);
     return hipGetLastError();
 }
+
+// The launchers' FP32 and FP64 forms.
+#define MRTFD_REAL_LAUNCHERS(Real)                                                                 \
+    template hipError_t launch_init<Real>(const Field &, const ConstsT<Real> &, Real *,            \
+                                          const float *, const float *, const float *,             \
+                                          const float *, int *, hipStream_t);                      \
+    template hipError_t launch_step_simple<Real>(const Field &, const ConstsT<Real> &,             \
+                                                 const GhostsT<Real> &, const Real *, Real *,      \
+                                                 const long long *, int, hipStream_t);             \
+    template hipError_t launch_read_macro<Real>(const Field &, const ConstsT<Real> &, const Real *, \
+                                                float *, float *, float *, float *, float *,       \
+                                                hipStream_t);                                      \
+    template hipError_t launch_sums<Real>(const Field &, const SumW &, const Real *, double *,     \
+                                          double *, hipStream_t);                                  \
+    template hipError_t launch_face_flux<Real>(const Field &, const ConstsT<Real> &,               \
+                                               const GhostsT<Real> &, const FluxCoef &,            \
+                                               const Real *, double *, const long long *, int,     \
+                                               hipStream_t);
+MRTFD_REAL_LAUNCHERS(float)
+MRTFD_REAL_LAUNCHERS(double)
+#undef MRTFD_REAL_LAUNCHERS
+template hipError_t launch_pack<float, float>(const Field &, const float *, float *, hipStream_t);
+template hipError_t launch_pack<float, double>(const Field &, const float *, double *, hipStream_t);
+template hipError_t launch_pack<double, float>(const Field &, const double *, float *, hipStream_t);
+template hipError_t launch_pack<double, double>(const Field &, const double *, double *, hipStream_t);
+template hipError_t launch_unpack<float, float>(const Field &, const float *, float *, hipStream_t);
+template hipError_t launch_unpack<float, double>(const Field &, const float *, double *, hipStream_t);
+template hipError_t launch_unpack<double, float>(const Field &, const double *, float *, hipStream_t);
+template hipError_t launch_unpack<double, double>(const Field &, const double *, double *, hipStream_t);
 
 // ------------------------------------------------------------ tube launchers
 

@@ -13,7 +13,7 @@ KERNELS = {"auto": _abi.MRTFD_KERNEL_AUTO, "simple": _abi.MRTFD_KERNEL_SIMPLE,
            "rows": _abi.MRTFD_KERNEL_ROWS}
 KERNEL_NAMES = {_abi.MRTFD_KERNEL_SIMPLE: "simple", _abi.MRTFD_KERNEL_ROWS: "rows",
                 _abi.MRTFD_KERNEL_MFMA: "mfma"}
-PRECISIONS = {"fp32": _abi.MRTFD_FP32, "bf16x3": _abi.MRTFD_BF16X3}
+PRECISIONS = {"fp32": _abi.MRTFD_FP32, "bf16x3": _abi.MRTFD_BF16X3, "fp64": _abi.MRTFD_FP64}
 
 
 COLLISIONS = {"mrt": _abi.MRTFD_COLLISION_MRT, "srt": _abi.MRTFD_COLLISION_SRT}
@@ -168,12 +168,32 @@ class MRT2D:
         self.stream.synchronize()
         return f.cpu().numpy()
 
+    def get_f64(self):
+        """The stored values as a device FP64 tensor (exact in the FP64 mode)."""
+        t = self.torch
+        f = t.empty((16, self.ny, self.nx), dtype=t.float64, device=self.device)
+        check(lib().mrtfd_get_f64(self._ctx, self._ptr(f)), self._ctx)
+        return f
+
+    def get_f64_numpy(self):
+        f = self.get_f64()
+        self.stream.synchronize()
+        return f.cpu().numpy()
+
+    def set_f64(self, f):
+        t = self.torch
+        if isinstance(f, np.ndarray):
+            f = t.from_numpy(np.ascontiguousarray(f, dtype=np.float64))
+        a = f.to(device=self.device, dtype=t.float64).contiguous().reshape(16, self.ny, self.nx)
+        self._keep = [a]
+        check(lib().mrtfd_set_f64(self._ctx, self._ptr(a)), self._ctx)
+
     def ref_populations(self):
         return ref_populations(self.p)
 
     def populations_numpy(self):
         """f = g + f_ref in FP64, [16][ny][nx]."""
-        return self.get_f_numpy().astype(np.float64) + self.ref_populations()[:, None, None]
+        return self.get_f64_numpy() + self.ref_populations()[:, None, None]
 
     def set_f(self, f):
         a = self._dev(f).reshape(16, self.ny, self.nx)

@@ -2,14 +2,14 @@
 oracle.  Each case draws a grid size (inside one tile, ragged, several
 tiles), a boundary rule per side (periodic pairs, Dirichlet, reflecting,
 extrapolating, walls, and two-rule sides whose switch point moves by a few
-cells over the run), random rates s5..s16, a reference state or none, FP32 or
-the matrix-core collision, a kernel variant and a population layout, and
+cells over the run), random rates s5..s16, a reference state or none, FP32,
+the matrix-core collision or FP64, a kernel variant and a population layout, and
 starts from random populations or from smooth macroscopic fields.  The
 oracle starts from the GPU's own initial state (the stored values plus
 f_ref, in FP64) and both run n steps; every population must agree within
 n (8 u + c) S, S = transform_scale of the initial state, c = 0 in FP32 and
 2^-14 with the matrix cores (their one-step bound,
-test_gpu_parity.test_bf16x3_one_step_error_bound)."""
+test_gpu_parity.test_bf16x3_one_step_error_bound); in FP64, n 16 u64 S."""
 import math
 import os
 
@@ -72,6 +72,10 @@ def draw(seed):
                 layout=str(rng.choice(["rows", "tiles", "planes"])),
                 ref=(float(rng.uniform(0.5, 2.0)), float(rng.uniform(0.5, 2.0))) if rng.random() < 0.5 else None,
                 init="populations" if rng.random() < 0.5 else "macro", seed=int(seed))
+    if precision == "fp32" and rng.random() < 0.3:  # drawn last: the other choices stay as they were
+        case["precision"] = "fp64"
+        if case["kernel"] == "rows":
+            case["kernel"], case["rows"] = "auto", 0
     return case
 
 
@@ -98,12 +102,12 @@ def test_random_configuration_matches_oracle(gpu, seed):
                          layout=c["layout"], ref=c["ref"])
     if c["init"] == "populations":
         f0 = synth.random_populations(nx, ny, seed=seed, spread=0.3)
-        g.set_f((f0 - fr[:, None, None]).astype(np.float32))
+        g.set_f64(f0 - fr[:, None, None])
     else:
         g.init_problem(prob)
-    start = g.get_f_numpy().astype(np.float64) + fr[:, None, None]
+    start = g.get_f64_numpy() + fr[:, None, None]
     g.step(c["nsteps"])
-    got = g.get_f_numpy().astype(np.float64) + fr[:, None, None]
+    got = g.get_f64_numpy() + fr[:, None, None]
     g.close()
     o = core.Grid(prob, nthreads=THREADS)
     o.set_f(start)
@@ -111,8 +115,11 @@ def test_random_configuration_matches_oracle(gpu, seed):
     want = o.get_f()
     assert np.all(np.isfinite(got))
     S = transform_scale(prob, start)
-    extra = 2.0 ** -14 if c["precision"] == "bf16x3" else 0.0
-    bound = c["nsteps"] * (8 * U32 + extra) * S
+    if c["precision"] == "fp64":
+        bound = c["nsteps"] * 16 * 2.0 ** -53 * S
+    else:
+        extra = 2.0 ** -14 if c["precision"] == "bf16x3" else 0.0
+        bound = c["nsteps"] * (8 * U32 + extra) * S
     err = float(np.max(np.abs(got - want)))
     print(f"  max err {err:.3e}, bound {bound:.3e} ({err / bound:.3f})", flush=True)
     assert err <= bound
