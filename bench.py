@@ -101,9 +101,10 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_entry(workload, kernel, seg, streaming, tile_order, per_launch_cells, ref):
+def traffic_entry(workload, kernel, seg, streaming, tile_order, per_launch_cells, ref, precision="fp32"):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source, this workload and kernel variant."""
+    taken on the current kernel code, this workload, precision and kernel
+    variant."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -111,6 +112,7 @@ def traffic_entry(workload, kernel, seg, streaming, tile_order, per_launch_cells
         return None
     for e in rec.get("entries", []):
         if (e.get("source_sha") == kernel_sha() and e.get("workload") == workload
+                and e.get("precision", "fp32") == precision
                 and e.get("kernel") == kernel and int(e.get("rows", 0)) == int(seg)
                 and bool(e.get("streaming", False)) == bool(streaming)
                 and int(e.get("tile_order", 0)) == int(tile_order)
@@ -473,9 +475,7 @@ def main():
 
     per_node = 2 * BYTES_PER_UPDATE if args.precision == "fp64" else BYTES_PER_UPDATE
     achieved = per_node * cells / (ms_step * 1e-3) / 1e9
-    # the counter entries are FP32-stored variants (fp32 rows/simple, bf16x3 mfma)
-    traffic = None if args.precision == "fp64" else traffic_entry(W["name"], kernel, seg, streaming,
-                                                                   tile_order, cells, ref)
+    traffic = traffic_entry(W["name"], kernel, seg, streaming, tile_order, cells, ref, args.precision)
     print(f"bench: {W['name']} {steps} steps, {ms_step * 1e3:.2f} us/step, step kernel "
           f"{variant_name((kernel, seg, streaming, tile_order))}, {mlups:.0f} MLUPS, {achieved:.0f} GB/s",
           file=sys.stderr, flush=True)
