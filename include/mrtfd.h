@@ -84,8 +84,9 @@ extern "C" {
                           grid column alone in its 64-column wave takes the
                           FP32 collision)                                   */
 #define MRTFD_FP64 2   /* the whole step in FP64, populations stored in FP64
-                          (one thread per node: MRTFD_KERNEL_SIMPLE, at 256
-                          bytes of populations per node update): for states
+                          (the rows kernel at one row per wave, or the
+                          simple kernel; 256 bytes of populations per node
+                          update): for states
                           whose populations sum to far more than rho (hot
                           gas: the 16-velocity equilibrium sums to about
                           0.7 T^2 rho), where FP32 storage rounds rho by that

@@ -441,15 +441,16 @@ int check(const mrtfd_params *p, char *msg, size_t len)
         return fail(MRTFD_ERR_ARG, "grid of %lld nodes is too large", (long long)p->nx * p->ny);
     {
         // the row and matrix-core kernels address one copy of f with 32-bit
-        // byte offsets: (ny + 2) rows of 16 x pitch floats must stay below 4 GiB
+        // byte offsets: (ny + 2) rows of 16 x pitch values must stay below 4 GiB
         const long long pitch = ((long long)p->nx + 65 + 63) / 64 * 64;
-        const long long bytes = 4LL * NQ * pitch * ((long long)p->ny + 2);
-        if (bytes >= (1LL << 32) && p->kernel != MRTFD_KERNEL_SIMPLE && p->precision != MRTFD_FP64)
+        const long long esize = p->precision == MRTFD_FP64 ? 8 : 4;
+        const long long bytes = esize * NQ * pitch * ((long long)p->ny + 2);
+        if (bytes >= (1LL << 32) && p->kernel != MRTFD_KERNEL_SIMPLE)
             return fail(MRTFD_ERR_ARG,
                         "grid %d x %d needs %lld bytes per copy of f: above 4 GiB only "
-                        "MRTFD_KERNEL_SIMPLE (FP32) runs it", p->nx, p->ny, bytes);
+                        "MRTFD_KERNEL_SIMPLE runs it", p->nx, p->ny, bytes);
         if (bytes >= (1LL << 32) && p->precision == MRTFD_BF16X3)
-            return fail(MRTFD_ERR_ARG, "grids above 4 GiB per copy of FP32 values run in FP32 or FP64");
+            return fail(MRTFD_ERR_ARG, "grids above 4 GiB per copy of f run in FP32 or FP64");
     }
     if (!(p->dx > 0) || !(p->dy > 0) || !(p->dt > 0) || !std::isfinite(p->dx) ||
         !std::isfinite(p->dy) || !std::isfinite(p->dt))
@@ -464,8 +465,8 @@ int check(const mrtfd_params *p, char *msg, size_t len)
     if (cfl > 1.0) return fail(MRTFD_ERR_UNSTABLE, "Courant number 6 dt / min(dx,dy) = %g exceeds 1", cfl);
     if (p->precision != MRTFD_FP32 && p->precision != MRTFD_BF16X3 && p->precision != MRTFD_FP64)
         return fail(MRTFD_ERR_ARG, "unknown precision mode %d", p->precision);
-    if (p->precision == MRTFD_FP64 && p->kernel == MRTFD_KERNEL_ROWS)
-        return fail(MRTFD_ERR_ARG, "MRTFD_FP64 runs the one-thread-per-node kernel (kernel AUTO or SIMPLE)");
+    if (p->precision == MRTFD_FP64 && p->rows == 2)
+        return fail(MRTFD_ERR_ARG, "MRTFD_FP64 runs the rows kernel at one row per wave (rows 0 or 1)");
     if (p->collision != MRTFD_COLLISION_MRT && p->collision != MRTFD_COLLISION_SRT)
         return fail(MRTFD_ERR_ARG, "unknown collision %d", p->collision);
     if (p->collision == MRTFD_COLLISION_SRT) {
@@ -667,8 +668,13 @@ bool is64(const mrtfd_ctx *c) { return c->p.precision == MRTFD_FP64; }
 // One step from copy a to copy a ^ 1.
 hipError_t launch_step(mrtfd_ctx *c, int a, int k, hipStream_t s)
 {
-    if (is64(c))
-        return launch_step_simple(c->F, c->K64, c->G64, c->f64[a], c->f64[a ^ 1], c->d_step, k, s);
+    if (is64(c)) {
+        if (c->kernel == MRTFD_KERNEL_SIMPLE)
+            return launch_step_simple(c->F, c->K64, c->G64, c->f64[a], c->f64[a ^ 1], c->d_step, k, s);
+        return launch_step_rows(c->F, c->K64, c->G64, c->f64[a], c->f64[a ^ 1], c->seg & 15,
+                                (c->seg >> 4) & 1, (c->seg >> 5) & 1, c->d_step, k, s,
+                                budget_fused(c) ? c->flux : nullptr);
+    }
     const float *fin = c->f[a];
     float *fout = c->f[a ^ 1];
     if (c->kernel == MRTFD_KERNEL_SIMPLE)
@@ -820,7 +826,7 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
         cands.push_back({MRTFD_KERNEL_SIMPLE, 0});
     } else {
         const bool bands = ((c->p.nx + 63) / 64) % 8 == 0;
-        for (int r = 1; r <= 2; ++r) {
+        for (int r = 1; r <= (is64(c) ? 1 : 2); ++r) {
             if (c->p.rows && r != c->p.rows) continue;
             for (int o = 0; o <= (bands ? 1 : 0); ++o) {
                 cands.push_back({MRTFD_KERNEL_ROWS, r | (o << 5)});
@@ -1042,11 +1048,7 @@ int32_t mrtfd_create(const mrtfd_params *p, void *d_ws, size_t ws_bytes, void *s
         c->seg = 1;
         c->tuned = false;
     }
-    if (p->precision == MRTFD_FP64) {  // the one-thread-per-node kernel, nothing to tune
-        c->kernel = MRTFD_KERNEL_SIMPLE;
-        c->seg = 0;
-        c->tuned = true;
-    }
+
     hipError_t e = hipGetDevice(&c->device);
     // this device's copy of the library scratch (mrtfd_sums_noalloc)
     if (e == hipSuccess) e = scratch_address(c->device, &c->scratch);

@@ -145,8 +145,10 @@ hipError_t launch_step_simple(const Field &F, const ConstsT<Real> &K, const Ghos
 // its own grid (constants from the device copies G.kd, G.gd, G.fd).
 // bops != nullptr (device copy of the block table): the collision's
 // transforms in split-BF16 on the matrix cores.
-hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
-                            float *fout, int rows, int stream_stores, int order,
+// In FP64 (Real = double) one row per wave and no matrix-core collision.
+template <class Real>
+hipError_t launch_step_rows(const Field &F, const ConstsT<Real> &K, const GhostsT<Real> &G,
+                            const Real *fin, Real *fout, int rows, int stream_stores, int order,
                             const long long *d_step, int k, hipStream_t s,
                             double *slots = nullptr, const Bf3Ops *bops = nullptr);
 // Outflow budget (FP64).  cx[q] = {(dt/dx) v_qx / 2, (dt/dx) v_qx^2 dt / (2 dx)}

@@ -578,21 +578,47 @@ __device__ __forceinline__ float shl1(float v, float edge)
     return __int_as_float(
         __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xF, 0xF, false));
 }
+// The same shifts of FP64 values: both 32-bit halves move by one lane.
+__device__ __forceinline__ double shr1(double v, double edge)
+{
+    const int2 a = __builtin_bit_cast(int2, v), e = __builtin_bit_cast(int2, edge);
+    const int2 r = make_int2(__builtin_amdgcn_update_dpp(e.x, a.x, 0x138, 0xF, 0xF, false),
+                             __builtin_amdgcn_update_dpp(e.y, a.y, 0x138, 0xF, 0xF, false));
+    return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double shl1(double v, double edge)
+{
+    const int2 a = __builtin_bit_cast(int2, v), e = __builtin_bit_cast(int2, edge);
+    const int2 r = make_int2(__builtin_amdgcn_update_dpp(e.x, a.x, 0x130, 0xF, 0xF, false),
+                             __builtin_amdgcn_update_dpp(e.y, a.y, 0x130, 0xF, 0xF, false));
+    return __builtin_bit_cast(double, r);
+}
 
 // Buffer resource over one copy of f (raw buffer, byte offsets, 32-bit range
 // checked by the hardware: out-of-range loads return 0, stores are dropped).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const float *p, unsigned bytes)
+template <class Real>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const Real *p, unsigned bytes)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), 0, (int)bytes, 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<Real *>(p), 0, (int)bytes, 0x00020000);
 }
-__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+template <class Real = float>
+__device__ __forceinline__ Real bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
 {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    if constexpr (sizeof(Real) == 8)
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 template <int AUX = 0>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
 {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, AUX);
+}
+template <int AUX = 0>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, double v, unsigned voff, unsigned soff)
+{
+    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0)) b64;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64, v), r, voff, soff, AUX);
 }
 
 // Row kernel.  Each wavefront updates R consecutive rows of 64 consecutive
@@ -616,10 +642,15 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsign
 // the lane just past the last column, whose own result is not stored).  Only
 // a wave whose last column is alone in it (nx = 1 mod 64), which has no
 // second column for an east ghost, takes node_update.
+//
+// Real: the stored type, float or double (the FP64 mode: one row per wave,
+// 64-bit buffer accesses and DPP shifts of both halves, two waves per SIMD
+// with its 185 registers; held to three it spills and is slower).
 // The row kernel's path for a wave at a side of the grid (see k_step_rows).
-template <int R, int AUX, bool BF>
-__device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const Ghosts &G,
-                                          const float *__restrict__ fin, float *__restrict__ fout,
+template <int R, int AUX, bool BF, class Real>
+__device__ __forceinline__ void rows_edge(const Field &F, const ConstsT<Real> &K,
+                                          const GhostsT<Real> &G, const Real *__restrict__ fin,
+                                          Real *__restrict__ fout,
                                           unsigned bytes, int x0, int y0, int lane,
                                           const long long *__restrict__ d_step, int k,
                                           const uint4 (*bt)[4])
@@ -633,9 +664,10 @@ __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const
     int xh = lane < 32 ? x0 - 1 : x0 + 64;
     if (G.per_x && west && lane < 32) xh = nx - 1;
     if (G.per_x && east && e == 63 && lane >= 32) xh = 0;
-    const unsigned vo = 4u * (unsigned)F.col(xl);
-    const unsigned vh = 4u * (unsigned)F.col(xh);
-    const unsigned qB = 4u * (unsigned)F.qstride, jB = 4u * (unsigned)F.jstride;
+    const unsigned vo = (unsigned)sizeof(Real) * (unsigned)F.col(xl);
+    const unsigned vh = (unsigned)sizeof(Real) * (unsigned)F.col(xh);
+    const unsigned es = (unsigned)sizeof(Real);
+    const unsigned qB = es * (unsigned)F.qstride, jB = es * (unsigned)F.jstride;
     const auto rin = buffer_of(fin, bytes);
     const auto rout = buffer_of(fout, bytes);
     // byte offset of row j (j = -1 .. ny) of plane q
@@ -643,16 +675,16 @@ __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const
     // rows -1 and ny of a periodic y side are the opposite edge rows
     auto jrow = [&](int j) { return !G.per_y ? j : j == -1 ? ny - 1 : j == ny ? 0 : j; };
 
-    float v[R + 2][NQ], h[R][NQ];
+    Real v[R + 2][NQ], h[R][NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        v[0][q] = has_y(q) ? bload(rin, vo, row(q, jrow(y0 - 1))) : 0.f;
+        v[0][q] = has_y(q) ? bload<Real>(rin, vo, row(q, jrow(y0 - 1))) : Real(0);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            v[r + 1][q] = bload(rin, vo, row(q, jrow(y0 + r)));
-            h[r][q] = has_x(q) ? bload(rin, vh, row(q, y0 + r)) : 0.f;
+            v[r + 1][q] = bload<Real>(rin, vo, row(q, jrow(y0 + r)));
+            h[r][q] = has_x(q) ? bload<Real>(rin, vh, row(q, y0 + r)) : Real(0);
         }
-        v[R + 1][q] = has_y(q) ? bload(rin, vo, row(q, jrow(y0 + R))) : 0.f;
+        v[R + 1][q] = has_y(q) ? bload<Real>(rin, vo, row(q, jrow(y0 + R))) : Real(0);
     }
     const bool edge = (west && !G.per_x) || (east && !G.per_x) || (south && !G.per_y) ||
                       (north && !G.per_y);
@@ -662,11 +694,11 @@ __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const
         const int y = y0 + r;
         if (y >= ny) break;
         if (edge) {
-            float g[NQ], n2[NQ];
+            Real g[NQ], n2[NQ];
             if (y == 0 && !G.per_y) {  // south ghost replaces the row below
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)  // row 1: a wave row when R > 1
-                    n2[q] = (R > 1 || has_y(q)) ? v[r + 2][q] : bload(rin, vo, row(q, 1));
+                    n2[q] = (R > 1 || has_y(q)) ? v[r + 2][q] : bload<Real>(rin, vo, row(q, 1));
                 ghost_of<2>(K, G, t, x, v[r + 1], n2, g);
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)
@@ -675,7 +707,7 @@ __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const
             if (y == ny - 1 && !G.per_y) {  // north ghost replaces the row above
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)  // row ny - 2: a wave row when r > 0
-                    n2[q] = (r >= 1 || has_y(q)) ? v[r][q] : bload(rin, vo, row(q, ny - 2));
+                    n2[q] = (r >= 1 || has_y(q)) ? v[r][q] : bload<Real>(rin, vo, row(q, ny - 2));
                 ghost_of<3>(K, G, t, x, v[r + 1], n2, g);
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)
@@ -683,7 +715,7 @@ __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const
             }
             if (west && !G.per_x) {  // west ghost: the halo of lane 0
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) n2[q] = shl1(v[r + 1][q], 0.f);
+                for (int q = 0; q < NQ; ++q) n2[q] = shl1(v[r + 1][q], Real(0));
                 ghost_of<0>(K, G, t, y, v[r + 1], n2, g);
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)
@@ -692,17 +724,17 @@ __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const
             if (east && !G.per_x) {
                 if (e == 63) {  // east ghost: the halo of lane 63
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q) n2[q] = shr1(v[r + 1][q], 0.f);
+                    for (int q = 0; q < NQ; ++q) n2[q] = shr1(v[r + 1][q], Real(0));
                     ghost_of<1>(K, G, t, y, v[r + 1], n2, g);
 #pragma unroll
                     for (int q = 0; q < NQ; ++q)
                         if (has_x(q) && lane == 63) h[r][q] = g[q];
                 } else {  // east ghost: the values of the lane past the last column
-                    float n1[NQ];
+                    Real n1[NQ];
 #pragma unroll
                     for (int q = 0; q < NQ; ++q) {
-                        n1[q] = shr1(v[r + 1][q], 0.f);
-                        n2[q] = shr1(n1[q], 0.f);
+                        n1[q] = shr1(v[r + 1][q], Real(0));
+                        n2[q] = shr1(n1[q], Real(0));
                     }
                     ghost_of<1>(K, G, t, y, n1, n2, g);
 #pragma unroll
@@ -711,19 +743,19 @@ __device__ __forceinline__ void rows_edge(const Field &F, const Consts &K, const
                 }
             }
         }
-        float dC[NQ];
+        Real dC[NQ];
         if constexpr (BF)
             collide_bf3(K, bt, lane & 3, v[r + 1], dC);
         else
             collide(K, v[r + 1], dC);
         Unroll<NQ>::run([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            float fE = 0.f, fW = 0.f;
+            Real fE = Real(0), fW = Real(0);
             if (has_x(q)) {
                 fE = shl1(v[r + 1][q], h[r][q]);
                 fW = shr1(v[r + 1][q], h[r][q]);
             }
-            const float o = lw_update<q>(K, v[r + 1][q], dC[q], fE, fW, v[r + 2][q], v[r][q]);
+            const Real o = lw_update<q>(K, v[r + 1][q], dC[q], fE, fW, v[r + 2][q], v[r][q]);
             if (x < nx) bstore<AUX>(rout, o, vo, row(q, y));
         });
     }
@@ -744,10 +776,11 @@ __device__ __forceinline__ void face_flux_node(const Field &F, const ConstsT<Rea
 //
 // BF: the collision's transforms in split-BF16 on the matrix cores
 // (collide_bf3), its block table copied from bops into LDS first.
-template <int R, int AUX, bool BUD, bool BF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 1 ? 5 : 3, 8)))
-void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
-                 float *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
+template <int R, int AUX, bool BUD, bool BF, class Real>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(Real) == 8 ? 2 : (R == 1 ? 5 : 3), 8)))
+void k_step_rows(Field F, ConstsT<Real> K, GhostsT<Real> G, const Real *__restrict__ fin,
+                 Real *__restrict__ fout, unsigned bytes, int ncol, int nrg, int nblocks,
                  const long long *__restrict__ d_step, int k, int order,
                  double *__restrict__ slots, int fblocks, const Bf3Ops *__restrict__ bops)
 {
@@ -787,8 +820,8 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
     const int x0 = col * 64, y0 = rg * R, x = x0 + lane;
     if (col == 0 || x0 + 64 >= F.nx || y0 == 0 || y0 + R >= F.ny) {
         // constants from the device copies (see Ghosts::kd)
-        const Consts &Kd = *G.kd;
-        const Ghosts &Gd = *G.gd;
+        const ConstsT<Real> &Kd = *G.kd;
+        const GhostsT<Real> &Gd = *G.gd;
         if (x0 + 1 == F.nx) {  // a last column alone in its wave
             const double t = step_time(Gd, d_step, k);
             if (x < F.nx) {
@@ -797,44 +830,45 @@ void k_step_rows(Field F, Consts K, Ghosts G, const float *__restrict__ fin,
                     if (y0 + r < F.ny) node_update(F, Kd, Gd, fin, fout, x, y0 + r, t);
             }
         } else {
-            rows_edge<R, AUX, BF>(F, Kd, Gd, fin, fout, bytes, x0, y0, lane, d_step, k, bt);
+            rows_edge<R, AUX, BF, Real>(F, Kd, Gd, fin, fout, bytes, x0, y0, lane, d_step, k, bt);
         }
         return;
     }
-    const unsigned vo = 4u * (unsigned)F.col(x);
-    const unsigned vh = 4u * (unsigned)F.col(lane < 32 ? x0 - 1 : x0 + 64);
-    const unsigned qB = 4u * (unsigned)F.qstride, jB = 4u * (unsigned)F.jstride;
+    const unsigned vo = (unsigned)sizeof(Real) * (unsigned)F.col(x);
+    const unsigned vh = (unsigned)sizeof(Real) * (unsigned)F.col(lane < 32 ? x0 - 1 : x0 + 64);
+    const unsigned es = (unsigned)sizeof(Real);
+    const unsigned qB = es * (unsigned)F.qstride, jB = es * (unsigned)F.jstride;
     const auto rin = buffer_of(fin, bytes);
     const auto rout = buffer_of(fout, bytes);
     // byte offset of row j (j = -1 .. ny) of plane q
     auto row = [&](int q, int j) { return (unsigned)q * qB + (unsigned)(j + 1) * jB; };
 
-    float v[R + 2][NQ], h[R][NQ];
+    Real v[R + 2][NQ], h[R][NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        v[0][q] = has_y(q) ? bload(rin, vo, row(q, y0 - 1)) : 0.f;
+        v[0][q] = has_y(q) ? bload<Real>(rin, vo, row(q, y0 - 1)) : Real(0);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            v[r + 1][q] = bload(rin, vo, row(q, y0 + r));
-            h[r][q] = has_x(q) ? bload(rin, vh, row(q, y0 + r)) : 0.f;
+            v[r + 1][q] = bload<Real>(rin, vo, row(q, y0 + r));
+            h[r][q] = has_x(q) ? bload<Real>(rin, vh, row(q, y0 + r)) : Real(0);
         }
-        v[R + 1][q] = has_y(q) ? bload(rin, vo, row(q, y0 + R)) : 0.f;
+        v[R + 1][q] = has_y(q) ? bload<Real>(rin, vo, row(q, y0 + R)) : Real(0);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        float dC[NQ];
+        Real dC[NQ];
         if constexpr (BF)
             collide_bf3(K, bt, lane & 3, v[r + 1], dC);
         else
             collide(K, v[r + 1], dC);
         Unroll<NQ>::run([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            float fE = 0.f, fW = 0.f;
+            Real fE = Real(0), fW = Real(0);
             if (has_x(q)) {
                 fE = shl1(v[r + 1][q], h[r][q]);
                 fW = shr1(v[r + 1][q], h[r][q]);
             }
-            const float o = lw_update<q>(K, v[r + 1][q], dC[q], fE, fW, v[r + 2][q], v[r][q]);
+            const Real o = lw_update<q>(K, v[r + 1][q], dC[q], fE, fW, v[r + 2][q], v[r][q]);
             bstore<AUX>(rout, o, vo, row(q, y0 + r));
         });
     }
@@ -1262,8 +1296,36 @@ hipError_t launch_step_simple(const Field &F, const ConstsT<Real> &K, const Ghos
     return hipGetLastError();
 }
 
-hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, const float *fin,
-                            float *fout, int rows, int stream_stores, int order,
+namespace {
+template <int R, int AUX, class Real>
+void launch_rows_variant(dim3 grid, hipStream_t s, const Field &F, const ConstsT<Real> &K,
+                         const GhostsT<Real> &G, const Real *fin, Real *fout, unsigned bytes, int ncol,
+                         int nrg, int nb, const long long *d_step, int k, int ord, double *slots, int fb,
+                         const Bf3Ops *bops)
+{
+#define MRTFD_ROWS_C(Bu, Bf)                                                                       \
+    hipLaunchKernelGGL((k_step_rows<R, AUX, Bu, Bf, Real>), grid, dim3(256), 0, s, F, K, G, fin,   \
+                       fout, bytes, ncol, nrg, nb, d_step, k, ord, slots, Bu ? fb : 0, bops)
+    if constexpr (sizeof(Real) == 4) {  // the matrix-core collision is FP32 only
+        if (bops) {
+            if (slots)
+                MRTFD_ROWS_C(true, true);
+            else
+                MRTFD_ROWS_C(false, true);
+            return;
+        }
+    }
+    if (slots)
+        MRTFD_ROWS_C(true, false);
+    else
+        MRTFD_ROWS_C(false, false);
+#undef MRTFD_ROWS_C
+}
+}  // namespace
+
+template <class Real>
+hipError_t launch_step_rows(const Field &F, const ConstsT<Real> &K, const GhostsT<Real> &G,
+                            const Real *fin, Real *fout, int rows, int stream_stores, int order,
                             const long long *d_step, int k, hipStream_t s, double *slots,
                             const Bf3Ops *bops)
 {
@@ -1271,46 +1333,41 @@ hipError_t launch_step_rows(const Field &F, const Consts &K, const Ghosts &G, co
     const int nrg = (F.ny + rows - 1) / rows;
     const int nb = ncol * ((nrg + 3) / 4);
     const int ord = (order == 1 && (ncol & 7) == 0) ? 1 : 0;  // column bands need ncol % 8 == 0
-    const long long total = 4LL * F.total;
+    const long long total = (long long)sizeof(Real) * F.total;
     if (total >= (1LL << 32)) return hipErrorInvalidValue;  // buffer offsets are 32-bit
+    if (sizeof(Real) == 8 && (rows != 1 || bops)) return hipErrorInvalidValue;  // FP64: one row per wave
     const unsigned bytes = (unsigned)total;
     // budget blocks: one thread per side node, rounded up to a multiple of 8
     const int fb = slots ? (int)((blocks_for(2LL * (F.nx + F.ny), 256) + 7) / 8 * 8) : 0;
     const dim3 grid(nb + fb);
-    switch (rows) {
     // store cache policy: 0 default, 2 non-temporal (streaming)
-#define MRTFD_ROWS_C(Rr, Aa, Bu, Bf)                                                               \
-    hipLaunchKernelGGL((k_step_rows<Rr, Aa, Bu, Bf>), grid, dim3(256), 0, s, F, K, G, fin, fout,   \
-                       bytes, ncol, nrg, nb, d_step, k, ord, slots, Bu ? fb : 0, bops)
-#define MRTFD_ROWS_B(Rr, Aa)                                                                       \
-    if (slots) {                                                                                   \
-        if (bops)                                                                                  \
-            MRTFD_ROWS_C(Rr, Aa, true, true);                                                      \
-        else                                                                                       \
-            MRTFD_ROWS_C(Rr, Aa, true, false);                                                     \
-    } else {                                                                                       \
-        if (bops)                                                                                  \
-            MRTFD_ROWS_C(Rr, Aa, false, true);                                                     \
-        else                                                                                       \
-            MRTFD_ROWS_C(Rr, Aa, false, false);                                                    \
-    }
-#define MRTFD_ROWS(Rr)                                                                             \
-    case Rr:                                                                                       \
-        if (stream_stores) {                                                                       \
-            MRTFD_ROWS_B(Rr, 2);                                                                   \
-        } else {                                                                                   \
-            MRTFD_ROWS_B(Rr, 0);                                                                   \
-        }                                                                                          \
-        break;
-        MRTFD_ROWS(1)
-        MRTFD_ROWS(2)
-#undef MRTFD_ROWS
-#undef MRTFD_ROWS_B
-#undef MRTFD_ROWS_C
-    default: return hipErrorInvalidValue;
+    if (rows == 1) {
+        if (stream_stores)
+            launch_rows_variant<1, 2>(grid, s, F, K, G, fin, fout, bytes, ncol, nrg, nb, d_step, k, ord,
+                                      slots, fb, bops);
+        else
+            launch_rows_variant<1, 0>(grid, s, F, K, G, fin, fout, bytes, ncol, nrg, nb, d_step, k, ord,
+                                      slots, fb, bops);
+    } else if (rows == 2) {
+        if constexpr (sizeof(Real) == 4) {
+            if (stream_stores)
+                launch_rows_variant<2, 2>(grid, s, F, K, G, fin, fout, bytes, ncol, nrg, nb, d_step, k,
+                                          ord, slots, fb, bops);
+            else
+                launch_rows_variant<2, 0>(grid, s, F, K, G, fin, fout, bytes, ncol, nrg, nb, d_step, k,
+                                          ord, slots, fb, bops);
+        }
+    } else {
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
+template hipError_t launch_step_rows<float>(const Field &, const Consts &, const Ghosts &, const float *,
+                                            float *, int, int, int, const long long *, int, hipStream_t,
+                                            double *, const Bf3Ops *);
+template hipError_t launch_step_rows<double>(const Field &, const Consts64 &, const Ghosts64 &,
+                                             const double *, double *, int, int, int, const long long *,
+                                             int, hipStream_t, double *, const Bf3Ops *);
 
 hipError_t launch_fill(void *p, size_t bytes, unsigned pattern, hipStream_t s)
 {

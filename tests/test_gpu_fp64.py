@@ -1,5 +1,6 @@
 """The FP64 mode (MRTFD_FP64: populations stored and every step computed in
-FP64, one thread per node) against the FP64 oracle.  Both sides compute in
+FP64, by the rows kernel at one row per wave or the simple kernel) against
+the FP64 oracle.  Both sides compute in
 FP64 but in different orders (the factored transform and summed increments
 here, the paper's dense M and the plain update in the oracle), so they agree
 to a few units of FP64 rounding per step, relative to the same scales as
@@ -66,17 +67,24 @@ def f_ref(prob, ref):
 @pytest.mark.parametrize("ref", [None, (1.0, 1.0)])
 @pytest.mark.parametrize("sides", sorted(SIDE_SETS))
 def test_fp64_one_step_matches_oracle(gpu, sides, ref):
+    """Both FP64 kernels (the rows kernel at one row per wave, the simple
+    kernel) on a ragged 150 x 37 grid: bit for bit the same, and within 16
+    u64 S of the oracle."""
     nx, ny = 150, 37
     prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS[sides], None)
     fr = f_ref(prob, ref)[:, None, None]
     f0 = synth.random_populations(nx, ny, seed=41)
-    g = gpu.from_problem(prob, precision="fp64", ref=ref)
-    g.set_f64(f0 - fr)
-    assert g.kernel_variant()[0] == "simple"
-    start = g.get_f64_numpy() + fr
-    g.step(1)
-    got = g.get_f64_numpy() + fr
-    g.close()
+    outs = []
+    for kernel, rows in (("rows", 1), ("simple", 0)):
+        g = gpu.from_problem(prob, precision="fp64", ref=ref, kernel=kernel, rows=rows)
+        g.set_f64(f0 - fr)
+        assert g.kernel_variant()[0] == kernel
+        start = g.get_f64_numpy() + fr
+        g.step(1)
+        outs.append(g.get_f64_numpy())
+        g.close()
+    assert np.array_equal(outs[0], outs[1])
+    got = outs[0] + fr
     o = core.Grid(prob, nthreads=THREADS)
     o.set_f(start)
     o.run(1)
@@ -85,6 +93,29 @@ def test_fp64_one_step_matches_oracle(gpu, sides, ref):
     err = float(np.max(np.abs(got - want)))
     print(f"fp64 {sides} ref {ref}: max err {err:.3e} = {err / (U64 * S):.2f} u64 S")
     assert err <= 16 * U64 * S
+
+
+def test_fp64_kernels_agree_over_many_steps(gpu):
+    """The FP64 rows kernel (plain and streaming stores, both tile orders,
+    with and without the fused outflow budget) and the simple kernel: 50
+    steps on every rule set of a grid with several tile columns, bit for bit
+    the same."""
+    nx, ny = 520, 70
+    ic = synth.smooth_macro(nx, ny, seed=8, du=0.3, dr=0.2)
+    for sides in sorted(SIDE_SETS):
+        prob = synth.generic(nx, ny, 2e-3, 1e-5, RATES, SIDE_SETS[sides], ic)
+        outs = {}
+        for kernel, rows, budget in (("simple", 0, False), ("rows", 1, False), ("rows", 1, True),
+                                     ("auto", 0, False)):
+            g = gpu.from_problem(prob, precision="fp64", kernel=kernel, rows=rows, flux_budget=budget,
+                                 graph_steps=16)
+            g.init_problem(prob)
+            g.step(50)
+            outs[(kernel, budget)] = g.get_f64_numpy()
+            g.close()
+        first = outs[("simple", False)]
+        for k, v in outs.items():
+            assert np.array_equal(v, first), (sides, k)
 
 
 def test_fp64_init_matches_oracle(gpu):
