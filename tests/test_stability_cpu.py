@@ -189,3 +189,45 @@ def test_high_mach_tube_is_unstable_whichever_moment_takes_each_rate(S):
             best = min(best, growth_1d(rates((a, a + 1), k)))
     print("least growth over the index readings", best)
     assert best > 1.01
+
+
+def test_fig2_state_under_the_printed_rates_and_their_readings(S):
+    """Sect. IV, Fig. 2: at (rho, u1, u2, T) = (2, 10, 0, 2), dx = 2e-3, dt =
+    1e-5, along k dx (the figure's abscissa, k dy = 0).  SRT with tau = 1e-5
+    is unstable by a hair (max |omega| = 1 + 1.2e-6), as the paper says; MRT
+    with the printed rates (s5 = 6500, s7 = s8 = 9e4, s9 = 8e4, s13 = 7e4,
+    s14 = 8e3, s15 = 2.5e4, others 1e5) has max |omega| = 1.0034, and no
+    other reading of the printed indices (all shifted by -2 .. 2, s6 = s5,
+    or one rate moved to another moment) brings it to 1 or below (least
+    1.00003): the figure's MRT curve is not reproduced."""
+    state = (2.0, 10.0, 0.0, 2.0)
+    dx, dt = 2e-3, 1e-5
+    mats = S.model()
+    th = np.linspace(0.0, math.pi, 91)
+
+    def growth_1d(s):
+        return max(np.max(np.abs(np.linalg.eigvals(S.amplification(state, s, dx, dx, dt, t, 0.0, mats))))
+                   for t in th)
+
+    def rates(mapping):
+        s = [0.0] * 4 + [1e5] * 12
+        for k, v in mapping.items():
+            if 5 <= k <= 16:
+                s[k - 1] = v
+        return s
+
+    printed = {5: 6500.0, 7: 9e4, 8: 9e4, 9: 8e4, 13: 7e4, 14: 8e3, 15: 2.5e4}
+    srt = growth_1d([0.0] * 4 + [1e5] * 12)
+    assert 1.0 < srt < 1.0 + 1e-5
+    assert growth_1d(rates(printed)) > 1.003
+    readings = [{k + d: v for k, v in printed.items()} for d in (-2, -1, 1, 2)]
+    readings.append({**printed, 6: 6500.0})
+    for k in printed:
+        for k2 in range(5, 17):
+            if k2 not in printed:
+                m = dict(printed)
+                m[k2] = m.pop(k)
+                readings.append(m)
+    least = min(growth_1d(rates(m)) for m in readings)
+    print("SRT", srt, "least MRT growth over the readings", least)
+    assert least > 1.00002
