@@ -304,6 +304,35 @@ int32_t mrtfd_set_step(mrtfd_ctx *ctx, int64_t step);
 int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_t *streaming,
                           int32_t *tile_order);
 
+/* Von Neumann screen of Sect. IV.  For the uniform state (rho, u1, u2, T) =
+ * state[0..3] (host array; rho > 0, T > 0) and the spacing, time step and
+ * rates of p (its boundary fields are validated but not used), the
+ * amplification matrix of one Fourier mode of the scheme (Eq. A.1a-b with
+ * the collision of Eq. 3 linearised about the state, the equilibria of Eq.
+ * 14 differentiated through rho, j and e) is
+ *   G_ij(theta) = delta_ij (1 - i a_i sin theta_x + a_i^2 (cos theta_x - 1)
+ *                 - i b_i sin theta_y + b_i^2 (cos theta_y - 1))
+ *                 - dt [M^-1 S (M - d f-hat^eq / d f)]_ij,
+ * a_i = v_i1 dt / dx, b_i = v_i2 dt / dy, theta = (k_x dx, k_y dy); the
+ * scheme is stable at the state when every eigenvalue omega of G has |omega|
+ * <= 1 over all phases.  For n phase pairs d_theta[2 p], d_theta[2 p + 1]
+ * (device array of 2 n doubles) computes the 16 eigenvalues of G in FP64
+ * (balancing, Householder reduction to Hessenberg form and the shifted QR
+ * algorithm, one block per phase pair) and writes them, largest modulus
+ * first, as (re, im) pairs to d_eig[32 p .. 32 p + 31], and the largest
+ * modulus to d_rho[p] (device arrays of 32 n and n doubles; either may be
+ * NULL, not both).  They are the exact eigenvalues of some G + E with ||E||
+ * a small multiple of u ||G|| (u = 2^-53), so an eigenvalue with condition
+ * number kappa (1 / |y^H x| for unit left and right eigenvectors y, x) is
+ * accurate to about kappa u ||G||: near 1e-12 at moderate states, but ~1e-4
+ * at hot or fast ones, where ||G|| and kappa both reach ~1e6.  A phase whose iteration does not converge in 480 QR steps
+ * gets NaN.  Enqueued on `stream` (a hipStream_t, NULL = default); nothing
+ * is allocated.  MRTFD_ERR_ARG for invalid parameters, a state with rho <=
+ * 0, T <= 0 or non-finite values, n < 0, d_theta NULL or both outputs NULL
+ * with n > 0; MRTFD_ERR_HIP if the launch fails. */
+int32_t mrtfd_screen(const mrtfd_params *p, const double state[4], const double *d_theta, int32_t n,
+                     double *d_eig, double *d_rho, void *stream);
+
 /* The library's FP64 model on the host: velocity set v[16][2] (Eq. 4), M
  * [16][16] (Eq. 5, row-major, M[k][i] = m_{k+1}(v_i)) and its inverse, as
  * used to build the kernels' constants.  Host arrays; any may be NULL. */

@@ -12,6 +12,8 @@ code with this package.
 * ``analytic`` -- Couette series, transport coefficients, Fourier
                   amplification of the difference scheme.
 * ``metrics``  -- the paper's relative error E, L1/Linf, shock location.
+* ``stability`` -- the von Neumann screen of Sect. IV in numpy (eigenvalues
+                  of the amplification matrix), the reference of the GPU one.
 """
-from . import analytic, core, metrics, riemann  # noqa: F401
+from . import analytic, core, metrics, riemann, stability  # noqa: F401
 from .core import Grid, model  # noqa: F401

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -419,6 +420,79 @@ void fill_ghosts(const Model &m, const mrtfd_params &p, const double (&fref)[NQ]
             feq_host(m, S.state_hi[0], S.state_hi[1], S.state_hi[2], S.state_hi[3], fe);
             for (int q = 0; q < NQ; ++q) g.feq_hi[q] = (Real)(fe[q] - fref[q]);
         }
+    }
+}
+
+// ------------------------------------------------------- stability screen
+
+// f-hat^eq of Eq. (14) as a function of the conserved moments (rho, j_x, j_y,
+// e), with P = e - |j|^2 / (2 rho); generic in the number type, so that its
+// Jacobian can be taken by complex steps.
+template <class Num>
+void feq_of_conserved(Num rho, Num jx, Num jy, Num e, Num (&h)[NQ])
+{
+    const Num r = Num(1.0) / rho;
+    const Num j2 = jx * jx + jy * jy;
+    const Num P = e - Num(0.5) * j2 * r;
+    const Num g = Num(6.0) * rho * e - Num(2.0) * j2;
+    h[0] = rho;
+    h[1] = jx;
+    h[2] = jy;
+    h[3] = e;
+    h[4] = (jx * jx - jy * jy) * r;
+    h[5] = jx * jy * r;
+    h[6] = (e + P) * jx * r;
+    h[7] = (e + P) * jy * r;
+    h[8] = (jx * jx - Num(3.0) * jy * jy) * jx * r * r;
+    h[9] = (Num(3.0) * jx * jx - jy * jy) * jy * r * r;
+    h[10] = Num(2.0) * e * e * r - Num(0.25) * j2 * j2 * r * r * r;
+    h[11] = Num(0.0);
+    h[12] = g * (jx * jx - jy * jy) * r * r * r;
+    h[13] = g * jx * jy * r * r * r;
+    h[14] = Num(0.0);
+    h[15] = Num(0.0);
+}
+
+// d f-hat^eq / d (rho, j_x, j_y, e) by complex steps (Squire and Trapp,
+// 1998): for an analytic h, Im h(x + i eps e_c) / eps = dh/dx_c with no
+// difference of nearby values, so the result is exact up to rounding.
+void feq_jacobian(double rho, double jx, double jy, double e, double J[NQ][4])
+{
+    const double eps = 1e-30;
+    for (int c = 0; c < 4; ++c) {
+        std::complex<double> x[4] = {rho, jx, jy, e};
+        x[c] += std::complex<double>(0.0, eps);
+        std::complex<double> h[NQ];
+        feq_of_conserved(x[0], x[1], x[2], x[3], h);
+        for (int k = 0; k < NQ; ++k) J[k][c] = h[k].imag() / eps;
+    }
+}
+
+// The screen's phase-independent part at a uniform state (rho, u1, u2, T):
+// C = dt M^-1 S (M - J M_c), J the Jacobian above and M_c the conserved rows
+// of M (the chain rule of Sect. IV through rho, j, e); and the Lax-Wendroff
+// weights a_i, b_i.
+void screen_coef(const Model &m, const mrtfd_params &p, const double state[4], ScreenCoef &S)
+{
+    const double rho = state[0], ux = state[1], uy = state[2], T = state[3];
+    double J[NQ][4];
+    feq_jacobian(rho, rho * ux, rho * uy, rho * (T + 0.5 * (ux * ux + uy * uy)), J);
+    double D[NQ][NQ];
+    for (int k = 0; k < NQ; ++k)
+        for (int i = 0; i < NQ; ++i) {
+            double a = m.M[k][i];
+            for (int c = 0; c < 4; ++c) a -= J[k][c] * m.M[c][i];
+            D[k][i] = a;
+        }
+    for (int a = 0; a < NQ; ++a)
+        for (int i = 0; i < NQ; ++i) {
+            double acc = 0.0;
+            for (int k = 0; k < NQ; ++k) acc += m.Minv[a][k] * p.s[k] * D[k][i];
+            S.C[a][i] = p.dt * acc;
+        }
+    for (int q = 0; q < NQ; ++q) {
+        S.a[q] = m.v[q][0] * p.dt / p.dx;
+        S.b[q] = m.v[q][1] * p.dt / p.dy;
     }
 }
 
@@ -925,6 +999,26 @@ int32_t mrtfd_model(double *v, double *M, double *Minv)
     if (M) std::memcpy(M, m.M, sizeof m.M);
     if (Minv) std::memcpy(Minv, m.Minv, sizeof m.Minv);
     return MRTFD_OK;
+}
+
+int32_t mrtfd_screen(const mrtfd_params *p, const double state[4], const double *d_theta, int32_t n,
+                     double *d_eig, double *d_rho, void *stream)
+{
+    if (!p || !state) return MRTFD_ERR_ARG;
+    if (check(p, nullptr, 0) != MRTFD_OK) return MRTFD_ERR_ARG;
+    for (int c = 0; c < 4; ++c)
+        if (!std::isfinite(state[c])) return MRTFD_ERR_ARG;
+    if (!(state[0] > 0) || !(state[3] > 0)) return MRTFD_ERR_ARG;
+    if (n < 0) return MRTFD_ERR_ARG;
+    if (n == 0) return MRTFD_OK;
+    if (!d_theta || (!d_eig && !d_rho)) return MRTFD_ERR_ARG;
+    const Model &m = model();
+    if (!m.ok) return MRTFD_ERR_ARG;
+    ScreenCoef S;
+    screen_coef(m, *p, state, S);
+    return launch_screen(S, d_theta, n, d_eig, d_rho, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? MRTFD_OK
+               : MRTFD_ERR_HIP;
 }
 
 int32_t mrtfd_ref_populations(const mrtfd_params *p, double out[16])

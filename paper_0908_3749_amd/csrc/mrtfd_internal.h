@@ -203,6 +203,23 @@ hipError_t launch_pack(const Field &F, const Src *f, Dst *dst, hipStream_t s);
 template <class Src, class Dst>
 hipError_t launch_unpack(const Field &F, const Src *src, Dst *f, hipStream_t s);
 
+// Von Neumann screen (Sect. IV): the amplification matrix of one Fourier
+// mode around a uniform state is G(theta) = diag(adv_i(theta)) - C with
+// adv_i = 1 - i a_i sin(theta_x) + a_i^2 (cos(theta_x) - 1) - i b_i
+// sin(theta_y) + b_i^2 (cos(theta_y) - 1), a_i = v_ix dt / dx, b_i = v_iy dt
+// / dy (Eq. A.1b), and C = dt M^-1 S (M - d f-hat^eq / d f), the same for
+// every phase.
+struct ScreenCoef {
+    double C[NQ][NQ];
+    double a[NQ], b[NQ];
+};
+// For each of n phase pairs theta[2 p], theta[2 p + 1] (device array): the
+// 16 eigenvalues of G, largest modulus first, as (re, im) pairs at eig[32 p
+// ..] and their largest modulus at rho[p] (either pointer may be null); NaN
+// where the QR iteration does not converge.
+hipError_t launch_screen(const ScreenCoef &S, const double *theta, int n, double *eig, double *rho,
+                         hipStream_t s);
+
 // ------------------------------------------------------------------ tubes
 // Batched independent tubes: tube k has n columns and TUBE_ROWS rows,
 // periodic in y, f = f^eq of its left / right state beyond its two ends.  All

@@ -1271,6 +1271,243 @@ __global__ __launch_bounds__(256) void k_unpack(Field F, const Src *__restrict__
     f[F.at(q, i, j)] = (Dst)src[(long long)q * n + c];
 }
 
+// Von Neumann screen: all 16 eigenvalues of the amplification matrix G of
+// Sect. IV for one phase pair per block of one wave, FP64 complex (double2 =
+// re, im) in LDS.  G is first balanced (Parlett and Reinsch 1969: row and
+// column i scaled by powers of 2, which is exact, until their 1-norms are
+// within a factor 2), then brought to upper Hessenberg form by Householder
+// reflections, then reduced by the shifted QR algorithm (Francis 1961;
+// Golub and Van Loan, Matrix Computations, Sect. 7.5) on the active window
+// only, since only the eigenvalues are wanted: each step takes the
+// Wilkinson shift of the trailing 2 x 2 block (an ad hoc shift every 10th
+// step without deflation), factors H - mu I by Givens rotations, forms R Q +
+// mu I, and deflates a subdiagonal entry once it is below the unit roundoff
+// times its two diagonal neighbours.  Every lane computes the control flow
+// and the rotation scalars from the same LDS values, so branches and
+// barriers are uniform over the block.
+constexpr int SCREEN_THREADS = 64;
+constexpr int SCREEN_MAX_STEPS = 30 * NQ;
+
+__device__ inline double2 c_mul(double2 a, double2 b)
+{
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ inline double2 c_conj_mul(double2 a, double2 b)  // conj(a) * b
+{
+    return make_double2(fma(a.x, b.x, a.y * b.y), fma(a.x, b.y, -a.y * b.x));
+}
+__device__ inline double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 c_scale(double2 a, double r) { return make_double2(a.x * r, a.y * r); }
+__device__ inline double c_abs1(double2 a) { return fabs(a.x) + fabs(a.y); }
+__device__ inline double c_abs(double2 a) { return hypot(a.x, a.y); }
+__device__ inline double2 c_div(double2 a, double2 b)  // Smith's algorithm
+{
+    if (fabs(b.x) >= fabs(b.y)) {
+        const double r = b.y / b.x, d = b.x + b.y * r;
+        return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+    }
+    const double r = b.x / b.y, d = b.x * r + b.y;
+    return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+__device__ inline double2 c_sqrt(double2 z)  // principal root, no cancellation
+{
+    const double r = c_abs(z);
+    if (r == 0.0) return make_double2(0.0, 0.0);
+    if (z.x >= 0.0) {
+        const double t = sqrt(0.5 * (r + z.x));
+        return make_double2(t, z.y / (2.0 * t));
+    }
+    const double t = sqrt(0.5 * (r - z.x));
+    return make_double2(fabs(z.y) / (2.0 * t), copysign(t, z.y));
+}
+
+__global__ __launch_bounds__(SCREEN_THREADS) void k_screen(ScreenCoef S, const double *__restrict__ theta,
+                                                           double *__restrict__ eig, double *__restrict__ rho)
+{
+    __shared__ double2 A[NQ][NQ];
+    __shared__ double2 v[NQ], w[NQ];
+    __shared__ double rc[NQ];
+    __shared__ double2 rs[NQ], ev[NQ];
+    const int p = blockIdx.x, t = threadIdx.x;
+    const double tx = theta[2 * p], ty = theta[2 * p + 1];
+    for (int e = t; e < NQ * NQ; e += SCREEN_THREADS) {
+        const int r = e / NQ, c = e % NQ;
+        double2 g = make_double2(-S.C[r][c], 0.0);
+        if (r == c) {
+            const double a = S.a[r], b = S.b[r];
+            g.x += 1.0 + a * a * (cos(tx) - 1.0) + b * b * (cos(ty) - 1.0);
+            g.y -= a * sin(tx) + b * sin(ty);
+        }
+        A[r][c] = g;
+    }
+    __syncthreads();
+
+    // balancing
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        bool changed = false;
+        for (int i = 0; i < NQ; ++i) {
+            double c = 0.0, r = 0.0;
+            for (int j = 0; j < NQ; ++j)
+                if (j != i) {
+                    c += c_abs1(A[j][i]);
+                    r += c_abs1(A[i][j]);
+                }
+            if (!(c > 0.0 && r > 0.0 && isfinite(c + r))) continue;
+            const double s0 = c + r;
+            double f = 1.0;
+            for (int k = 0; k < 1000 && c < 0.5 * r; ++k) {
+                f *= 2.0;
+                c *= 4.0;
+            }
+            for (int k = 0; k < 1000 && c >= 2.0 * r; ++k) {
+                f *= 0.5;
+                c *= 0.25;
+            }
+            if ((c + r) / f < 0.95 * s0) {  // c is now c f^2: new column + row norm < 0.95 old
+                changed = true;
+                __syncthreads();
+                if (t < NQ && t != i) A[i][t] = c_scale(A[i][t], 1.0 / f);
+                else if (t >= NQ && t < 2 * NQ && t - NQ != i) A[t - NQ][i] = c_scale(A[t - NQ][i], f);
+                __syncthreads();
+            }
+        }
+        if (!changed) break;
+    }
+
+    // Householder reduction to upper Hessenberg form
+    for (int k = 0; k + 2 < NQ; ++k) {
+        double tail = 0.0;
+        for (int i = k + 2; i < NQ; ++i) tail += A[i][k].x * A[i][k].x + A[i][k].y * A[i][k].y;
+        if (tail == 0.0) continue;
+        const double2 x0 = A[k + 1][k];
+        const double a0 = c_abs(x0);
+        const double xn = sqrt(tail + a0 * a0);
+        const double2 ph = a0 > 0.0 ? c_scale(x0, 1.0 / a0) : make_double2(1.0, 0.0);
+        const double2 alpha = c_scale(ph, -xn);           // v = x - alpha e_1: no cancellation in v_0
+        const double tau = 1.0 / (xn * (xn + a0));        // 2 / (v^H v)
+        if (t > k && t < NQ) v[t] = t == k + 1 ? c_scale(ph, a0 + xn) : A[t][k];
+        __syncthreads();
+        if (t > k && t < NQ) {  // w_j = v^H A(:, j) over rows k + 1 ..
+            double2 acc = make_double2(0.0, 0.0);
+            for (int i = k + 1; i < NQ; ++i) acc = c_add(acc, c_conj_mul(v[i], A[i][t]));
+            w[t] = acc;
+        }
+        __syncthreads();
+        for (int e = t; e < NQ * NQ; e += SCREEN_THREADS) {
+            const int r = e / NQ, c = e % NQ;
+            if (r <= k) continue;
+            if (c == k) A[r][c] = r == k + 1 ? alpha : make_double2(0.0, 0.0);
+            else if (c > k) A[r][c] = c_sub(A[r][c], c_scale(c_mul(v[r], w[c]), tau));
+        }
+        __syncthreads();
+        if (t < NQ) {  // z_r = A(r, :) v over columns k + 1 ..
+            double2 acc = make_double2(0.0, 0.0);
+            for (int j = k + 1; j < NQ; ++j) acc = c_add(acc, c_mul(A[t][j], v[j]));
+            w[t] = acc;
+        }
+        __syncthreads();
+        for (int e = t; e < NQ * NQ; e += SCREEN_THREADS) {
+            const int r = e / NQ, c = e % NQ;
+            if (c > k) A[r][c] = c_sub(A[r][c], c_scale(c_mul(w[r], make_double2(v[c].x, -v[c].y)), tau));
+        }
+        __syncthreads();
+    }
+
+    // shifted QR on the active window [l, hi]
+    const double ulp = 0x1p-52;
+    int hi = NQ - 1, since = 0, steps = 0;
+    bool failed = false;
+    while (hi >= 0) {
+        int l = hi;
+        for (; l > 0; --l) {
+            const double sub = c_abs1(A[l][l - 1]);
+            if (sub <= ulp * (c_abs1(A[l - 1][l - 1]) + c_abs1(A[l][l])) || sub < 0x1p-1000) break;
+        }
+        if (l == hi) {
+            if (t == 0) ev[hi] = A[hi][hi];
+            --hi;
+            since = 0;
+            continue;
+        }
+        if (steps == SCREEN_MAX_STEPS) {
+            failed = true;
+            break;
+        }
+        ++steps;
+        ++since;
+        double2 mu;
+        if (since % 10 == 0) {
+            mu = A[hi][hi];
+            mu.x += 0.75 * c_abs1(A[hi][hi - 1]);
+        } else {
+            const double2 a = A[hi - 1][hi - 1], b = A[hi - 1][hi], c = A[hi][hi - 1], d = A[hi][hi];
+            const double2 h = c_scale(c_sub(a, d), 0.5), bc = c_mul(b, c);
+            const double2 root = c_sqrt(c_add(c_mul(h, h), bc));
+            const double2 d1 = c_add(h, root), d2 = c_sub(h, root);
+            const double2 den = c_abs1(d1) >= c_abs1(d2) ? d1 : d2;
+            mu = c_abs1(den) > 0.0 ? c_sub(d, c_div(bc, den)) : d;
+        }
+        __syncthreads();
+        if (t >= l && t <= hi) A[t][t] = c_sub(A[t][t], mu);
+        __syncthreads();
+        for (int k = l; k < hi; ++k) {  // H - mu I = Q R, rotation k zeroes (k + 1, k)
+            const double2 a = A[k][k], b = A[k + 1][k];
+            const double na = c_abs(a), r = hypot(na, c_abs(b));
+            double cr;
+            double2 sr;
+            if (na == 0.0) {
+                cr = 0.0;
+                sr = make_double2(1.0, 0.0);
+            } else {
+                cr = na / r;
+                sr = c_scale(c_conj_mul(b, a), 1.0 / (na * r));  // conj(b) a / (|a| r)
+            }
+            __syncthreads();
+            if (t == 0) {
+                rc[k] = cr;
+                rs[k] = sr;
+            }
+            if (t >= k && t <= hi) {
+                const double2 x = A[k][t], y = A[k + 1][t];
+                A[k][t] = c_add(c_scale(x, cr), c_mul(sr, y));
+                A[k + 1][t] = c_sub(c_scale(y, cr), c_conj_mul(sr, x));
+            }
+            __syncthreads();
+        }
+        for (int k = l; k < hi; ++k) {  // R Q: columns k, k + 1 times the rotation's adjoint
+            const double cr = rc[k];
+            const double2 sr = rs[k];
+            if (t >= l && t <= min(k + 1, hi)) {
+                const double2 x = A[t][k], y = A[t][k + 1];
+                A[t][k] = c_add(c_scale(x, cr), c_mul(y, make_double2(sr.x, -sr.y)));
+                A[t][k + 1] = c_sub(c_scale(y, cr), c_mul(x, sr));
+            }
+            __syncthreads();
+        }
+        if (t >= l && t <= hi) A[t][t] = c_add(A[t][t], mu);
+        __syncthreads();
+    }
+    __syncthreads();
+    if (t == 0) {  // largest modulus first
+        if (failed)
+            for (int i = 0; i < NQ; ++i) ev[i] = make_double2(NAN, NAN);
+        for (int i = 1; i < NQ; ++i) {
+            const double2 x = ev[i];
+            const double m = c_abs(x);
+            int j = i;
+            for (; j > 0 && c_abs(ev[j - 1]) < m; --j) ev[j] = ev[j - 1];
+            ev[j] = x;
+        }
+        if (rho) rho[p] = failed ? NAN : c_abs(ev[0]);
+    }
+    __syncthreads();
+    if (eig && t < NQ) {
+        eig[(long long)p * 2 * NQ + 2 * t] = ev[t].x;
+        eig[(long long)p * 2 * NQ + 2 * t + 1] = ev[t].y;
+    }
+}
+
 inline unsigned blocks_for(long long n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -1514,6 +1751,14 @@ template hipError_t launch_unpack<float, float>(const Field &, const float *, fl
 template hipError_t launch_unpack<float, double>(const Field &, const float *, double *, hipStream_t);
 template hipError_t launch_unpack<double, float>(const Field &, const double *, float *, hipStream_t);
 template hipError_t launch_unpack<double, double>(const Field &, const double *, double *, hipStream_t);
+
+hipError_t launch_screen(const ScreenCoef &S, const double *theta, int n, double *eig, double *rho,
+                         hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_screen, dim3(n), dim3(SCREEN_THREADS), 0, s, S, theta, eig, rho);
+    return hipGetLastError();
+}
 
 // ------------------------------------------------------------ tube launchers
 

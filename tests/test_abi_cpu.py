@@ -167,3 +167,21 @@ def test_reference_populations(abi):
     for bad in ((1.0, 0.0), (0.0, 1.0), (-1.0, 1.0), (1.0, math.inf), (1e300, 1.0)):
         p = _params(prob, ref=bad)
         assert check_params(p)[0] == abi.MRTFD_ERR_ARG, bad
+
+
+def test_screen_rejects_bad_arguments_without_gpu(abi):
+    """mrtfd_screen validates its arguments before any HIP call: n < 0, a
+    NULL phase array, both outputs NULL, a state with rho <= 0, T <= 0 or
+    non-finite values; n = 0 does nothing."""
+    p = _params(synth.sod())
+    L = abi.lib()
+    good = (C.c_double * 4)(1.0, 0.0, 0.0, 1.0)
+    dummy = C.c_void_p(8)  # never dereferenced: every case returns before a launch
+    assert L.mrtfd_screen(C.byref(p), good, dummy, 0, dummy, dummy, None) == 0
+    assert L.mrtfd_screen(C.byref(p), good, dummy, -1, dummy, dummy, None) == abi.MRTFD_ERR_ARG
+    assert L.mrtfd_screen(C.byref(p), good, None, 4, dummy, dummy, None) == abi.MRTFD_ERR_ARG
+    assert L.mrtfd_screen(C.byref(p), good, dummy, 4, None, None, None) == abi.MRTFD_ERR_ARG
+    assert L.mrtfd_screen(None, good, dummy, 4, dummy, dummy, None) == abi.MRTFD_ERR_ARG
+    for bad in ((0.0, 0.0, 0.0, 1.0), (1.0, 0.0, 0.0, -1.0), (1.0, math.nan, 0.0, 1.0), (1.0, 0.0, math.inf, 1.0)):
+        st = (C.c_double * 4)(*bad)
+        assert L.mrtfd_screen(C.byref(p), st, dummy, 4, dummy, dummy, None) == abi.MRTFD_ERR_ARG, bad

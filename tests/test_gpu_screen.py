@@ -1,0 +1,256 @@
+"""The von Neumann screen of Sect. IV on the GPU (mrtfd_screen: the 16
+eigenvalues of the amplification matrix G per phase pair, by balancing,
+Householder reduction and shifted QR in FP64).
+
+Against closed forms: at theta = 0 the eigenvalues are 1 (four times, the
+conserved moments) and 1 - dt s_k; with all rates zero G is diagonal and its
+eigenvalues are the Lax-Wendroff factors.  Against numpy (LAPACK's
+eigenvalues of the matrix the oracle builds, oracle/stability.py) over the
+paper's parameter sets, eigenvalue by eigenvalue after an optimal matching:
+both are backward stable, so each pair agrees within the first-order
+perturbation bound c u (||G||_F + K) kappa_i, with kappa_i the eigenvalue's
+condition number (from numpy's left and right eigenvectors), u = 2^-53, K =
+|| |dt M^-1| |S| |M - J M_c| ||_F the scale of the rounding in the two
+constructions of G, and c = 16 (a CPU replica of the kernel's steps reaches
+at most 2.4 u ||G|| kappa_i against numpy).  Where G is far from normal
+(||G|| and kappa ~ 1e6 at hot or fast states) this bound is ~1e-4: FP64
+cannot pin max |omega| more closely there, whatever the method.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+import scipy.linalg as sl
+from scipy.optimize import linear_sum_assignment
+
+import synth
+from oracle import riemann
+from oracle import stability as ref
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+FIG2_MRT = synth.rates(1e-5, s5=6500, s7=9e4, s8=9e4, s9=8e4, s13=7e4, s14=8e3, s15=2.5e4)
+CASES = {
+    "sod_left": ((1.0, 0.0, 0.0, 1.0), synth.sod().s, 1.0 / 400, 2e-5),
+    "sod_right": ((0.125, 0.0, 0.0, 0.8), synth.sod().s, 1.0 / 400, 2e-5),
+    "high_mach_west": ((5.0, 45.0, 0.0, 10.0), synth.rates(1e-5, s5=1.5e4, s6=1.5e4, s10=5e4), 0.003, 1e-5),
+    "fig2_mrt": ((2.0, 10.0, 0.0, 2.0), FIG2_MRT, 2e-3, 1e-5),
+    "fig2_srt": ((2.0, 10.0, 0.0, 2.0), [0.0] * 4 + [1e5] * 12, 2e-3, 1e-5),
+    "regular_inflow": ((1.0, 5.0, 0.0, 0.5), synth.rates(1e-5, s5=1e4, s6=2e3, s7=1e4, s8=1e4), 0.002, 1e-5),
+    "colella_hot": ((1.0, 0.0, 0.0, 1000.0), synth.rates(2e-6, s7=5e4, s8=5e4, s11=5e5, s13=5e5), 0.002, 2e-6),
+    "oblique": ((0.7, 0.4, -0.9, 2.5), synth.rates(1e-5, s5=800, s6=3e3, s9=2e4), 0.003, 1e-5),
+}
+
+
+@pytest.fixture(scope="module")
+def screen():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_0908_3749_amd import stability
+    return stability
+
+
+def construction_scale(state, s, dt, mats):
+    v, M, Minv = mats
+    Jf = ref.feq_jacobian(*state) @ M[:4]
+    return float(np.linalg.norm(dt * np.abs(Minv) @ np.diag(np.abs(s)) @ np.abs(M - Jf)))
+
+
+def condition_numbers(G, exact=None):
+    """numpy's eigenvalues of G, and for each the condition number of its
+    cluster: the 2-norm of the spectral projector P = V (W^H V)^-1 W^H onto
+    the cluster's invariant subspace (V orthonormal), which bounds the
+    first-order motion of every eigenvalue in it by ||P|| ||E|| under a
+    perturbation E (for a simple eigenvalue, 1 / |y^H x|), and the cluster's
+    diameter.  The clusters are the eigenvalues within 1e-6 of each other
+    (single linkage) or, given the exact eigenvalues, those matched to one
+    exact value."""
+    w, vl, vr = sl.eig(G, left=True, right=True)
+    if exact is None:
+        label = list(range(16))
+
+        def root(i):
+            while label[i] != i:
+                i = label[i]
+            return i
+
+        for i in range(16):
+            for j in range(i):
+                if abs(w[i] - w[j]) <= 1e-6 * max(1.0, abs(w[i])):
+                    label[root(i)] = root(j)
+        label = [root(i) for i in range(16)]
+    else:
+        ri, ci = linear_sum_assignment(np.abs(w[:, None] - np.asarray(exact)[None, :]))
+        label = [0] * 16
+        for i, j in zip(ri, ci):
+            label[i] = float(np.asarray(exact)[j])
+    kap, diam = np.zeros(16), np.zeros(16)
+    for g in set(label):
+        idx = [i for i in range(16) if label[i] == g]
+        V, _ = np.linalg.qr(vr[:, idx])
+        W = vl[:, idx]
+        P = V @ np.linalg.solve(W.conj().T @ V, W.conj().T)
+        kap[idx] = np.linalg.norm(P, 2)
+        diam[idx] = max(abs(w[i] - w[j]) for i in idx for j in idx)
+    return w, kap, diam
+
+
+def compare(got, G, K, c=16.0):
+    """Match got (16 eigenvalues) to numpy's eigenvalues of G; returns the
+    worst ratio of |difference| to its bound c u (||G||_F + K) kappa +
+    (cluster diameter), and numpy's max |omega| with its bound."""
+    w, kap, diam = condition_numbers(G)
+    cost = np.abs(w[:, None] - got[None, :])
+    ri, ci = linear_sum_assignment(cost)
+    tol = c * U * (np.linalg.norm(G) + K) * kap[ri] + diam[ri] + 1e-15
+    i = int(np.argmax(np.abs(w)))
+    return float(np.max(cost[ri, ci] / tol)), float(np.abs(w[i])), float(tol[list(ri).index(i)])
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_eigenvalues_match_numpy(screen, name):
+    state, s, dx, dt = CASES[name]
+    mats = ref.model()
+    K = construction_scale(state, s, dt, mats)
+    th = screen.phase_grid(6)
+    got = screen.eigenvalues(state, s, dx, dx, dt, th)
+    rho = screen.spectral_radius(state, s, dx, dx, dt, th)
+    assert np.all(np.isfinite(got))
+    mod = np.abs(got)  # the kernel's own moduli may differ from numpy's in the last bit
+    assert np.all(np.diff(mod, axis=1) <= 4 * U * mod[:, :-1])              # largest modulus first
+    np.testing.assert_allclose(rho, mod[:, 0], rtol=4 * U, atol=0)         # either output, same path
+    worst, top = 0.0, (0.0, None, None, None)
+    for p, (a, b) in enumerate(th):
+        G = ref.amplification(state, s, dx, dx, dt, a, b, mats)
+        r, wmax, tmax = compare(got[p], G, K)
+        worst = max(worst, r)
+        assert abs(rho[p] - wmax) <= tmax, (p, rho[p], wmax, tmax)
+        if wmax > top[0]:
+            top = (wmax, (a, b), rho[p], tmax)
+    print(f"{name}: max |omega| numpy {top[0]:.12f} at {top[1]}, GPU {top[2]:.12f} (bound {top[3]:.1e}); "
+          f"worst eigenvalue difference {worst:.3f} of its bound")
+    assert worst <= 1.0
+
+
+@pytest.mark.parametrize("name", ["sod_left", "high_mach_west", "colella_hot", "fig2_mrt"])
+def test_uniform_mode_closed_form(screen, name):
+    """theta = 0: G = I - dt M^-1 S (M - J M_c) has the eigenvalues 1 (x4)
+    and 1 - dt s_k, k = 5..16, whatever the state."""
+    state, s, dx, dt = CASES[name]
+    got = screen.eigenvalues(state, s, dx, dx, dt, np.zeros((1, 2)))[0]
+    want = np.array([1.0] * 4 + [1.0 - dt * sk for sk in s[4:]])
+    G = ref.amplification(state, s, dx, dx, dt, 0.0, 0.0)
+    K = construction_scale(state, s, dt, ref.model())
+    w, kap, _ = condition_numbers(G, exact=want)
+    cost = np.abs(want[:, None] - got[None, :])
+    ri, ci = linear_sum_assignment(cost)
+    # the projector norm of the exact eigenvalue's whole eigenspace (the 1 - dt s_k repeat)
+    kmatch = np.array([kap[int(np.argmin(np.abs(w - want[i])))] for i in ri])
+    tol = 16 * U * (np.linalg.norm(G) + K) * kmatch + 1e-15
+    print(name, "worst difference", float(np.max(cost[ri, ci] / tol)), "of its bound")
+    assert np.all(cost[ri, ci] <= tol)
+
+
+def test_zero_rates_give_the_lax_wendroff_factors(screen):
+    """With S = 0, G = diag(1 - i a sin th_x + a^2 (cos th_x - 1) - i b sin
+    th_y + b^2 (cos th_y - 1)), a = v_x dt / dx, b = v_y dt / dy (Eq.
+    A.1b): balancing, Householder and QR all leave a diagonal matrix alone."""
+    v, _, _ = ref.model()
+    dx, dy, dt = 0.002, 0.003, 1e-5
+    th = screen.phase_grid(5)
+    got = screen.eigenvalues((1.0, 0.3, 0.1, 1.0), [0.0] * 16, dx, dy, dt, th)
+    a, b = v[:, 0] * dt / dx, v[:, 1] * dt / dy
+    for p, (tx, ty) in enumerate(th):
+        adv = (1 - 1j * a * math.sin(tx) + a * a * (math.cos(tx) - 1)
+               - 1j * b * math.sin(ty) + b * b * (math.cos(ty) - 1))
+        cost = np.abs(adv[:, None] - got[p][None, :])
+        ri, ci = linear_sum_assignment(cost)
+        assert np.max(cost[ri, ci]) <= 4 * U, (p, np.max(cost[ri, ci]))
+
+
+def test_fig2_curve_along_k_dx(screen):
+    """Sect. IV's Fig. 2 axes (max |omega| against k dx, k dy = 0) at 721
+    points for both rate sets: the GPU curves match numpy's at every 40th
+    point, and their maxima are the numpy screen's (SRT 1 + 1.2e-6, MRT
+    1.0034)."""
+    th = np.stack([np.linspace(0.0, math.pi, 721), np.zeros(721)], axis=1)
+    mats = ref.model()
+    for name, expect in (("fig2_srt", (1.0, 1.00001)), ("fig2_mrt", (1.003, 1.004))):
+        state, s, dx, dt = CASES[name]
+        K = construction_scale(state, s, dt, mats)
+        got = screen.spectral_radius(state, s, dx, dx, dt, th)
+        for p in range(0, 721, 40):
+            G = ref.amplification(state, s, dx, dx, dt, th[p, 0], 0.0, mats)
+            _, wmax, tmax = compare(np.zeros(16), G, K)
+            assert abs(got[p] - wmax) <= tmax, (name, p, got[p], wmax, tmax)
+        i = int(np.argmax(got))
+        print(f"{name}: max |omega| along k dx {got[i]:.9f} at k dx {th[i, 0]:.4f}")
+        assert expect[0] < got[i] < expect[1]
+
+
+def test_tube_batch_states_along_the_tube(screen):
+    """The 512-tube batch starts uniform across its 4 periodic rows, so only
+    modes with k dy = 0 are present; along k dx (361 points) every end and
+    star state grows by at most 4 times over its tube's run.  Across the
+    rows the screen does find growth: at the star state of tube 272 (rho,
+    u, T) = (0.331, 4.39, 176), k dy = pi / 2 (a mode the 4-row tube can
+    hold) gives max |omega| = 1.0006 per step, and an oblique phase 1.0017;
+    that mode never starts because the rows stay equal bit for bit
+    (test_gpu_tubes checks them), but a 2D run at that state would not."""
+    def star(L, R):
+        W = riemann.wave_speeds(L, R)
+        return (riemann.max_signal_speed(L, R), min(W["rho_star_left"], W["rho_star_right"]),
+                W["pstar"] / min(W["rho_star_left"], W["rho_star_right"]))
+
+    batch = synth.tube_batch(star_fn=star)
+    dx, dt, s = batch["dx"], batch["dt"], batch["s"]
+    along = np.stack([np.linspace(0.0, math.pi, 361), np.zeros(361)], axis=1)
+    worst, where = 0.0, None
+    for k, t in enumerate(batch["tubes"]):
+        L, R = t["left"], t["right"]
+        W = riemann.wave_speeds(L, R)
+        states = [(L[0], L[1], L[2] / L[0]), (R[0], R[1], R[2] / R[0]),
+                  (W["rho_star_left"], W["ustar"], W["pstar"] / W["rho_star_left"]),
+                  (W["rho_star_right"], W["ustar"], W["pstar"] / W["rho_star_right"])]
+        for rho, u, T in states:
+            w = float(np.max(screen.spectral_radius((rho, u, 0.0, T), s, dx, dx, dt, along)))
+            g = t["steps"] * math.log(max(w, 1.0))
+            if g > worst:
+                worst, where = g, (k, rho, u, T, w)
+    print("largest growth over a run along the tubes", math.exp(worst), "tube, state, max |omega|:", where)
+    assert math.exp(worst) <= 4.0
+    t = batch["tubes"][272]
+    W = riemann.wave_speeds(t["left"], t["right"])
+    hot = (W["rho_star_right"], W["ustar"], 0.0, W["pstar"] / W["rho_star_right"])
+    across = np.stack([np.linspace(0.0, math.pi, 97), np.full(97, math.pi / 2)], axis=1)
+    w_across = float(np.max(screen.spectral_radius(hot, s, dx, dx, dt, across)))
+    w_2d = screen.max_growth(hot, s, dx, dx, dt, n=12)[0]
+    print("tube 272 star state", hot, "k dy = pi/2:", w_across, "any phase:", w_2d)
+    assert 1.0005 < w_across < w_2d
+
+
+def test_screen_throughput(screen):
+    """A 65 x 129 phase grid (8385 matrices) at the Fig. 2 state, timed
+    after a warm-up call; numpy's time for 200 of the same matrices beside
+    it.  Reported, not asserted beyond finiteness."""
+    import torch
+
+    state, s, dx, dt = CASES["fig2_mrt"]
+    th = screen.phase_grid(64)
+    screen.spectral_radius(state, s, dx, dx, dt, th)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w = screen.spectral_radius(state, s, dx, dx, dt, th)
+    gpu_s = time.perf_counter() - t0
+    mats = ref.model()
+    t0 = time.perf_counter()
+    for a, b in th[:200]:
+        np.linalg.eigvals(ref.amplification(state, s, dx, dx, dt, a, b, mats))
+    cpu_s = (time.perf_counter() - t0) / 200 * len(th)
+    print(f"screen: {len(th)} phase pairs in {gpu_s * 1e3:.2f} ms on the GPU (call to result on the host), "
+          f"numpy {cpu_s * 1e3:.0f} ms estimated from 200")
+    assert np.all(np.isfinite(w))
