@@ -318,7 +318,7 @@ int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_
  * <= 1 over all phases.  For n phase pairs d_theta[2 p], d_theta[2 p + 1]
  * (device array of 2 n doubles) computes the 16 eigenvalues of G in FP64
  * (balancing, Householder reduction to Hessenberg form and the shifted QR
- * algorithm, one block per phase pair) and writes them, largest modulus
+ * algorithm, four phase pairs per wave) and writes them, largest modulus
  * first, as (re, im) pairs to d_eig[32 p .. 32 p + 31], and the largest
  * modulus to d_rho[p] (device arrays of 32 n and n doubles; either may be
  * NULL, not both).  They are the exact eigenvalues of some G + E with ||E||

@@ -1272,20 +1272,23 @@ __global__ __launch_bounds__(256) void k_unpack(Field F, const Src *__restrict__
 }
 
 // Von Neumann screen: all 16 eigenvalues of the amplification matrix G of
-// Sect. IV for one phase pair per block of one wave, FP64 complex (double2 =
-// re, im) in LDS.  G is first balanced (Parlett and Reinsch 1969: row and
-// column i scaled by powers of 2, which is exact, until their 1-norms are
-// within a factor 2), then brought to upper Hessenberg form by Householder
-// reflections, then reduced by the shifted QR algorithm (Francis 1961;
-// Golub and Van Loan, Matrix Computations, Sect. 7.5) on the active window
-// only, since only the eigenvalues are wanted: each step takes the
-// Wilkinson shift of the trailing 2 x 2 block (an ad hoc shift every 10th
-// step without deflation), factors H - mu I by Givens rotations, forms R Q +
-// mu I, and deflates a subdiagonal entry once it is below the unit roundoff
-// times its two diagonal neighbours.  Every lane computes the control flow
-// and the rotation scalars from the same LDS values, so branches and
-// barriers are uniform over the block.
-constexpr int SCREEN_THREADS = 64;
+// Sect. IV for one phase pair per group of 16 lanes (four per wave), FP64
+// complex (double2 = re, im) in LDS.  G is first balanced (Parlett and
+// Reinsch 1969: row and column i scaled by powers of 2, which is exact,
+// until their 1-norms are within a factor 2), then brought to upper
+// Hessenberg form by Householder reflections, then reduced by the shifted
+// QR algorithm (Francis 1961; Golub and Van Loan, Matrix Computations,
+// Sect. 7.5) on the active window only, since only the eigenvalues are
+// wanted: each step takes the Wilkinson shift of the trailing 2 x 2 block
+// (an ad hoc shift every 10th step without deflation), factors H - mu I by
+// Givens rotations, forms R Q + mu I, and deflates a subdiagonal entry once
+// it is below the unit roundoff times its two diagonal neighbours.  The 16
+// lanes of a group compute the same control flow and rotation scalars from
+// the same LDS values, so branches are uniform within a group; groups share
+// nothing, and a group's lanes order their LDS accesses by wave-scope
+// fences (one wave executes its LDS instructions in order).
+constexpr int SCREEN_GROUP = 16;                     // lanes per matrix
+constexpr int SCREEN_PER_BLOCK = 64 / SCREEN_GROUP;  // matrices per wave (one wave per block)
 constexpr int SCREEN_MAX_STEPS = 30 * NQ;
 
 __device__ inline double2 c_mul(double2 a, double2 b)
@@ -1322,37 +1325,83 @@ __device__ inline double2 c_sqrt(double2 z)  // principal root, no cancellation
     return make_double2(fabs(z.y) / (2.0 * t), copysign(t, z.y));
 }
 
-__global__ __launch_bounds__(SCREEN_THREADS) void k_screen(ScreenCoef S, const double *__restrict__ theta,
-                                                           double *__restrict__ eig, double *__restrict__ rho)
+__device__ inline void wave_sync()
 {
-    __shared__ double2 A[NQ][NQ];
-    __shared__ double2 v[NQ], w[NQ];
-    __shared__ double rc[NQ];
-    __shared__ double2 rs[NQ], ev[NQ];
-    const int p = blockIdx.x, t = threadIdx.x;
-    const double tx = theta[2 * p], ty = theta[2 * p + 1];
-    for (int e = t; e < NQ * NQ; e += SCREEN_THREADS) {
-        const int r = e / NQ, c = e % NQ;
-        double2 g = make_double2(-S.C[r][c], 0.0);
-        if (r == c) {
-            const double a = S.a[r], b = S.b[r];
-            g.x += 1.0 + a * a * (cos(tx) - 1.0) + b * b * (cos(ty) - 1.0);
-            g.y -= a * sin(tx) + b * sin(ty);
-        }
-        A[r][c] = g;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over the 16 lanes of a group by a fixed butterfly: every lane gets the
+// same bits (each addition pairs the same two values, and + commutes).
+__device__ inline double group_sum(double x)
+{
+    x += __shfl_xor(x, 8, SCREEN_GROUP);
+    x += __shfl_xor(x, 4, SCREEN_GROUP);
+    x += __shfl_xor(x, 2, SCREEN_GROUP);
+    x += __shfl_xor(x, 1, SCREEN_GROUP);
+    return x;
+}
+
+// Givens rotation [[c, s], [-conj(s), c]] (c real) that zeroes b against a:
+// c = |a| / r, s = conj(b) a / (|a| r), r = sqrt(|a|^2 + |b|^2), with a and b
+// first scaled exactly by the power of 2 that brings max(|a|_1, |b|_1) into
+// [1/2, 1), so that no square under- or overflows; a = 0 gives the swap (0,
+// 1), a = b = 0 the identity.
+__device__ inline void givens(double2 a, double2 b, double &c, double2 &s)
+{
+    const double m = fmax(c_abs1(a), c_abs1(b));
+    if (m == 0.0) {
+        c = 1.0;
+        s = make_double2(0.0, 0.0);
+        return;
     }
-    __syncthreads();
+    int e;
+    frexp(m, &e);
+    a = make_double2(ldexp(a.x, -e), ldexp(a.y, -e));
+    b = make_double2(ldexp(b.x, -e), ldexp(b.y, -e));
+    const double na2 = a.x * a.x + a.y * a.y, r2 = na2 + b.x * b.x + b.y * b.y;
+    if (na2 < 0x1p-1000) {  // |a| below 2^-500 |b|: a rotation by pi / 2 leaves at most |a| behind
+        c = 0.0;
+        s = make_double2(1.0, 0.0);
+        return;
+    }
+    const double rinv = rsqrt(na2 * r2);  // 1 / (|a| r)
+    c = na2 * rinv;
+    s = c_scale(c_conj_mul(b, a), rinv);
+}
+
+__global__ __launch_bounds__(64) void k_screen(ScreenCoef S, const double *__restrict__ theta, int n,
+                                               double *__restrict__ eig, double *__restrict__ rho)
+{
+    __shared__ double2 As[SCREEN_PER_BLOCK][NQ][NQ];
+    __shared__ double2 vs[SCREEN_PER_BLOCK][NQ], ws[SCREEN_PER_BLOCK][NQ];
+    __shared__ double rcs[SCREEN_PER_BLOCK][NQ], mods[SCREEN_PER_BLOCK][NQ];
+    __shared__ double2 rss[SCREEN_PER_BLOCK][NQ], evs[SCREEN_PER_BLOCK][NQ];
+    const int g = threadIdx.x / SCREEN_GROUP, t = threadIdx.x % SCREEN_GROUP;
+    const int p = blockIdx.x * SCREEN_PER_BLOCK + g;
+    if (p >= n) return;  // the whole group
+    auto &A = As[g];
+    double2 *v = vs[g], *w = ws[g], *rs = rss[g], *ev = evs[g];
+    double *rc = rcs[g], *mod = mods[g];
+    const double tx = theta[2 * p], ty = theta[2 * p + 1];
+    for (int r = 0; r < NQ; ++r) {  // lane t builds column t
+        double2 e = make_double2(-S.C[r][t], 0.0);
+        if (r == t) {
+            const double a = S.a[r], b = S.b[r];
+            e.x += 1.0 + a * a * (cos(tx) - 1.0) + b * b * (cos(ty) - 1.0);
+            e.y -= a * sin(tx) + b * sin(ty);
+        }
+        A[r][t] = e;
+    }
+    wave_sync();
 
     // balancing
     for (int sweep = 0; sweep < 40; ++sweep) {
         bool changed = false;
         for (int i = 0; i < NQ; ++i) {
-            double c = 0.0, r = 0.0;
-            for (int j = 0; j < NQ; ++j)
-                if (j != i) {
-                    c += c_abs1(A[j][i]);
-                    r += c_abs1(A[i][j]);
-                }
+            double c = group_sum(t != i ? c_abs1(A[t][i]) : 0.0);
+            const double r = group_sum(t != i ? c_abs1(A[i][t]) : 0.0);
             if (!(c > 0.0 && r > 0.0 && isfinite(c + r))) continue;
             const double s0 = c + r;
             double f = 1.0;
@@ -1366,10 +1415,12 @@ __global__ __launch_bounds__(SCREEN_THREADS) void k_screen(ScreenCoef S, const d
             }
             if ((c + r) / f < 0.95 * s0) {  // c is now c f^2: new column + row norm < 0.95 old
                 changed = true;
-                __syncthreads();
-                if (t < NQ && t != i) A[i][t] = c_scale(A[i][t], 1.0 / f);
-                else if (t >= NQ && t < 2 * NQ && t - NQ != i) A[t - NQ][i] = c_scale(A[t - NQ][i], f);
-                __syncthreads();
+                wave_sync();
+                if (t != i) {
+                    A[i][t] = c_scale(A[i][t], 1.0 / f);
+                    A[t][i] = c_scale(A[t][i], f);
+                }
+                wave_sync();
             }
         }
         if (!changed) break;
@@ -1377,8 +1428,8 @@ __global__ __launch_bounds__(SCREEN_THREADS) void k_screen(ScreenCoef S, const d
 
     // Householder reduction to upper Hessenberg form
     for (int k = 0; k + 2 < NQ; ++k) {
-        double tail = 0.0;
-        for (int i = k + 2; i < NQ; ++i) tail += A[i][k].x * A[i][k].x + A[i][k].y * A[i][k].y;
+        const double2 xt = A[t][k];
+        const double tail = group_sum(t >= k + 2 ? xt.x * xt.x + xt.y * xt.y : 0.0);
         if (tail == 0.0) continue;
         const double2 x0 = A[k + 1][k];
         const double a0 = c_abs(x0);
@@ -1386,32 +1437,31 @@ __global__ __launch_bounds__(SCREEN_THREADS) void k_screen(ScreenCoef S, const d
         const double2 ph = a0 > 0.0 ? c_scale(x0, 1.0 / a0) : make_double2(1.0, 0.0);
         const double2 alpha = c_scale(ph, -xn);           // v = x - alpha e_1: no cancellation in v_0
         const double tau = 1.0 / (xn * (xn + a0));        // 2 / (v^H v)
-        if (t > k && t < NQ) v[t] = t == k + 1 ? c_scale(ph, a0 + xn) : A[t][k];
-        __syncthreads();
-        if (t > k && t < NQ) {  // w_j = v^H A(:, j) over rows k + 1 ..
+        if (t > k) v[t] = t == k + 1 ? c_scale(ph, a0 + xn) : xt;
+        wave_sync();
+        if (t > k) {  // w_t = v^H A(:, t) over rows k + 1 ..
             double2 acc = make_double2(0.0, 0.0);
             for (int i = k + 1; i < NQ; ++i) acc = c_add(acc, c_conj_mul(v[i], A[i][t]));
             w[t] = acc;
         }
-        __syncthreads();
-        for (int e = t; e < NQ * NQ; e += SCREEN_THREADS) {
-            const int r = e / NQ, c = e % NQ;
-            if (r <= k) continue;
-            if (c == k) A[r][c] = r == k + 1 ? alpha : make_double2(0.0, 0.0);
-            else if (c > k) A[r][c] = c_sub(A[r][c], c_scale(c_mul(v[r], w[c]), tau));
-        }
-        __syncthreads();
-        if (t < NQ) {  // z_r = A(r, :) v over columns k + 1 ..
+        wave_sync();
+        if (t == k)
+            for (int r = k + 1; r < NQ; ++r) A[r][k] = r == k + 1 ? alpha : make_double2(0.0, 0.0);
+        else if (t > k)
+            for (int r = k + 1; r < NQ; ++r) A[r][t] = c_sub(A[r][t], c_scale(c_mul(v[r], w[t]), tau));
+        wave_sync();
+        {  // z_t = A(t, :) v over columns k + 1 ..
             double2 acc = make_double2(0.0, 0.0);
             for (int j = k + 1; j < NQ; ++j) acc = c_add(acc, c_mul(A[t][j], v[j]));
+            wave_sync();
             w[t] = acc;
         }
-        __syncthreads();
-        for (int e = t; e < NQ * NQ; e += SCREEN_THREADS) {
-            const int r = e / NQ, c = e % NQ;
-            if (c > k) A[r][c] = c_sub(A[r][c], c_scale(c_mul(w[r], make_double2(v[c].x, -v[c].y)), tau));
+        wave_sync();
+        if (t > k) {
+            const double2 vc = make_double2(v[t].x, -v[t].y);
+            for (int r = 0; r < NQ; ++r) A[r][t] = c_sub(A[r][t], c_scale(c_mul(w[r], vc), tau));
         }
-        __syncthreads();
+        wave_sync();
     }
 
     // shifted QR on the active window [l, hi]
@@ -1419,11 +1469,13 @@ __global__ __launch_bounds__(SCREEN_THREADS) void k_screen(ScreenCoef S, const d
     int hi = NQ - 1, since = 0, steps = 0;
     bool failed = false;
     while (hi >= 0) {
-        int l = hi;
-        for (; l > 0; --l) {
-            const double sub = c_abs1(A[l][l - 1]);
-            if (sub <= ulp * (c_abs1(A[l - 1][l - 1]) + c_abs1(A[l][l])) || sub < 0x1p-1000) break;
+        bool small = false;
+        if (t >= 1 && t <= hi) {
+            const double sub = c_abs1(A[t][t - 1]);
+            small = sub <= ulp * (c_abs1(A[t - 1][t - 1]) + c_abs1(A[t][t])) || sub < 0x1p-1000;
         }
+        const unsigned mask = (unsigned)(__ballot(small) >> (SCREEN_GROUP * g)) & 0xffffu;
+        const int l = mask ? 31 - __clz(mask) : 0;  // the last negligible subdiagonal entry at or above hi
         if (l == hi) {
             if (t == 0) ev[hi] = A[hi][hi];
             --hi;
@@ -1448,22 +1500,14 @@ __global__ __launch_bounds__(SCREEN_THREADS) void k_screen(ScreenCoef S, const d
             const double2 den = c_abs1(d1) >= c_abs1(d2) ? d1 : d2;
             mu = c_abs1(den) > 0.0 ? c_sub(d, c_div(bc, den)) : d;
         }
-        __syncthreads();
+        wave_sync();
         if (t >= l && t <= hi) A[t][t] = c_sub(A[t][t], mu);
-        __syncthreads();
+        wave_sync();
         for (int k = l; k < hi; ++k) {  // H - mu I = Q R, rotation k zeroes (k + 1, k)
-            const double2 a = A[k][k], b = A[k + 1][k];
-            const double na = c_abs(a), r = hypot(na, c_abs(b));
             double cr;
             double2 sr;
-            if (na == 0.0) {
-                cr = 0.0;
-                sr = make_double2(1.0, 0.0);
-            } else {
-                cr = na / r;
-                sr = c_scale(c_conj_mul(b, a), 1.0 / (na * r));  // conj(b) a / (|a| r)
-            }
-            __syncthreads();
+            givens(A[k][k], A[k + 1][k], cr, sr);
+            wave_sync();
             if (t == 0) {
                 rc[k] = cr;
                 rs[k] = sr;
@@ -1473,7 +1517,7 @@ __global__ __launch_bounds__(SCREEN_THREADS) void k_screen(ScreenCoef S, const d
                 A[k][t] = c_add(c_scale(x, cr), c_mul(sr, y));
                 A[k + 1][t] = c_sub(c_scale(y, cr), c_conj_mul(sr, x));
             }
-            __syncthreads();
+            wave_sync();
         }
         for (int k = l; k < hi; ++k) {  // R Q: columns k, k + 1 times the rotation's adjoint
             const double cr = rc[k];
@@ -1483,29 +1527,32 @@ __global__ __launch_bounds__(SCREEN_THREADS) void k_screen(ScreenCoef S, const d
                 A[t][k] = c_add(c_scale(x, cr), c_mul(y, make_double2(sr.x, -sr.y)));
                 A[t][k + 1] = c_sub(c_scale(y, cr), c_mul(x, sr));
             }
-            __syncthreads();
+            wave_sync();
         }
         if (t >= l && t <= hi) A[t][t] = c_add(A[t][t], mu);
-        __syncthreads();
+        wave_sync();
     }
-    __syncthreads();
-    if (t == 0) {  // largest modulus first
-        if (failed)
-            for (int i = 0; i < NQ; ++i) ev[i] = make_double2(NAN, NAN);
-        for (int i = 1; i < NQ; ++i) {
-            const double2 x = ev[i];
-            const double m = c_abs(x);
-            int j = i;
-            for (; j > 0 && c_abs(ev[j - 1]) < m; --j) ev[j] = ev[j - 1];
-            ev[j] = x;
-        }
-        if (rho) rho[p] = failed ? NAN : c_abs(ev[0]);
+    wave_sync();
+    // largest modulus first: lane t places its eigenvalue at its rank (ties by index)
+    double2 e = failed ? make_double2(NAN, NAN) : ev[t];
+    double m = failed ? NAN : c_abs(e);
+    if ((__ballot(isnan(m)) >> (SCREEN_GROUP * g)) & 0xffffu) {  // NaN anywhere: all NaN, in lane order
+        e = make_double2(NAN, NAN);
+        m = NAN;
     }
-    __syncthreads();
-    if (eig && t < NQ) {
-        eig[(long long)p * 2 * NQ + 2 * t] = ev[t].x;
-        eig[(long long)p * 2 * NQ + 2 * t + 1] = ev[t].y;
+    mod[t] = m;
+    wave_sync();
+    int rank = 0;
+    for (int j = 0; j < NQ; ++j) {
+        const double mj = mod[j];
+        rank += (mj > m || (mj == m && j < t)) ? 1 : 0;
     }
+    if (isnan(m)) rank = t;
+    if (eig) {
+        eig[(long long)p * 2 * NQ + 2 * rank] = e.x;
+        eig[(long long)p * 2 * NQ + 2 * rank + 1] = e.y;
+    }
+    if (rho && rank == 0) rho[p] = m;
 }
 
 inline unsigned blocks_for(long long n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -1756,7 +1803,7 @@ hipError_t launch_screen(const ScreenCoef &S, const double *theta, int n, double
                          hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_screen, dim3(n), dim3(SCREEN_THREADS), 0, s, S, theta, eig, rho);
+    hipLaunchKernelGGL(k_screen, dim3(blocks_for(n, SCREEN_PER_BLOCK)), dim3(64), 0, s, S, theta, n, eig, rho);
     return hipGetLastError();
 }
 
