@@ -338,12 +338,69 @@ def bench_batch(with_separate=True, with_accuracy=True, no_graph=False):
     return out
 
 
+# FP64 flops per matrix of the von Neumann screen at the Fig. 2 state,
+# counted on a replica of the kernel's steps: balancing and the Householder
+# reduction ~5.0e4, ~42 shifted QR steps ~9.7e4.
+SCREEN_FLOPS_PER_MATRIX = 1.5e5
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def bench_screen(reps=20, cpu_sample=200):
+    """The von Neumann screen (Sect. IV) at the Fig. 2 state over a 65 x 129
+    phase grid (8385 matrices): the kernel timed with HIP events on the
+    stream it runs on, the numpy screen (the oracle's matrix, LAPACK's
+    eigenvalues, one host core) timed on the first cpu_sample matrices, and
+    the agreement of max |omega| between the two on that sample."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0908_3749_amd import stability
+
+    state, dx, dt = (2.0, 10.0, 0.0, 2.0), 2e-3, 1e-5
+    s = synth.rates(dt, s5=6500, s7=9e4, s8=9e4, s9=8e4, s13=7e4, s14=8e3, s15=2.5e4)
+    th = stability.phase_grid(64)
+    n = th.shape[0]
+    d_th = torch.from_numpy(np.ascontiguousarray(th)).cuda()
+    d_rho = torch.empty(n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    stability.screen_into(state, s, dx, dx, dt, d_th, d_rho, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        stability.screen_into(state, s, dx, dx, dt, d_th, d_rho, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    rho = d_rho.cpu().numpy()
+    from oracle import stability as ref  # the numpy screen, timed beside
+
+    mats = ref.model()
+    t0 = time.perf_counter()
+    want = np.array([np.max(np.abs(np.linalg.eigvals(ref.amplification(state, s, dx, dx, dt, a, b, mats))))
+                     for a, b in th[:cpu_sample]])
+    cpu_s = time.perf_counter() - t0
+    tflops = SCREEN_FLOPS_PER_MATRIX * n / (ms * 1e-3) / 1e12
+    return {"value": round(n / (ms * 1e-3), 1), "unit": "matrices/s", "matrices": n, "ms_per_call": round(ms, 4),
+            "max_omega": float(rho.max()),
+            "roofline": {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4),
+                         "flops_per_matrix": SCREEN_FLOPS_PER_MATRIX,
+                         "note": "bound by each matrix's chain of dependent rotations, not by the FP64 rate"},
+            "cpu_baseline": {"value": round(cpu_sample / cpu_s, 1), "unit": "matrices/s", "cores": 1,
+                             "kind": "oracle", "sample": f"the first {cpu_sample} of the same matrices, numpy"},
+            "max_rel_diff_vs_numpy": float(f"{np.max(np.abs(rho[:cpu_sample] - want) / want):.3e}"),
+            "config": "state (2, 10, 0, 2), dx = dy = 2e-3, dt = 1e-5, the printed MRT rates (Fig. 2), "
+                      "phase pairs over [0, pi] x [-pi, pi]"}
+
+
 def comparison(warmup):
     """The metric's other forms in the same run: the Mach-3 reflection
     (2048x512, cache-resident) and the shock-bubble (4096x1024) in FP32, the
     Couette 8192x2048 with the split-BF16x3 matrix-core transforms and in
     FP64 (populations stored in FP64: 256 B per node update), each 2000
-    timed steps after the set-up and warm-up; and the 512-tube batch."""
+    timed steps after the set-up and warm-up; the 512-tube batch; and the
+    von Neumann screen of Sect. IV."""
     import synth
 
     out = {}
@@ -365,6 +422,7 @@ def comparison(warmup):
                      "bytes_per_node_update": per_node,
                      "kernel": variant_name(v), "steps": n, "graph_steps": G}
     out["batched"] = bench_batch()
+    out["stability_screen_fig2_8385"] = bench_screen()
     return out
 
 
@@ -390,6 +448,8 @@ def main():
                     help="1: after the headline run, time the same workload with the FP64 "
                          "outflow budget on (up to 2000 steps) and report it beside")
     ap.add_argument("--no-graph", action="store_true", help="tubes: launch rounds directly")
+    ap.add_argument("--screen", action="store_true",
+                    help="only time the von Neumann screen (as in the comparison) and print it")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only time a plain device copy of MIB MiB (the reference for the HBM "
                          "byte counters and for achievable bandwidth) and exit")
@@ -426,6 +486,9 @@ def main():
         ms = e0.elapsed_time(e1) / reps
         print(json.dumps({"copy_mib": args.calibrate_copy, "bytes_read": 4 * n, "bytes_written": 4 * n,
                           "ms": round(ms, 4), "gbs_read_plus_write": round(8 * n / ms / 1e6, 1)}), flush=True)
+        return 0
+    if args.screen:
+        print(json.dumps(bench_screen()), flush=True)
         return 0
     if args.config == "tubes":
         out = bench_batch(with_separate=not args.no_cpu, with_accuracy=not args.no_cpu,

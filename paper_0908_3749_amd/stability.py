@@ -13,6 +13,24 @@ _PERIODIC = {"kind_lo": "periodic", "kind_hi": "periodic", "state_lo": (1.0, 0.0
              "state_hi": (1.0, 0.0, 0.0, 1.0), "split0": math.inf, "split_rate": 0.0}
 
 
+def screen_into(state, s, dx, dy, dt, d_theta, d_rho=None, d_eig=None, stream=None):
+    """Enqueue the screen on torch device tensors without synchronising:
+    d_theta (n, 2) float64 phase pairs, d_rho (n,) and/or d_eig (n, 16, 2)
+    float64 outputs; stream = a torch stream (default: the current one)."""
+    import torch
+
+    n = int(d_theta.shape[0])
+    for t in (d_theta, d_rho, d_eig):
+        assert t is None or (t.dtype == torch.float64 and t.is_contiguous() and t.is_cuda)
+    p = make_params(3, 3, dx, dy, dt, s, {k: dict(_PERIODIC) for k in ("west", "east", "south", "north")})
+    st = (C.c_double * 4)(*[float(v) for v in state])
+    stream = stream if stream is not None else torch.cuda.current_stream(d_theta.device)
+    check(lib().mrtfd_screen(C.byref(p), st, C.c_void_p(d_theta.data_ptr()), n,
+                             C.c_void_p(d_eig.data_ptr() if d_eig is not None else 0),
+                             C.c_void_p(d_rho.data_ptr() if d_rho is not None else 0),
+                             C.c_void_p(stream.cuda_stream)))
+
+
 def _screen(state, s, dx, dy, dt, theta, device, want_eig):
     import torch
 
@@ -22,12 +40,8 @@ def _screen(state, s, dx, dy, dt, theta, device, want_eig):
     d_th = torch.from_numpy(th).to(dev)
     rho = torch.empty(n, dtype=torch.float64, device=dev)
     eig = torch.empty((n, 16, 2), dtype=torch.float64, device=dev) if want_eig else None
-    p = make_params(3, 3, dx, dy, dt, s, {k: dict(_PERIODIC) for k in ("west", "east", "south", "north")})
-    st = (C.c_double * 4)(*[float(v) for v in state])
     stream = torch.cuda.current_stream(dev)
-    check(lib().mrtfd_screen(C.byref(p), st, C.c_void_p(d_th.data_ptr()), n,
-                             C.c_void_p(eig.data_ptr() if want_eig else 0), C.c_void_p(rho.data_ptr()),
-                             C.c_void_p(stream.cuda_stream)))
+    screen_into(state, s, dx, dy, dt, d_th, rho, eig, stream)
     stream.synchronize()
     r = rho.cpu().numpy()
     if not want_eig:
