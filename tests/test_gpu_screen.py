@@ -136,6 +136,35 @@ def test_eigenvalues_match_numpy(screen, name):
     assert worst <= 1.0
 
 
+@pytest.mark.parametrize("seed", range(500, 524))
+def test_random_parameter_sets_match_numpy(screen, seed):
+    """Seeded draws: rho in [0.2, 5], u in [-4, 4]^2, T log-uniform in [0.1,
+    100], the twelve rates log-uniform in [100, 1 / dt], dx and dy
+    log-uniform in [1e-3, 1e-2], dt = 1e-5; eight phase pairs (theta = 0 and
+    seven drawn); every eigenvalue within its bound, and max |omega| within
+    the bound of numpy's largest."""
+    rng = np.random.default_rng(seed)
+    dt = 1e-5
+    state = (float(rng.uniform(0.2, 5.0)), float(rng.uniform(-4, 4)), float(rng.uniform(-4, 4)),
+             float(np.exp(rng.uniform(np.log(0.1), np.log(100.0)))))
+    s = [0.0] * 4 + [float(v) for v in np.exp(rng.uniform(np.log(100.0), np.log(1.0 / dt), 12))]
+    dx, dy = (float(np.exp(rng.uniform(np.log(1e-3), np.log(1e-2)))) for _ in range(2))
+    th = np.vstack([np.zeros((1, 2)), rng.uniform(-math.pi, math.pi, (7, 2))])
+    mats = ref.model()
+    K = construction_scale(state, s, dt, mats)
+    got = screen.eigenvalues(state, s, dx, dy, dt, th)
+    rho = screen.spectral_radius(state, s, dx, dy, dt, th)
+    worst = 0.0
+    for p, (a, b) in enumerate(th):
+        G = ref.amplification(state, s, dx, dy, dt, a, b, mats)
+        r, wmax, tmax = compare(got[p], G, K)
+        worst = max(worst, r)
+        assert abs(rho[p] - wmax) <= tmax, (seed, p, rho[p], wmax, tmax)
+    print(f"seed {seed}: state {tuple(round(v, 3) for v in state)}, dx {dx:.2e}, dy {dy:.2e}: max |omega| "
+          f"{rho.max():.9f}, worst eigenvalue difference {worst:.3f} of its bound")
+    assert worst <= 1.0
+
+
 @pytest.mark.parametrize("name", ["sod_left", "high_mach_west", "colella_hot", "fig2_mrt"])
 def test_uniform_mode_closed_form(screen, name):
     """theta = 0: G = I - dt M^-1 S (M - J M_c) has the eigenvalues 1 (x4)
