@@ -43,7 +43,7 @@ ALU_LANE_OPS_PER_CU_CLOCK = 64
 OPS_PER_UPDATE = 330
 ALU_NODE_RATE = 256 * ALU_LANE_OPS_PER_CU_CLOCK * 2.4e9 / OPS_PER_UPDATE
 BYTES_PER_UPDATE = 128  # 16 FP32 populations read + 16 written
-SETUP_STEPS = 1024      # untimed: covers the autotuner's trials (<= ~600 steps) and graph capture
+SETUP_STEPS = 1024      # untimed: covers the autotuner's trials (<= ~620 steps) and graph capture
 KERNEL_SRCS = [os.path.join(ROOT, "paper_0908_3749_amd", "csrc", f) for f in ("mrtfd_kernels.hip", "mrtfd_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 COUETTE_REF = os.path.join(ROOT, "tests", "golden", "couette_256x2048_50000.npz")

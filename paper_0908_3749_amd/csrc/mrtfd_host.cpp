@@ -916,7 +916,9 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
         return MRTFD_OK;
     }
     const double cells = (double)c->p.nx * c->p.ny;
-    const long long reps = 2 * (long long)std::max(4.0, std::min(16.0, 1e7 / cells));
+    // at least ~1.5 ms of steps per timed trial (about 3.4e7 node updates),
+    // 8 to 32 steps
+    const long long reps = 2 * (long long)std::max(4.0, std::min(16.0, 3.4e7 / cells));
     const long long warm = 2;
     const int passes = 2;
     if (avail < passes * (long long)cands.size() * (reps + warm)) return MRTFD_OK;

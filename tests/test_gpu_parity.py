@@ -572,7 +572,7 @@ def _steps_to_autotune(nx, ny):
     its candidates (rows per wave x store kind x tile order, plus the simple
     kernel; two passes), plus a few steps of the chosen variant."""
     cells = nx * ny
-    reps = 2 * int(max(4.0, min(16.0, 1e7 / cells)))
+    reps = 2 * int(max(4.0, min(16.0, 3.4e7 / cells)))
     ncand = 9 if ((nx + 63) // 64) % 8 == 0 else 5
     return 2 * ncand * (reps + 2) + 4
 
@@ -638,7 +638,7 @@ def test_full_size_bf16x3_couette_matches_oracle(gpu):
     prob = synth.couette()
     ref = (1.0, 1.0)
     cells = prob.nx * prob.ny
-    reps = 2 * int(max(4.0, min(16.0, 1e7 / cells)))
+    reps = 2 * int(max(4.0, min(16.0, 3.4e7 / cells)))
     # rows per wave x store kind x tile order
     ncand = 8 if ((prob.nx + 63) // 64) % 8 == 0 else 4
     n = 2 * ncand * (reps + 2) + 4
