@@ -201,6 +201,23 @@ def test_zero_rates_give_the_lax_wendroff_factors(screen):
         assert np.max(cost[ri, ci]) <= 4 * U, (p, np.max(cost[ri, ci]))
 
 
+def test_non_finite_phase_gives_nan_for_that_matrix_only(screen):
+    """A NaN or infinite phase pair makes its matrix NaN: the QR iteration
+    finds nothing to deflate, stops after its 480 steps and writes NaN for
+    all 16 eigenvalues and max |omega|; the other matrices of the same wave
+    (four per wave) and of the call keep their values bit for bit."""
+    state, s, dx, dt = CASES["sod_left"]
+    th = np.array([[0.3, -0.2], [math.nan, 0.0], [1.1, 0.4], [0.5, math.inf], [2.0, 1.0], [0.7, 0.7]])
+    got = screen.eigenvalues(state, s, dx, dx, dt, th)
+    rho = screen.spectral_radius(state, s, dx, dx, dt, th)
+    bad = [1, 3]
+    assert np.all(np.isnan(got[bad])) and np.all(np.isnan(rho[bad]))
+    good = [0, 2, 4, 5]
+    alone = screen.eigenvalues(state, s, dx, dx, dt, th[good])
+    np.testing.assert_array_equal(got[good], alone)
+    np.testing.assert_array_equal(rho[good], screen.spectral_radius(state, s, dx, dx, dt, th[good]))
+
+
 def test_fig2_curve_along_k_dx(screen):
     """Sect. IV's Fig. 2 axes (max |omega| against k dx, k dy = 0) at 721
     points for both rate sets: the GPU curves match numpy's at every 40th
