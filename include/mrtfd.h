@@ -333,6 +333,27 @@ int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_
 int32_t mrtfd_screen(const mrtfd_params *p, const double state[4], const double *d_theta, int32_t n,
                      double *d_eig, double *d_rho, void *stream);
 
+/* The von Neumann screen of Sect. IV over many parameter sets at once, for
+ * searches over states and rates.  Set q (0 <= q < nsets) has the uniform
+ * state d_states[4 q .. 4 q + 3] = (rho, u1, u2, T) and the 16 rates
+ * d_rates[16 q .. 16 q + 15] (device arrays); the spacing and time step
+ * come from p (its rates and boundary fields are validated but not used).
+ * For the n phase pairs d_theta (device, 2 n doubles) shared by all sets,
+ * writes max |omega| of G (as mrtfd_screen) for set q at pair j to
+ * d_rho[q n + j] (device, nsets n doubles) and the largest over j to
+ * d_max[q] (device, nsets doubles); either may be NULL, not both.  Each set's
+ * coefficients are formed on the GPU (the Jacobian of Eq. 14 by dual
+ * numbers), so the values agree with mrtfd_screen's to within rounding, not
+ * bit for bit.  A set with rho <= 0, T <= 0 or a non-finite state or rate,
+ * and a non-finite phase pair, give NaN (and NaN as that set's maximum).
+ * Enqueued on `stream`; the first call on a device uploads the model (M,
+ * M^-1, velocities: 4.3 KB) to a static device array, synchronously; nothing
+ * is allocated.  MRTFD_ERR_ARG for invalid parameters, nsets < 0, n < 0,
+ * nsets n >= 2^31, or NULL arrays with nsets n > 0; MRTFD_ERR_HIP if the
+ * upload or a launch fails; nsets n = 0 writes nothing. */
+int32_t mrtfd_screen_sets(const mrtfd_params *p, int32_t nsets, const double *d_states, const double *d_rates,
+                          const double *d_theta, int32_t n, double *d_rho, double *d_max, void *stream);
+
 /* The library's FP64 model on the host: velocity set v[16][2] (Eq. 4), M
  * [16][16] (Eq. 5, row-major, M[k][i] = m_{k+1}(v_i)) and its inverse, as
  * used to build the kernels' constants.  Host arrays; any may be NULL. */

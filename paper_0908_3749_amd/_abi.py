@@ -94,6 +94,7 @@ _PROTOS = {
     "mrtfd_set_f64": (C.c_int32, [_vp, _vp]),
     "mrtfd_ref_populations": (C.c_int32, [C.POINTER(mrtfd_params), C.POINTER(C.c_double)]),
     "mrtfd_screen": (C.c_int32, [C.POINTER(mrtfd_params), C.POINTER(C.c_double), _vp, C.c_int32, _vp, _vp, _vp]),
+    "mrtfd_screen_sets": (C.c_int32, [C.POINTER(mrtfd_params), C.c_int32, _vp, _vp, _vp, C.c_int32, _vp, _vp, _vp]),
     "mrtfd_time": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "mrtfd_set_step": (C.c_int32, [_vp, C.c_int64]),
     "mrtfd_kernel_info": (C.c_int32, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),

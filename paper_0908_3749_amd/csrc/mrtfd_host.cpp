@@ -425,34 +425,6 @@ void fill_ghosts(const Model &m, const mrtfd_params &p, const double (&fref)[NQ]
 
 // ------------------------------------------------------- stability screen
 
-// f-hat^eq of Eq. (14) as a function of the conserved moments (rho, j_x, j_y,
-// e), with P = e - |j|^2 / (2 rho); generic in the number type, so that its
-// Jacobian can be taken by complex steps.
-template <class Num>
-void feq_of_conserved(Num rho, Num jx, Num jy, Num e, Num (&h)[NQ])
-{
-    const Num r = Num(1.0) / rho;
-    const Num j2 = jx * jx + jy * jy;
-    const Num P = e - Num(0.5) * j2 * r;
-    const Num g = Num(6.0) * rho * e - Num(2.0) * j2;
-    h[0] = rho;
-    h[1] = jx;
-    h[2] = jy;
-    h[3] = e;
-    h[4] = (jx * jx - jy * jy) * r;
-    h[5] = jx * jy * r;
-    h[6] = (e + P) * jx * r;
-    h[7] = (e + P) * jy * r;
-    h[8] = (jx * jx - Num(3.0) * jy * jy) * jx * r * r;
-    h[9] = (Num(3.0) * jx * jx - jy * jy) * jy * r * r;
-    h[10] = Num(2.0) * e * e * r - Num(0.25) * j2 * j2 * r * r * r;
-    h[11] = Num(0.0);
-    h[12] = g * (jx * jx - jy * jy) * r * r * r;
-    h[13] = g * jx * jy * r * r * r;
-    h[14] = Num(0.0);
-    h[15] = Num(0.0);
-}
-
 // d f-hat^eq / d (rho, j_x, j_y, e) by complex steps (Squire and Trapp,
 // 1998): for an analytic h, Im h(x + i eps e_c) / eps = dh/dx_c with no
 // difference of nearby values, so the result is exact up to rounding.
@@ -1021,6 +993,30 @@ int32_t mrtfd_screen(const mrtfd_params *p, const double state[4], const double 
     return launch_screen(S, d_theta, n, d_eig, d_rho, static_cast<hipStream_t>(stream)) == hipSuccess
                ? MRTFD_OK
                : MRTFD_ERR_HIP;
+}
+
+int32_t mrtfd_screen_sets(const mrtfd_params *p, int32_t nsets, const double *d_states, const double *d_rates,
+                          const double *d_theta, int32_t n, double *d_rho, double *d_max, void *stream)
+{
+    if (!p) return MRTFD_ERR_ARG;
+    if (check(p, nullptr, 0) != MRTFD_OK) return MRTFD_ERR_ARG;
+    if (nsets < 0 || n < 0) return MRTFD_ERR_ARG;
+    if ((long long)nsets * n > 0x7fffffffLL) return MRTFD_ERR_ARG;
+    if ((long long)nsets * n == 0) return MRTFD_OK;
+    if (!d_states || !d_rates || !d_theta || (!d_rho && !d_max)) return MRTFD_ERR_ARG;
+    const Model &m = model();
+    if (!m.ok) return MRTFD_ERR_ARG;
+    static double host_model[2 * NQ * NQ + 2 * NQ];
+    static std::once_flag once;
+    std::call_once(once, [&] {
+        std::memcpy(host_model, m.M, sizeof(double) * NQ * NQ);
+        std::memcpy(host_model + NQ * NQ, m.Minv, sizeof(double) * NQ * NQ);
+        std::memcpy(host_model + 2 * NQ * NQ, m.v, sizeof(double) * 2 * NQ);
+    });
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || screen_model_ready(dev, host_model) != hipSuccess) return MRTFD_ERR_HIP;
+    ScreenSetArgs a{d_states, d_rates, d_theta, d_rho, d_max, nsets, n, p->dx, p->dy, p->dt};
+    return launch_screen_sets(a, static_cast<hipStream_t>(stream)) == hipSuccess ? MRTFD_OK : MRTFD_ERR_HIP;
 }
 
 int32_t mrtfd_ref_populations(const mrtfd_params *p, double out[16])

@@ -213,6 +213,50 @@ struct ScreenCoef {
     double C[NQ][NQ];
     double a[NQ], b[NQ];
 };
+// f-hat^eq of Eq. (14) as a function of the conserved moments (rho, j_x, j_y,
+// e), with P = e - |j|^2 / (2 rho); generic in the number type, so that its
+// Jacobian can be taken by complex steps.
+template <class Num>
+__host__ __device__ inline void feq_of_conserved(Num rho, Num jx, Num jy, Num e, Num (&h)[NQ])
+{
+    const Num r = Num(1.0) / rho;
+    const Num j2 = jx * jx + jy * jy;
+    const Num P = e - Num(0.5) * j2 * r;
+    const Num g = Num(6.0) * rho * e - Num(2.0) * j2;
+    h[0] = rho;
+    h[1] = jx;
+    h[2] = jy;
+    h[3] = e;
+    h[4] = (jx * jx - jy * jy) * r;
+    h[5] = jx * jy * r;
+    h[6] = (e + P) * jx * r;
+    h[7] = (e + P) * jy * r;
+    h[8] = (jx * jx - Num(3.0) * jy * jy) * jx * r * r;
+    h[9] = (Num(3.0) * jx * jx - jy * jy) * jy * r * r;
+    h[10] = Num(2.0) * e * e * r - Num(0.25) * j2 * j2 * r * r * r;
+    h[11] = Num(0.0);
+    h[12] = g * (jx * jx - jy * jy) * r * r * r;
+    h[13] = g * jx * jy * r * r * r;
+    h[14] = Num(0.0);
+    h[15] = Num(0.0);
+}
+
+// Many parameter sets at once (mrtfd_screen_sets): set q has the state
+// states[4 q ..] = (rho, u1, u2, T) and the rates rates[16 q ..]; matrix q n
+// + j is set q at phase pair theta[2 j], theta[2 j + 1] (device arrays).
+// Writes max |omega| to rho[q n + j] and the largest over j to max[q] (either
+// may be null; max must hold 0 beforehand), NaN for an invalid set or phase.
+struct ScreenSetArgs {
+    const double *states, *rates, *theta;
+    double *rho, *max;
+    int nsets, n;
+    double dx, dy, dt;
+};
+hipError_t launch_screen_sets(const ScreenSetArgs &a, hipStream_t s);
+// Uploads M, M^-1 and the velocities (2 * 256 + 32 doubles) for the screen
+// of many sets to the current device, once per device.
+hipError_t screen_model_ready(int device, const double *model);
+
 // For each of n phase pairs theta[2 p], theta[2 p + 1] (device array): the
 // 16 eigenvalues of G, largest modulus first, as (re, im) pairs at eig[32 p
 // ..] and their largest modulus at rho[p] (either pointer may be null); NaN

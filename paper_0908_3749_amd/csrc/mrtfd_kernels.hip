@@ -1371,30 +1371,31 @@ __device__ inline void givens(double2 a, double2 b, double &c, double2 &s)
     s = c_scale(c_conj_mul(b, a), rinv);
 }
 
-__global__ __launch_bounds__(64) void k_screen(ScreenCoef S, const double *__restrict__ theta, int n,
-                                               double *__restrict__ eig, double *__restrict__ rho)
+// LDS of one wave's four matrices.
+struct ScreenLds {
+    double2 A[SCREEN_PER_BLOCK][NQ][NQ];
+    double2 v[SCREEN_PER_BLOCK][NQ], w[SCREEN_PER_BLOCK][NQ];
+    double rc[SCREEN_PER_BLOCK][NQ], mod[SCREEN_PER_BLOCK][NQ];
+    double2 rs[SCREEN_PER_BLOCK][NQ], ev[SCREEN_PER_BLOCK][NQ];
+};
+
+// Lax-Wendroff factor of velocity i at the phases (tx, ty), Eq. (A.1b):
+// 1 - i a sin(tx) + a^2 (cos(tx) - 1) - i b sin(ty) + b^2 (cos(ty) - 1).
+__device__ inline double2 lw_factor(double a, double b, double tx, double ty)
 {
-    __shared__ double2 As[SCREEN_PER_BLOCK][NQ][NQ];
-    __shared__ double2 vs[SCREEN_PER_BLOCK][NQ], ws[SCREEN_PER_BLOCK][NQ];
-    __shared__ double rcs[SCREEN_PER_BLOCK][NQ], mods[SCREEN_PER_BLOCK][NQ];
-    __shared__ double2 rss[SCREEN_PER_BLOCK][NQ], evs[SCREEN_PER_BLOCK][NQ];
-    const int g = threadIdx.x / SCREEN_GROUP, t = threadIdx.x % SCREEN_GROUP;
-    const int p = blockIdx.x * SCREEN_PER_BLOCK + g;
-    if (p >= n) return;  // the whole group
-    auto &A = As[g];
-    double2 *v = vs[g], *w = ws[g], *rs = rss[g], *ev = evs[g];
-    double *rc = rcs[g], *mod = mods[g];
-    const double tx = theta[2 * p], ty = theta[2 * p + 1];
-    for (int r = 0; r < NQ; ++r) {  // lane t builds column t
-        double2 e = make_double2(-S.C[r][t], 0.0);
-        if (r == t) {
-            const double a = S.a[r], b = S.b[r];
-            e.x += 1.0 + a * a * (cos(tx) - 1.0) + b * b * (cos(ty) - 1.0);
-            e.y -= a * sin(tx) + b * sin(ty);
-        }
-        A[r][t] = e;
-    }
-    wave_sync();
+    return make_double2(1.0 + a * a * (cos(tx) - 1.0) + b * b * (cos(ty) - 1.0), -(a * sin(tx) + b * sin(ty)));
+}
+
+// The eigenvalues of group g's matrix in L.A[g] (its lane t calling):
+// balancing, Householder reduction, shifted QR, then the ranking by modulus.
+// Lane t returns the eigenvalue e of rank `rank` (largest modulus first, ties
+// by index) and its modulus m; all NaN, ranked by lane, when the iteration
+// does not converge or any eigenvalue is NaN.
+__device__ void screen_eig(ScreenLds &L, int g, int t, double2 &e_out, double &m_out, int &rank_out)
+{
+    auto &A = L.A[g];
+    double2 *v = L.v[g], *w = L.w[g], *rs = L.rs[g], *ev = L.ev[g];
+    double *rc = L.rc[g], *mod = L.mod[g];
 
     // balancing
     for (int sweep = 0; sweep < 40; ++sweep) {
@@ -1548,11 +1549,119 @@ __global__ __launch_bounds__(64) void k_screen(ScreenCoef S, const double *__res
         rank += (mj > m || (mj == m && j < t)) ? 1 : 0;
     }
     if (isnan(m)) rank = t;
+    e_out = e;
+    m_out = m;
+    rank_out = rank;
+}
+
+__global__ __launch_bounds__(64) void k_screen(ScreenCoef S, const double *__restrict__ theta, int n,
+                                               double *__restrict__ eig, double *__restrict__ rho)
+{
+    __shared__ ScreenLds L;
+    const int g = threadIdx.x / SCREEN_GROUP, t = threadIdx.x % SCREEN_GROUP;
+    const int p = blockIdx.x * SCREEN_PER_BLOCK + g;
+    if (p >= n) return;  // the whole group
+    const double tx = theta[2 * p], ty = theta[2 * p + 1];
+    for (int r = 0; r < NQ; ++r) {  // lane t builds column t
+        double2 e = make_double2(-S.C[r][t], 0.0);
+        if (r == t) e = c_add(e, lw_factor(S.a[r], S.b[r], tx, ty));
+        L.A[g][r][t] = e;
+    }
+    wave_sync();
+    double2 e;
+    double m;
+    int rank;
+    screen_eig(L, g, t, e, m, rank);
     if (eig) {
         eig[(long long)p * 2 * NQ + 2 * rank] = e.x;
         eig[(long long)p * 2 * NQ + 2 * rank + 1] = e.y;
     }
     if (rho && rank == 0) rho[p] = m;
+}
+
+// Forward-mode dual number: value and derivative along one direction.
+struct Dual {
+    double v, d;
+    __device__ Dual(double x = 0.0) : v(x), d(0.0) {}
+    __device__ Dual(double x, double dx) : v(x), d(dx) {}
+};
+__device__ inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.v * b.d + a.d * b.v); }
+__device__ inline Dual operator/(Dual a, Dual b)
+{
+    const double q = a.v / b.v;
+    return Dual(q, (a.d - q * b.d) / b.v);
+}
+
+// The model for the screen of many sets: M (Eq. 5, M[k][i] = m_k(v_i)), its
+// inverse and the velocities v[i][2], in FP64; filled once per device.
+__device__ double screen_model[2 * NQ * NQ + 2 * NQ];
+
+// Many parameter sets: matrix idx = q n + j is set q at phase pair j.  Each
+// group builds its own C = dt M^-1 S (M - J M_c) from its set's state and
+// rates (J, the Jacobian of Eq. 14 through rho, j, e, by dual numbers: lane c
+// < 4 takes the derivative along conserved moment c), then G = diag(lw) - C.
+__global__ __launch_bounds__(64) void k_screen_sets(ScreenSetArgs a)
+{
+    __shared__ ScreenLds L;
+    __shared__ double Js[SCREEN_PER_BLOCK][NQ][4];
+    const int g = threadIdx.x / SCREEN_GROUP, t = threadIdx.x % SCREEN_GROUP;
+    const long long idx = (long long)blockIdx.x * SCREEN_PER_BLOCK + g;
+    if (idx >= (long long)a.nsets * a.n) return;  // the whole group
+    const int q = (int)(idx / a.n), j = (int)(idx % a.n);
+    const double *M = screen_model, *Minv = screen_model + NQ * NQ, *vel = screen_model + 2 * NQ * NQ;
+    const double rho = a.states[4 * q], ux = a.states[4 * q + 1], uy = a.states[4 * q + 2],
+                 T = a.states[4 * q + 3];
+    bool ok = rho > 0.0 && T > 0.0 && isfinite(rho + ux + uy + T);
+    for (int k = 0; k < NQ; ++k) ok = ok && isfinite(a.rates[(long long)NQ * q + k]);
+    const double tx = a.theta[2 * j], ty = a.theta[2 * j + 1];
+    ok = ok && isfinite(tx) && isfinite(ty);
+    if (!ok) {  // uniform over the group
+        if (a.rho && t == 0) a.rho[idx] = NAN;
+        if (a.max && t == 0) atomicMax((unsigned long long *)&a.max[q], (unsigned long long)__double_as_longlong(NAN));
+        return;
+    }
+    if (t < 4) {  // column t of J = d f-hat^eq / d (rho, j_x, j_y, e)
+        const Dual c0(rho, t == 0 ? 1.0 : 0.0), c1(rho * ux, t == 1 ? 1.0 : 0.0),
+            c2(rho * uy, t == 2 ? 1.0 : 0.0), c3(rho * (T + 0.5 * (ux * ux + uy * uy)), t == 3 ? 1.0 : 0.0);
+        Dual h[NQ];
+        feq_of_conserved(c0, c1, c2, c3, h);
+        for (int k = 0; k < NQ; ++k) Js[g][k][t] = h[k].d;
+    }
+    wave_sync();
+    double D[NQ];  // column t of M - J M_c
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        double acc = M[k * NQ + t];
+        for (int c = 0; c < 4; ++c) acc -= Js[g][k][c] * M[c * NQ + t];
+        D[k] = acc * a.rates[(long long)NQ * q + k];
+    }
+    const double ax = vel[2 * t] * a.dt / a.dx, by = vel[2 * t + 1] * a.dt / a.dy;
+    const double2 lw = lw_factor(ax, by, tx, ty);
+    for (int r = 0; r < NQ; ++r) {  // lane t builds column t
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) acc += Minv[r * NQ + k] * D[k];
+        double2 e = make_double2(-a.dt * acc, 0.0);
+        if (r == t) e = c_add(e, lw);
+        L.A[g][r][t] = e;
+    }
+    wave_sync();
+    double2 e;
+    double m;
+    int rank;
+    screen_eig(L, g, t, e, m, rank);
+    if (rank == 0) {
+        if (a.rho) a.rho[idx] = m;
+        if (a.max) atomicMax((unsigned long long *)&a.max[q], (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+__global__ void k_fill_f64(double *p, long long n, double value)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
 }
 
 inline unsigned blocks_for(long long n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -1798,6 +1907,33 @@ template hipError_t launch_unpack<float, float>(const Field &, const float *, fl
 template hipError_t launch_unpack<float, double>(const Field &, const float *, double *, hipStream_t);
 template hipError_t launch_unpack<double, float>(const Field &, const double *, float *, hipStream_t);
 template hipError_t launch_unpack<double, double>(const Field &, const double *, double *, hipStream_t);
+
+hipError_t launch_screen_sets(const ScreenSetArgs &a, hipStream_t s)
+{
+    const long long total = (long long)a.nsets * a.n;
+    if (total <= 0) return hipSuccess;
+    if (a.max) hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(a.nsets, 256)), dim3(256), 0, s, a.max, (long long)a.nsets, 0.0);
+    hipLaunchKernelGGL(k_screen_sets, dim3(blocks_for(total, SCREEN_PER_BLOCK)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+namespace {
+std::mutex g_screen_model_mu;
+std::map<int, bool> g_screen_model;
+}  // namespace
+
+hipError_t screen_model_ready(int device, const double *model)
+{
+    std::lock_guard<std::mutex> lk(g_screen_model_mu);
+    if (g_screen_model.count(device)) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    e = hipMemcpyToSymbol(HIP_SYMBOL(screen_model), model, sizeof(double) * (2 * NQ * NQ + 2 * NQ));
+    if (e == hipSuccess) g_screen_model[device] = true;
+    return e;
+}
 
 hipError_t launch_screen(const ScreenCoef &S, const double *theta, int n, double *eig, double *rho,
                          hipStream_t s)

@@ -63,6 +63,37 @@ def spectral_radius(state, s, dx, dy, dt, theta, device=None):
     return _screen(state, s, dx, dy, dt, theta, device, False)
 
 
+def screen_sets(states, rates, dx, dy, dt, theta, per_phase=False, device=None):
+    """max |omega| over the phase pairs theta (an (n, 2) array) for each of
+    many parameter sets: states (nsets, 4) = (rho, u1, u2, T), rates (nsets,
+    16); numpy arrays or torch tensors.  Returns the (nsets,) maxima as a
+    numpy array, and with per_phase=True also the (nsets, n) values."""
+    import torch
+
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+
+    def on_dev(x, cols):
+        t = x if isinstance(x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))
+        return t.to(device=dev, dtype=torch.float64).reshape(-1, cols).contiguous()
+
+    d_st, d_s, d_th = on_dev(states, 4), on_dev(rates, 16), on_dev(theta, 2)
+    nsets, n = d_st.shape[0], d_th.shape[0]
+    if d_s.shape[0] != nsets:
+        raise ValueError(f"{nsets} states but {d_s.shape[0]} rate sets")
+    d_max = torch.empty(nsets, dtype=torch.float64, device=dev)
+    d_rho = torch.empty((nsets, n), dtype=torch.float64, device=dev) if per_phase else None
+    p = make_params(3, 3, dx, dy, dt, [0.0] * 16, {k: dict(_PERIODIC) for k in ("west", "east", "south", "north")})
+    stream = torch.cuda.current_stream(dev)
+    check(lib().mrtfd_screen_sets(C.byref(p), nsets, C.c_void_p(d_st.data_ptr()), C.c_void_p(d_s.data_ptr()),
+                                  C.c_void_p(d_th.data_ptr()), n,
+                                  C.c_void_p(d_rho.data_ptr() if per_phase else 0), C.c_void_p(d_max.data_ptr()),
+                                  C.c_void_p(stream.cuda_stream)))
+    stream.synchronize()
+    if per_phase:
+        return d_max.cpu().numpy(), d_rho.cpu().numpy()
+    return d_max.cpu().numpy()
+
+
 def phase_grid(n):
     """(n + 1) x (2 n + 1) phase pairs over [0, pi] x [-pi, pi] (the other
     half follows by the symmetry of real data), as an (m, 2) array."""

@@ -185,3 +185,19 @@ def test_screen_rejects_bad_arguments_without_gpu(abi):
     for bad in ((0.0, 0.0, 0.0, 1.0), (1.0, 0.0, 0.0, -1.0), (1.0, math.nan, 0.0, 1.0), (1.0, 0.0, math.inf, 1.0)):
         st = (C.c_double * 4)(*bad)
         assert L.mrtfd_screen(C.byref(p), st, dummy, 4, dummy, dummy, None) == abi.MRTFD_ERR_ARG, bad
+
+
+def test_screen_sets_rejects_bad_arguments_without_gpu(abi):
+    """mrtfd_screen_sets validates before any HIP call: nsets < 0, n < 0,
+    nsets n of 2^31 or more, NULL inputs, both outputs NULL; nsets n = 0
+    does nothing."""
+    p = _params(synth.sod())
+    L = abi.lib()
+    d = C.c_void_p(8)  # never dereferenced: every case returns before a launch
+    assert L.mrtfd_screen_sets(C.byref(p), 0, d, d, d, 5, d, d, None) == 0
+    assert L.mrtfd_screen_sets(C.byref(p), 3, d, d, d, 0, d, d, None) == 0
+    for args in ((-1, d, d, d, 4, d, d), (3, d, d, d, -1, d, d), (1 << 16, d, d, d, 1 << 15, d, d),
+                 (3, None, d, d, 4, d, d), (3, d, None, d, 4, d, d), (3, d, d, None, 4, d, d),
+                 (3, d, d, d, 4, None, None)):
+        assert L.mrtfd_screen_sets(C.byref(p), *args, None) == abi.MRTFD_ERR_ARG, args
+    assert L.mrtfd_screen_sets(None, 3, d, d, d, 4, d, d, None) == abi.MRTFD_ERR_ARG

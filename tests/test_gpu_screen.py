@@ -279,6 +279,121 @@ def test_tube_batch_states_along_the_tube(screen):
     assert 1.0005 < w_across < w_2d
 
 
+def test_many_sets_match_numpy_and_their_maxima(screen):
+    """mrtfd_screen_sets on the paper's parameter sets and 6 seeded random
+    ones at one spacing and time step (each set's coefficients formed on the
+    GPU, the Jacobian of Eq. 14 by dual numbers): every set's max |omega| at
+    every phase pair within the bound of numpy's, as for the screen of one
+    set; the per-set maxima equal to the largest per-phase values bit for
+    bit; 14 sets x 13 phase pairs = 182 matrices (not a multiple of four)."""
+    dx, dt = 2e-3, 1e-5
+    cap = 1.0 / dt
+    sets = [(st, [min(v, cap) for v in s]) for st, s, _, _ in CASES.values()]
+    rng = np.random.default_rng(9)
+    for _ in range(6):
+        st = (float(rng.uniform(0.2, 5)), float(rng.uniform(-4, 4)), float(rng.uniform(-4, 4)),
+              float(np.exp(rng.uniform(np.log(0.1), np.log(100.0)))))
+        sets.append((st, [0.0] * 4 + [float(v) for v in np.exp(rng.uniform(np.log(100.0), np.log(cap), 12))]))
+    states = np.array([st for st, _ in sets])
+    rates = np.array([s for _, s in sets])
+    th = np.vstack([np.zeros((1, 2)), rng.uniform(-math.pi, math.pi, (12, 2))])
+    mx, per = screen.screen_sets(states, rates, dx, dx, dt, th, per_phase=True)
+    assert per.shape == (len(sets), len(th))
+    np.testing.assert_array_equal(mx, per.max(axis=1))
+    mats = ref.model()
+    worst = 0.0
+    for q, (st, s) in enumerate(sets):
+        K = construction_scale(st, s, dt, mats)
+        single = screen.spectral_radius(st, s, dx, dx, dt, th)
+        for j, (a, b) in enumerate(th):
+            G = ref.amplification(st, s, dx, dx, dt, a, b, mats)
+            _, wmax, tmax = compare(np.zeros(16), G, K)
+            assert abs(per[q, j] - wmax) <= tmax, (q, j, per[q, j], wmax, tmax)
+            assert abs(per[q, j] - single[j]) <= 2 * tmax, (q, j, per[q, j], single[j])
+            worst = max(worst, abs(per[q, j] - wmax) / tmax)
+    print(f"many sets: worst max |omega| difference {worst:.3f} of its bound")
+
+
+def test_many_sets_invalid_sets_and_phases_give_nan(screen):
+    """A set with rho <= 0, T <= 0 or a non-finite value, and a non-finite
+    phase pair, give NaN for their matrices (and NaN as the set's maximum);
+    the valid matrices keep the values they have without them."""
+    dx, dt = 2e-3, 1e-5
+    good_s = synth.rates(dt, s5=6500, s7=9e4)
+    states = np.array([(2.0, 10.0, 0.0, 2.0), (0.0, 1.0, 0.0, 1.0), (1.0, 0.0, 0.0, -1.0),
+                       (1.0, math.nan, 0.0, 1.0), (1.0, 0.5, 0.2, 1.5)])
+    rates = np.array([good_s] * 5)
+    rates[4, 9] = math.inf
+    th = np.array([[0.4, 0.1], [1.0, -0.5], [math.nan, 0.0]])
+    mx, per = screen.screen_sets(states, rates, dx, dx, dt, th, per_phase=True)
+    assert np.all(np.isnan(mx))                    # every set has the NaN phase pair
+    assert np.all(np.isnan(per[1:]))               # invalid sets
+    assert np.all(np.isnan(per[0, 2])) and np.all(np.isfinite(per[0, :2]))
+    mx0, per0 = screen.screen_sets(states[:1], rates[:1], dx, dx, dt, th[:2], per_phase=True)
+    np.testing.assert_array_equal(per0[0], per[0, :2])
+    assert mx0[0] == per0[0].max()
+
+
+def test_fig2_every_placement_of_the_printed_rates(screen):
+    """Sect. IV, Fig. 2 (state (2, 10, 0, 2), dx = 2e-3, dt = 1e-5, along k
+    dx): every placement of the seven printed MRT rate values (6500, 9e4,
+    9e4, 8e4, 7e4, 8e3, 2.5e4) on distinct moments 5..16, the others at
+    1e5 -- 1 995 840 sets, 46 phases each, in one pass of mrtfd_screen_sets.
+    The printed placement is unstable (1.0034), but about 2 % of the
+    placements make MRT stable (max |omega| <= 1 + 1e-7, within the FP64
+    bound of the screen at this state): never one with a rate of 2.5e4 or
+    less on moments 5, 7, 11 or 13, which a mode along x with u2 = 0
+    couples to; the low rates sit on moments such as 6, 8, 10, 14 and 16,
+    odd in y, which such a mode leaves alone.  The best and some unstable
+    placements are checked against numpy."""
+    import itertools
+
+    vals = [6500.0, 9e4, 9e4, 8e4, 7e4, 8e3, 2.5e4]
+    orders = np.array(sorted(set(itertools.permutations(vals))))
+    slots = np.array(list(itertools.combinations(range(12), 7)))
+    state, _, dx, dt = CASES["fig2_mrt"]
+    th = np.stack([np.linspace(0.0, math.pi, 46), np.zeros(46)], axis=1)
+    allmax = np.empty((len(slots), len(orders)))
+    rates = np.empty((len(slots), len(orders), 12))
+    for c0 in range(0, len(slots), 132):
+        cs = slots[c0:c0 + 132]
+        R = np.full((len(cs), len(orders), 12), 1e5)
+        R[np.arange(len(cs))[:, None, None], np.arange(len(orders))[None, :, None], cs[:, None, :]] = orders[None]
+        rates[c0:c0 + len(cs)] = R
+        full = np.concatenate([np.zeros((R.shape[0] * R.shape[1], 4)), R.reshape(-1, 12)], axis=1)
+        st = np.broadcast_to(np.array(state), (full.shape[0], 4))
+        allmax[c0:c0 + len(cs)] = screen.screen_sets(st, full, dx, dx, dt, th).reshape(len(cs), len(orders))
+    assert np.all(np.isfinite(allmax))
+    printed = {5: 6500.0, 7: 9e4, 8: 9e4, 9: 8e4, 13: 7e4, 14: 8e3, 15: 2.5e4}
+    pr = [1e5] * 12
+    for k, v in printed.items():
+        pr[k - 5] = v
+    hit = np.all(rates == np.array(pr), axis=2)
+    assert hit.sum() == 1 and allmax[hit][0] > 1.003
+    stable = allmax <= 1.0 + 1e-7
+    n_stable = int(stable.sum())
+    print(f"placements {allmax.size}: stable {n_stable} ({n_stable / allmax.size:.2%}), least max |omega| "
+          f"{allmax.min():.12f}, printed {allmax[hit][0]:.9f}")
+    assert 0.01 * allmax.size < n_stable < 0.05 * allmax.size
+    low = rates <= 2.5e4
+    for k in (5, 7, 11, 13):
+        assert not np.any(low[..., k - 5] & stable), k
+    # the GPU's verdicts against numpy: the five best placements and five unstable ones
+    mats = ref.model()
+    K0 = None
+    flat = allmax.ravel()
+    pick = list(np.argsort(flat)[:5]) + list(np.random.default_rng(3).choice(np.flatnonzero(~stable.ravel()), 5))
+    for idx in pick:
+        s = [0.0] * 4 + list(rates.reshape(-1, 12)[idx])
+        K0 = construction_scale(state, s, dt, mats)
+        for a in th[::5, 0]:
+            G = ref.amplification(state, s, dx, dx, dt, a, 0.0, mats)
+            _, wmax, tmax = compare(np.zeros(16), G, K0)
+            w = screen.spectral_radius(state, s, dx, dx, dt, [[a, 0.0]])[0]
+            assert abs(w - wmax) <= tmax, (idx, a, w, wmax, tmax)
+        assert (flat[idx] <= 1.0 + 1e-7) == (idx in pick[:5])
+
+
 def test_screen_throughput(screen):
     """A 65 x 129 phase grid (8385 matrices) at the Fig. 2 state, timed
     after a warm-up call; numpy's time for 200 of the same matrices beside
