@@ -394,6 +394,44 @@ def test_fig2_every_placement_of_the_printed_rates(screen):
         assert (flat[idx] <= 1.0 + 1e-7) == (idx in pick[:5])
 
 
+def test_high_mach_west_state_grows_under_every_rate_set(screen):
+    """Sect. V.A(e): the west state (5, 45, 0, 10) at dx = 0.003, dt = 1e-5
+    has a growing mode along k dx under every placement of the printed rates
+    (1.5e4 twice and 5e4 on distinct moments 5..16, the others 1e5: 660
+    sets) and under 200 000 random rate sets log-uniform in [1e2, 1e5]
+    (max |omega| > 1.01 per step in every case), so no choice of the rates
+    makes the tube stable at this spacing and time step; the least unstable
+    random set is checked against numpy."""
+    import itertools
+
+    state, dx, dt = (5.0, 45.0, 0.0, 10.0), 0.003, 1e-5
+    th = np.stack([np.linspace(0.0, math.pi, 46), np.zeros(46)], axis=1)
+    R = []
+    for pair in itertools.combinations(range(12), 2):
+        for k in range(12):
+            if k not in pair:
+                r = [1e5] * 12
+                r[pair[0]] = r[pair[1]] = 1.5e4
+                r[k] = 5e4
+                R.append([0.0] * 4 + r)
+    R = np.array(R)
+    placed = screen.screen_sets(np.tile(state, (len(R), 1)), R, dx, dx, dt, th)
+    rng = np.random.default_rng(21)
+    Rr = np.concatenate([np.zeros((200000, 4)), np.exp(rng.uniform(np.log(1e2), np.log(1e5), (200000, 12)))], axis=1)
+    rand = screen.screen_sets(np.tile(state, (len(Rr), 1)), Rr, dx, dx, dt, th)
+    print(f"high-Mach west state: least max |omega| over the placements {placed.min():.6f}, "
+          f"over the random sets {rand.min():.6f}")
+    assert placed.min() > 1.01 and rand.min() > 1.01
+    s = list(Rr[int(np.argmin(rand))])
+    mats = ref.model()
+    K = construction_scale(state, s, dt, mats)
+    _, per = screen.screen_sets(np.array([state]), np.array([s]), dx, dx, dt, th, per_phase=True)
+    for a, wa in zip(th[:, 0], per[0]):
+        _, wmax, tmax = compare(np.zeros(16), ref.amplification(state, s, dx, dx, dt, a, 0.0, mats), K)
+        assert abs(wa - wmax) <= tmax, (a, wa, wmax, tmax)
+    assert per[0].max() == rand.min()
+
+
 def test_screen_throughput(screen):
     """A 65 x 129 phase grid (8385 matrices) at the Fig. 2 state, timed
     after a warm-up call; numpy's time for 200 of the same matrices beside
