@@ -342,10 +342,11 @@ def test_fig2_every_placement_of_the_printed_rates(screen):
     The printed placement is unstable (1.0034), but about 2 % of the
     placements make MRT stable (max |omega| <= 1 + 1e-7, within the FP64
     bound of the screen at this state): never one with a rate of 2.5e4 or
-    less on moments 5, 7, 11 or 13, which a mode along x with u2 = 0
-    couples to; the low rates sit on moments such as 6, 8, 10, 14 and 16,
-    odd in y, which such a mode leaves alone.  The best and some unstable
-    placements are checked against numpy."""
+    less on moments 5, 7, 11 or 13 (even in y, with non-zero equilibria);
+    the low rates sit on moments odd in y (6, 8, 10, 14, 16), which a mode
+    along x with u2 = 0 leaves alone, or on 12 and 15, whose equilibria are
+    zero.  The best and some unstable placements are checked against
+    numpy."""
     import itertools
 
     vals = [6500.0, 9e4, 9e4, 8e4, 7e4, 8e3, 2.5e4]
