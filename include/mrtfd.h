@@ -306,7 +306,8 @@ int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_
 
 /* Von Neumann screen of Sect. IV.  For the uniform state (rho, u1, u2, T) =
  * state[0..3] (host array; rho > 0, T > 0) and the spacing, time step and
- * rates of p (its boundary fields are validated but not used), the
+ * rates of p (dx, dy, dt > 0 and rates >= 0, finite; dt s_k may exceed 1,
+ * which mrtfd_create refuses; the grid and boundary fields are not used), the
  * amplification matrix of one Fourier mode of the scheme (Eq. A.1a-b with
  * the collision of Eq. 3 linearised about the state, the equilibria of Eq.
  * 14 differentiated through rho, j and e) is
@@ -327,9 +328,10 @@ int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_
  * accurate to about kappa u ||G||: near 1e-12 at moderate states, but ~1e-4
  * at hot or fast ones, where ||G|| and kappa both reach ~1e6.  A phase whose iteration does not converge in 480 QR steps
  * gets NaN.  Enqueued on `stream` (a hipStream_t, NULL = default); nothing
- * is allocated.  MRTFD_ERR_ARG for invalid parameters, a state with rho <=
- * 0, T <= 0 or non-finite values, n < 0, d_theta NULL or both outputs NULL
- * with n > 0; MRTFD_ERR_HIP if the launch fails. */
+ * is allocated.  MRTFD_ERR_ARG for p NULL, dx, dy or dt not positive and
+ * finite, a negative or non-finite rate, a state with rho <= 0, T <= 0 or
+ * non-finite values, n < 0, d_theta NULL or both outputs NULL with n > 0;
+ * MRTFD_ERR_HIP if the launch fails. */
 int32_t mrtfd_screen(const mrtfd_params *p, const double state[4], const double *d_theta, int32_t n,
                      double *d_eig, double *d_rho, void *stream);
 
@@ -337,7 +339,8 @@ int32_t mrtfd_screen(const mrtfd_params *p, const double state[4], const double 
  * searches over states and rates.  Set q (0 <= q < nsets) has the uniform
  * state d_states[4 q .. 4 q + 3] = (rho, u1, u2, T) and the 16 rates
  * d_rates[16 q .. 16 q + 15] (device arrays); the spacing and time step
- * come from p (its rates and boundary fields are validated but not used).
+ * come from p (dx, dy, dt > 0, finite; its rates, grid and boundary fields
+ * are not used).
  * For the n phase pairs d_theta (device, 2 n doubles) shared by all sets,
  * writes max |omega| of G (as mrtfd_screen) for set q at pair j to
  * d_rho[q n + j] (device, nsets n doubles) and the largest over j to
@@ -348,8 +351,9 @@ int32_t mrtfd_screen(const mrtfd_params *p, const double state[4], const double 
  * and a non-finite phase pair, give NaN (and NaN as that set's maximum).
  * Enqueued on `stream`; the first call on a device uploads the model (M,
  * M^-1, velocities: 4.3 KB) to a static device array, synchronously; nothing
- * is allocated.  MRTFD_ERR_ARG for invalid parameters, nsets < 0, n < 0,
- * nsets n >= 2^31, or NULL arrays with nsets n > 0; MRTFD_ERR_HIP if the
+ * is allocated.  MRTFD_ERR_ARG for p NULL, dx, dy or dt not positive and
+ * finite, nsets < 0, n < 0, nsets n >= 2^31, or NULL arrays with nsets n >
+ * 0; MRTFD_ERR_HIP if the
  * upload or a launch fails; nsets n = 0 writes nothing. */
 int32_t mrtfd_screen_sets(const mrtfd_params *p, int32_t nsets, const double *d_states, const double *d_rates,
                           const double *d_theta, int32_t n, double *d_rho, double *d_max, void *stream);

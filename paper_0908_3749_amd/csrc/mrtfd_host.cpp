@@ -943,6 +943,20 @@ int autotune(mrtfd_ctx *c, long long avail, long long *taken)
     return rc;
 }
 
+// The screen's own check of p: positive finite dx, dy, dt and finite,
+// non-negative rates; dt s_k above 1 is allowed (finding out what happens
+// there is what the screen is for), the grid and boundary fields are not used.
+bool screen_params_ok(const mrtfd_params *p, bool rates)
+{
+    if (!p) return false;
+    for (double x : {p->dx, p->dy, p->dt})
+        if (!(x > 0.0) || !std::isfinite(x)) return false;
+    if (rates)
+        for (int k = 0; k < NQ; ++k)
+            if (!(p->s[k] >= 0.0) || !std::isfinite(p->s[k])) return false;
+    return true;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------- C ABI
@@ -979,7 +993,7 @@ int32_t mrtfd_screen(const mrtfd_params *p, const double state[4], const double 
                      double *d_eig, double *d_rho, void *stream)
 {
     if (!p || !state) return MRTFD_ERR_ARG;
-    if (check(p, nullptr, 0) != MRTFD_OK) return MRTFD_ERR_ARG;
+    if (!screen_params_ok(p, true)) return MRTFD_ERR_ARG;
     for (int c = 0; c < 4; ++c)
         if (!std::isfinite(state[c])) return MRTFD_ERR_ARG;
     if (!(state[0] > 0) || !(state[3] > 0)) return MRTFD_ERR_ARG;
@@ -998,8 +1012,7 @@ int32_t mrtfd_screen(const mrtfd_params *p, const double state[4], const double 
 int32_t mrtfd_screen_sets(const mrtfd_params *p, int32_t nsets, const double *d_states, const double *d_rates,
                           const double *d_theta, int32_t n, double *d_rho, double *d_max, void *stream)
 {
-    if (!p) return MRTFD_ERR_ARG;
-    if (check(p, nullptr, 0) != MRTFD_OK) return MRTFD_ERR_ARG;
+    if (!screen_params_ok(p, false)) return MRTFD_ERR_ARG;
     if (nsets < 0 || n < 0) return MRTFD_ERR_ARG;
     if ((long long)nsets * n > 0x7fffffffLL) return MRTFD_ERR_ARG;
     if ((long long)nsets * n == 0) return MRTFD_OK;

@@ -94,6 +94,35 @@ def screen_sets(states, rates, dx, dy, dt, theta, per_phase=False, device=None):
     return d_max.cpu().numpy()
 
 
+def largest_stable_dt(states, rates, dx, dy, dt_lo, dt_hi, n=16, tol=1e-9, rel=1e-3, device=None):
+    """Bisection for the largest time step in [dt_lo, dt_hi] at which every
+    state (rows of `states`, (rho, u1, u2, T)) with the 16 `rates` has max
+    |omega| <= 1 + tol over phase_grid(n), to a relative width `rel`.
+    Assumes that the stable time steps in the interval are those below some
+    dt*; raises ValueError when dt_lo is unstable.  Returns (dt, dt_next):
+    the largest stable time step found and the smallest unstable one (None
+    when dt_hi is stable)."""
+    st = np.atleast_2d(np.asarray(states, dtype=np.float64))
+    R = np.tile(np.asarray(rates, dtype=np.float64).reshape(1, 16), (st.shape[0], 1))
+    th = phase_grid(n)
+
+    def stable(dt):
+        return bool(np.max(screen_sets(st, R, dx, dy, dt, th, device=device)) <= 1.0 + tol)
+
+    if not stable(dt_lo):
+        raise ValueError(f"unstable already at dt = {dt_lo}")
+    if stable(dt_hi):
+        return dt_hi, None
+    lo, hi = dt_lo, dt_hi
+    while hi - lo > rel * lo:
+        mid = 0.5 * (lo + hi)
+        if stable(mid):
+            lo = mid
+        else:
+            hi = mid
+    return lo, hi
+
+
 def phase_grid(n):
     """(n + 1) x (2 n + 1) phase pairs over [0, pi] x [-pi, pi] (the other
     half follows by the symmetry of real data), as an (m, 2) array."""

@@ -185,6 +185,19 @@ def test_screen_rejects_bad_arguments_without_gpu(abi):
     for bad in ((0.0, 0.0, 0.0, 1.0), (1.0, 0.0, 0.0, -1.0), (1.0, math.nan, 0.0, 1.0), (1.0, 0.0, math.inf, 1.0)):
         st = (C.c_double * 4)(*bad)
         assert L.mrtfd_screen(C.byref(p), st, dummy, 4, dummy, dummy, None) == abi.MRTFD_ERR_ARG, bad
+    # dt s_k beyond 1 (refused by mrtfd_create) is what the screen is for; a bad spacing or rate is not
+    from paper_0908_3749_amd import make_params
+    fast = make_params(3, 3, 0.01, 0.01, 1e-5, [0.0] * 4 + [1e5] * 12, synth.sod().sides)
+    fast.dt = 5e-5
+    assert L.mrtfd_screen(C.byref(fast), good, dummy, 0, dummy, dummy, None) == 0
+    for field, value in (("dt", 0.0), ("dx", -1.0), ("dy", math.inf)):
+        q = make_params(3, 3, 0.01, 0.01, 1e-5, [0.0] * 16, synth.sod().sides)
+        setattr(q, field, value)
+        assert L.mrtfd_screen(C.byref(q), good, dummy, 4, dummy, dummy, None) == abi.MRTFD_ERR_ARG, field
+        assert L.mrtfd_screen_sets(C.byref(q), 1, dummy, dummy, dummy, 4, dummy, dummy, None) == abi.MRTFD_ERR_ARG
+    q = make_params(3, 3, 0.01, 0.01, 1e-5, [0.0] * 16, synth.sod().sides)
+    q.s[7] = -1.0
+    assert L.mrtfd_screen(C.byref(q), good, dummy, 4, dummy, dummy, None) == abi.MRTFD_ERR_ARG
 
 
 def test_screen_sets_rejects_bad_arguments_without_gpu(abi):

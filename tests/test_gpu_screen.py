@@ -433,6 +433,31 @@ def test_high_mach_west_state_grows_under_every_rate_set(screen):
     assert per[0].max() == rand.min()
 
 
+def test_largest_stable_dt_for_sod_with_the_papers_rates(screen):
+    """The Sod tube (Sect. V.A(a): dx = 1/400, s5 = s6 = 500, s7 = s8 =
+    1000, s11 = 2500) with the other rates at the paper's 1e5, not capped at
+    1/dt: the time step as printed (2e-5, dt s = 2) is unstable, and the
+    bisection on the GPU screen puts the largest stable time step just below
+    it, where 1 - dt s_k, the uniform modes' factors, approach -1 (stable up
+    to dt s ~ 1.95 in both end states).  numpy agrees on either side."""
+    s = synth.rates(None, s5=500, s6=500, s7=1000, s8=1000, s11=2500)
+    dx = 1.0 / 400
+    states = [(1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.8)]
+    dt, dt_next = screen.largest_stable_dt(states, s, dx, dx, 1e-6, 2e-5, n=8, rel=1e-3)
+    print(f"Sod with rates 1e5: largest stable dt {dt:.6e} (unstable at {dt_next:.6e}, dt s = {dt_next * 1e5:.4f})")
+    assert 1.9e-5 < dt < dt_next < 2e-5
+    mats = ref.model()
+    th = screen.phase_grid(8)
+    for t_, want_stable in ((dt, True), (dt_next, False)):
+        worst = 0.0
+        for st in states:
+            K = construction_scale(st, s, t_, mats)
+            for a, b in th:
+                _, wmax, tmax = compare(np.zeros(16), ref.amplification(st, s, dx, dx, t_, a, b, mats), K)
+                worst = max(worst, wmax - tmax if want_stable else wmax + tmax)
+        assert (worst <= 1.0 + 1e-9) if want_stable else (worst > 1.0 + 1e-9), (t_, worst)
+
+
 def test_screen_throughput(screen):
     """A 65 x 129 phase grid (8385 matrices) at the Fig. 2 state, timed
     after a warm-up call; numpy's time for 200 of the same matrices beside
