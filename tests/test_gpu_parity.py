@@ -661,6 +661,42 @@ def test_full_size_bf16x3_couette_matches_oracle(gpu):
     assert err <= bound
 
 
+def test_full_size_fp64_couette_matches_oracle(gpu):
+    """The FP64 form bench.py times beside the headline (Couette 8192 x 2048,
+    stored relative to (1, 1) in FP64, graph of 64 steps, the step kernel
+    autotuned on the run's first steps: one row per wave x store kind x
+    tile order, plus the simple kernel): after the autotune's two passes it
+    agrees with the whole-grid FP64 oracle node by node within n 16 u64 S
+    (the FP64 one-step bound, test_gpu_fp64), S = transform_scale."""
+    from paper_0908_3749_amd import make_params, ref_populations
+    prob = synth.couette()
+    ref = (1.0, 1.0)
+    cells = prob.nx * prob.ny
+    reps = 2 * int(max(4.0, min(16.0, 3.4e7 / cells)))
+    ncand = 5 if ((prob.nx + 63) // 64) % 8 == 0 else 3
+    n = 2 * ncand * (reps + 2) + 4
+    o = core.Grid(prob, nthreads=THREADS)
+    o.init_problem()
+    fr = ref_populations(make_params(prob.nx, prob.ny, prob.dx, prob.dy, prob.dt, prob.s, prob.sides, ref=ref))
+    g0 = o.get_f() - fr[:, None, None]
+    o.set_f(g0 + fr[:, None, None])
+    scale = transform_scale(prob, o.get_f())
+    o.run(n)
+    want = o.get_f()
+    del o
+    g = gpu.from_problem(prob, graph_steps=64, precision="fp64", ref=ref)
+    g.set_f64(g0)
+    del g0
+    g.step(n)
+    got = g.get_f64_numpy()
+    variant = g.kernel_variant()
+    g.close()
+    err = max(float(np.max(np.abs(got[q] + fr[q] - want[q]))) for q in range(16))
+    bound = n * 16 * 2.0 ** -53 * scale
+    print(f"full size couette fp64, {n} steps, variant {variant}: max err {err:.3e}, bound {bound:.3e}")
+    assert err <= bound
+
+
 def test_largest_grid_for_32bit_offsets(gpu):
     """Maximum size: 8192 x 8063 is the largest grid of that width whose copy
     of f (rows of 16 x 8320 floats and the padding ring) stays below 4 GiB,
