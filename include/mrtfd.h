@@ -308,52 +308,53 @@ int32_t mrtfd_kernel_info(mrtfd_ctx *ctx, int32_t *kernel, int32_t *rows, int32_
  * state[0..3] (host array; rho > 0, T > 0) and the spacing, time step and
  * rates of p (dx, dy, dt > 0 and rates >= 0, finite; dt s_k may exceed 1,
  * which mrtfd_create refuses; the grid and boundary fields are not used), the
- * amplification matrix of one Fourier mode of the scheme (Eq. A.1a-b with
- * the collision of Eq. 3 linearised about the state, the equilibria of Eq.
- * 14 differentiated through rho, j and e) is
+ * amplification matrix of one Fourier mode of the scheme (Eq. A.1a-b with the
+ * collision of Eq. 3 linearised about the state, the equilibria of Eq. 14
+ * differentiated through rho, j and e) is
  *   G_ij(theta) = delta_ij (1 - i a_i sin theta_x + a_i^2 (cos theta_x - 1)
  *                 - i b_i sin theta_y + b_i^2 (cos theta_y - 1))
  *                 - dt [M^-1 S (M - d f-hat^eq / d f)]_ij,
- * a_i = v_i1 dt / dx, b_i = v_i2 dt / dy, theta = (k_x dx, k_y dy); the
- * scheme is stable at the state when every eigenvalue omega of G has |omega|
- * <= 1 over all phases.  For n phase pairs d_theta[2 p], d_theta[2 p + 1]
- * (device array of 2 n doubles) computes the 16 eigenvalues of G in FP64
- * (balancing, Householder reduction to Hessenberg form and the shifted QR
- * algorithm, four phase pairs per wave) and writes them, largest modulus
- * first, as (re, im) pairs to d_eig[32 p .. 32 p + 31], and the largest
- * modulus to d_rho[p] (device arrays of 32 n and n doubles; either may be
- * NULL, not both).  They are the exact eigenvalues of some G + E with ||E||
- * a small multiple of u ||G|| (u = 2^-53), so an eigenvalue with condition
- * number kappa (1 / |y^H x| for unit left and right eigenvectors y, x) is
- * accurate to about kappa u ||G||: near 1e-12 at moderate states, but ~1e-4
- * at hot or fast ones, where ||G|| and kappa both reach ~1e6.  A phase whose iteration does not converge in 480 QR steps
- * gets NaN.  Enqueued on `stream` (a hipStream_t, NULL = default); nothing
- * is allocated.  MRTFD_ERR_ARG for p NULL, dx, dy or dt not positive and
- * finite, a negative or non-finite rate, a state with rho <= 0, T <= 0 or
- * non-finite values, n < 0, d_theta NULL or both outputs NULL with n > 0;
- * MRTFD_ERR_HIP if the launch fails. */
+ * a_i = v_i1 dt / dx, b_i = v_i2 dt / dy, theta = (k_x dx, k_y dy); the scheme
+ * is stable at the state when every eigenvalue omega of G has |omega| <= 1
+ * over all phases.  For n phase pairs d_theta[2 p], d_theta[2 p + 1] (device
+ * array of 2 n doubles) computes the 16 eigenvalues of G in FP64 (balancing,
+ * Householder reduction to Hessenberg form and the shifted QR algorithm, four
+ * phase pairs per wave) and writes them, largest modulus first, as (re, im)
+ * pairs to d_eig[32 p .. 32 p + 31], and the largest modulus to d_rho[p]
+ * (device arrays of 32 n and n doubles; either may be NULL, not both).  They
+ * are the exact eigenvalues of some G + E with ||E|| a small multiple of u
+ * ||G|| (u = 2^-53), so an eigenvalue with condition number kappa (1 / |y^H x|
+ * for unit left and right eigenvectors y, x) is accurate to about kappa u
+ * ||G||: near 1e-12 at moderate states, but ~1e-4 at hot or fast ones, where
+ * ||G|| and kappa both reach ~1e6.  A phase whose iteration does not converge
+ * in 480 QR steps gets NaN.  Enqueued on `stream` (a hipStream_t, NULL =
+ * default); nothing is allocated.  MRTFD_ERR_ARG for p NULL, dx, dy or dt not
+ * positive and finite, a negative or non-finite rate, a state with rho <= 0, T
+ * <= 0 or non-finite values, n < 0, d_theta NULL or both outputs NULL with n >
+ * 0; MRTFD_ERR_HIP if the launch fails. */
 int32_t mrtfd_screen(const mrtfd_params *p, const double state[4], const double *d_theta, int32_t n,
                      double *d_eig, double *d_rho, void *stream);
 
 /* The von Neumann screen of Sect. IV over many parameter sets at once, for
  * searches over states and rates.  Set q (0 <= q < nsets) has the uniform
  * state d_states[4 q .. 4 q + 3] = (rho, u1, u2, T) and the 16 rates
- * d_rates[16 q .. 16 q + 15] (device arrays); the spacing and time step
- * come from p (dx, dy, dt > 0, finite; its rates, grid and boundary fields
- * are not used).
- * For the n phase pairs d_theta (device, 2 n doubles) shared by all sets,
- * writes max |omega| of G (as mrtfd_screen) for set q at pair j to
- * d_rho[q n + j] (device, nsets n doubles) and the largest over j to
- * d_max[q] (device, nsets doubles); either may be NULL, not both.  Each set's
- * coefficients are formed on the GPU (the Jacobian of Eq. 14 by dual
- * numbers), so the values agree with mrtfd_screen's to within rounding, not
- * bit for bit.  A set with rho <= 0, T <= 0 or a non-finite state or rate,
- * and a non-finite phase pair, give NaN (and NaN as that set's maximum).
- * Enqueued on `stream`; the first call on a device uploads the model (M,
- * M^-1, velocities: 4.3 KB) to a static device array, synchronously; nothing
- * is allocated.  MRTFD_ERR_ARG for p NULL, dx, dy or dt not positive and
- * finite, nsets < 0, n < 0, nsets n >= 2^31, or NULL arrays with nsets n >
- * 0; MRTFD_ERR_HIP if the
+ * d_rates[16 q .. 16 q + 15] (device arrays); the spacing and time step come
+ * from p (dx, dy, dt > 0, finite; its rates, grid and boundary fields are not
+ * used).  For the n phase pairs d_theta (device, 2 n doubles) shared by all
+ * sets, writes max |omega| of G (as mrtfd_screen) for set q at pair j to
+ * d_rho[q n + j] (device, nsets n doubles) and the largest over j to d_max[q]
+ * (device, nsets doubles); either may be NULL, not both.  Each set's
+ * coefficients are formed on the GPU (the Jacobian of Eq. 14 by dual numbers),
+ * so the values differ from mrtfd_screen's by the rounding of the
+ * coefficients, amplified as there by the eigenvalues' condition numbers
+ * (far below 1e-9 at moderate states, 4e-6 at the high-Mach tube's west
+ * state).  A
+ * set with rho <= 0, T <= 0 or a non-finite state or rate, and a non-finite
+ * phase pair, give NaN (and NaN as that set's maximum).  Enqueued on `stream`;
+ * the first call on a device uploads the model (M, M^-1, velocities: 4.3 KB)
+ * to a static device array, synchronously; nothing is allocated.
+ * MRTFD_ERR_ARG for p NULL, dx, dy or dt not positive and finite, nsets < 0, n
+ * < 0, nsets n >= 2^31, or NULL arrays with nsets n > 0; MRTFD_ERR_HIP if the
  * upload or a launch fails; nsets n = 0 writes nothing. */
 int32_t mrtfd_screen_sets(const mrtfd_params *p, int32_t nsets, const double *d_states, const double *d_rates,
                           const double *d_theta, int32_t n, double *d_rho, double *d_max, void *stream);
