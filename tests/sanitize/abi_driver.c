@@ -5,6 +5,7 @@
  * UndefinedBehaviorSanitizer.  Prints "ok" when every result is as the
  * header states. */
 #include <math.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -130,6 +131,27 @@ int main(void)
     EXPECT(mrtfd_batch_create(NULL, n, NULL, NULL, NULL, NULL, 0, NULL, &b) == MRTFD_ERR_ARG);
     EXPECT(mrtfd_batch_destroy(NULL) == MRTFD_ERR_ARG);
     EXPECT(mrtfd_batch_last_error(NULL) != NULL);
+
+    /* the von Neumann screen: validation before any HIP call */
+    p = valid();
+    const double st[4] = {1.0, 0.0, 0.0, 1.0}, bad[4] = {1.0, 0.0, 0.0, -1.0};
+    double *d = (double *)(uintptr_t)8; /* never dereferenced: every case returns before a launch */
+    EXPECT(mrtfd_screen(&p, st, d, 0, d, d, NULL) == MRTFD_OK);
+    EXPECT(mrtfd_screen(&p, st, d, -1, d, d, NULL) == MRTFD_ERR_ARG);
+    EXPECT(mrtfd_screen(&p, st, NULL, 4, d, d, NULL) == MRTFD_ERR_ARG);
+    EXPECT(mrtfd_screen(&p, st, d, 4, NULL, NULL, NULL) == MRTFD_ERR_ARG);
+    EXPECT(mrtfd_screen(&p, bad, d, 4, d, d, NULL) == MRTFD_ERR_ARG);
+    EXPECT(mrtfd_screen(NULL, st, d, 4, d, d, NULL) == MRTFD_ERR_ARG);
+    p.dt = 1e-3;  /* dt s beyond 1: refused by create, accepted by the screen */
+    EXPECT(mrtfd_screen(&p, st, d, 0, d, d, NULL) == MRTFD_OK);
+    p.dy = 0.0;
+    EXPECT(mrtfd_screen(&p, st, d, 4, d, d, NULL) == MRTFD_ERR_ARG);
+    p = valid();
+    EXPECT(mrtfd_screen_sets(&p, 0, d, d, d, 4, d, d, NULL) == MRTFD_OK);
+    EXPECT(mrtfd_screen_sets(&p, -1, d, d, d, 4, d, d, NULL) == MRTFD_ERR_ARG);
+    EXPECT(mrtfd_screen_sets(&p, 1 << 16, d, d, d, 1 << 15, d, d, NULL) == MRTFD_ERR_ARG);
+    EXPECT(mrtfd_screen_sets(&p, 3, NULL, d, d, 4, d, d, NULL) == MRTFD_ERR_ARG);
+    EXPECT(mrtfd_screen_sets(&p, 3, d, d, d, 4, NULL, NULL, NULL) == MRTFD_ERR_ARG);
 
     if (fails) return 1;
     printf("ok\n");
