@@ -1,6 +1,9 @@
 """Von Neumann screen of Sect. IV on the GPU: the eigenvalues of the
 amplification matrix of one Fourier mode around a uniform state, per phase
-pair (mrtfd_screen in include/mrtfd.h).  Argument marshalling only."""
+pair (mrtfd_screen in include/mrtfd.h), and max |omega| for many parameter
+sets at once (mrtfd_screen_sets).  Argument marshalling, plus a bisection
+over the time step that calls the screen (largest_stable_dt); the screen's
+arithmetic runs in the library's kernels."""
 import ctypes as C
 import math
 
